@@ -1,0 +1,538 @@
+/*
+ * FP64 CPU oracle for the GRACE-DG collision operator (Yang, Chen & Bai,
+ * "GRACE-DG: A Discontinuous Galerkin Method-Based Code for General Nonlinear
+ * Coagulation-Fragmentation Equations").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark use it.  It shares no code, header, table or constant with
+ * the HIP library.
+ *
+ * It evaluates the paper's discrete operator directly: the nested
+ * Gauss-Legendre sums of the truncated coagulation and fragmentation fluxes
+ * (Sec. 3.3, Eqs. Fcoagtrun and Ffragtrun, with the inner fragment-mass
+ * integrals of App. B, Eqs. inte1/inte2), assembled into the DG right-hand
+ * side (Sec. 3.1, Eq. evo), the scaling limiter (Sec. 3.2, Eqs. recon/gamma)
+ * and the SSP-RK3 step (Eq. RK3).  No tensor is precomputed; every call walks
+ * the quadrature nodes again.  Plain loops, FP64, OpenMP across hydro cells only.
+ *
+ * The Gauss-Legendre rule (nodes/weights on [-1,1]) is passed in by the
+ * caller, which takes it from a library routine.
+ *
+ * Readings of points the paper leaves open (each one is listed with its reason
+ * in the design notes):
+ *  - grid: e_j = x_min exp(j ln(x_max/x_min)/N), bin centre = arithmetic
+ *    midpoint (Sec. 3.1 says "logarithmic grid" and defines the centre as
+ *    the midpoint);
+ *  - the u-integral for a flux at an interior node x_j^theta includes the
+ *    partial bin [e_j, x_j^theta] with its own Q-point rule (Sec. 3.3 only says
+ *    "x_{j+1/2} simply replaced by x_j^theta");
+ *  - every integration range is split at every bin edge inside it and pieces
+ *    of zero length are skipped (Sec. 3.3, the A..B partial-bin sums);
+ *  - the sharp collision outcome: a node pair (u,v) fragments iff
+ *    dv(u,v) = v0 (u^-1/6 + v^-1/6) > v_frag, else it coagulates;
+ *  - per-cell v_frag between tabulated levels: the raw flux vector is the
+ *    linear blend of the two neighbouring level evaluations (clamped at the
+ *    ends);
+ *  - the limiter with a non-positive cell average flattens the bin (gamma=0);
+ *    a negative average is counted as a positivity violation.  The limiter is
+ *    applied to the initial state and after every RK stage.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- enums mirrored by value in oracle.py (not shared with the library) ---- */
+enum { OK_CONST = 0, OK_ADDITIVE = 1, OK_MULTIPLICATIVE = 2, OK_BALLISTIC = 3 };
+enum { OF_NONE = 0, OF_POWERLAW = 1, OF_UNIFORM_BINARY = 2, OF_REMNANT_ONLY = 3 };
+
+typedef struct {
+    int N, k, Q;            /* mass bins, Legendre degree, GL points per piece */
+    const double *s, *w;    /* GL nodes / weights on [-1,1], length Q           */
+    double xmin, xmax;
+    int conservative;       /* 1: dx = -u + x_min ; 0: dx = 0                    */
+    int kern;               /* OK_*                                              */
+    double v0;              /* relative-velocity scale of the threshold          */
+    int frag;               /* OF_*                                              */
+    double alpha;           /* power-law index of the fragment distribution      */
+} ocfg;
+
+/* per-evaluation parameters that vary by cell */
+typedef struct {
+    double vfrag;           /* sharp fragmentation threshold                     */
+    double kscale;          /* multiplies both kernels                           */
+} ocell;
+
+/* ---------------------------------------------------------------- grid (Sec 3.1) */
+static void make_edges(const ocfg* c, double* e)
+{
+    double lr = log(c->xmax / c->xmin);
+    for (int j = 0; j <= c->N; ++j) e[j] = c->xmin * exp(lr * (double)j / (double)c->N);
+    e[0] = c->xmin;
+    e[c->N] = c->xmax;
+}
+
+/* ---------------------------------------------------- Legendre basis (Eq. 2.4) */
+static double legendre(int n, double x)
+{
+    if (n == 0) return 1.0;
+    double p0 = 1.0, p1 = x;
+    for (int m = 1; m < n; ++m) {
+        double p2 = ((2.0 * m + 1.0) * x * p1 - m * p0) / (m + 1.0);
+        p0 = p1; p1 = p2;
+    }
+    return p1;
+}
+
+/* P_n'(x) from P'_{m+1} = P'_{m-1} + (2m+1) P_m */
+static double legendre_d(int n, double x)
+{
+    if (n == 0) return 0.0;
+    double dm1 = 0.0, d = 1.0;     /* P'_0, P'_1 */
+    for (int m = 1; m < n; ++m) {
+        double dn = dm1 + (2.0 * m + 1.0) * legendre(m, x);
+        dm1 = d; d = dn;
+    }
+    return d;
+}
+
+/* value of the DG polynomial of bin j at mass x (Eq. 2.3) */
+static double g_at(const ocfg* c, const double* e, const double* g, int j, double x)
+{
+    double h = e[j + 1] - e[j], mid = 0.5 * (e[j] + e[j + 1]);
+    double xi = 2.0 * (x - mid) / h;
+    double acc = 0.0;
+    for (int i = 0; i <= c->k; ++i) acc += g[j * (c->k + 1) + i] * legendre(i, xi);
+    return acc;
+}
+
+/* ------------------------------------------------------------- kernels */
+static double kernel_K(const ocfg* c, double u, double v)
+{
+    switch (c->kern) {
+    case OK_CONST: return 1.0;
+    case OK_ADDITIVE: return u + v;
+    case OK_MULTIPLICATIVE: return u * v;
+    default: {
+        double a = cbrt(u) + cbrt(v);
+        return a * a * c->v0 * (pow(u, -1.0 / 6.0) + pow(v, -1.0 / 6.0));
+    }
+    }
+}
+
+static double rel_velocity(const ocfg* c, double u, double v)
+{
+    return c->v0 * (pow(u, -1.0 / 6.0) + pow(v, -1.0 / 6.0));
+}
+
+/* split into coagulating and fragmenting parts at one node pair */
+static void kernel_split(const ocfg* c, const ocell* p, double u, double v, double* kc, double* kf)
+{
+    double K = p->kscale * kernel_K(c, u, v);
+    if (c->frag == OF_NONE) { *kc = K; *kf = 0.0; return; }
+    if (rel_velocity(c, u, v) > p->vfrag) { *kc = 0.0; *kf = K; }
+    else { *kc = K; *kf = 0.0; }
+}
+
+/* ------------------------------------------- inner w-integrals (App. B, inte1/2)
+ * Pw = int_x^{u+v} w b(w,u,v) dw ,  Nw = int_{x_min}^x w b(w,u,v) dw              */
+static double Pw(const ocfg* c, double x, double u, double v)
+{
+    double S = u + v;
+    switch (c->frag) {
+    case OF_POWERLAW: {
+        /* destructive: m_frag = u+v, no remnant; A/(2+alpha) = S/D */
+        if (x >= S) return 0.0;
+        double be = 2.0 + c->alpha;
+        double D = pow(S, be) - pow(c->xmin, be);
+        return S * (pow(S, be) - pow(x, be)) / D;
+    }
+    case OF_UNIFORM_BINARY: {
+        double r = 0.0;
+        if (x < u) r += (u * u - x * x) / u;
+        if (x < v) r += (v * v - x * x) / v;
+        return r;
+    }
+    case OF_REMNANT_ONLY:
+        return (x < S) ? S : 0.0;
+    default:
+        return 0.0;
+    }
+}
+
+static double Nw(const ocfg* c, double x, double u, double v)
+{
+    double S = u + v;
+    switch (c->frag) {
+    case OF_POWERLAW: {
+        double be = 2.0 + c->alpha;
+        double D = pow(S, be) - pow(c->xmin, be);
+        double top = (x < S) ? x : S;
+        return S * (pow(top, be) - pow(c->xmin, be)) / D;
+    }
+    case OF_UNIFORM_BINARY: {
+        double mu = (x < u) ? x : u, mv = (x < v) ? x : v;
+        return (mu * mu - c->xmin * c->xmin) / u + (mv * mv - c->xmin * c->xmin) / v;
+    }
+    case OF_REMNANT_ONLY:
+        return (c->xmin < S && S < x) ? S : 0.0;
+    default:
+        return 0.0;
+    }
+}
+
+/* ---------------------------------------- composite GL rule G[a,b] (Sec. 3.3)
+ * Split [a,b] at every bin edge inside it, skip pieces of length <= 0, map the Q
+ * nodes to every piece.  Returns the node count; bin[] says which polynomial
+ * evaluates g at the node.                                                        */
+static int composite(const ocfg* c, const double* e, double a, double b,
+                     double* x, double* wt, int* bin)
+{
+    int n = 0;
+    if (!(b > a)) return 0;
+    for (int j = 0; j < c->N; ++j) {
+        double lo = (a > e[j]) ? a : e[j];
+        double hi = (b < e[j + 1]) ? b : e[j + 1];
+        if (!(hi > lo)) continue;
+        double mid = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+        for (int q = 0; q < c->Q; ++q) {
+            x[n] = mid + half * c->s[q];
+            wt[n] = half * c->w[q];
+            bin[n] = j;
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* ---------------------------------------------- flux at one mass point (O6)
+ * F(x) = sum_{u in G[xmin,x]} wu g(u) sum_{v in G[x-u+xmin, Vmax(u)]} wv g(v)
+ *            [Kc/v + Kf Pw/(v(u+v))]
+ *      - sum_{u in G[x,xmax]} wu g(u) sum_{v in G[xmin, Vmax(u)]} wv g(v) Kf Nw/(v(u+v))
+ * with Vmax(u) = xmax - u + xmin (conservative) or xmax.                          */
+static double flux_at(const ocfg* c, const ocell* p, const double* e, const double* g, double x,
+                      double* ux, double* uw, int* ub, double* vx, double* vw, int* vb)
+{
+    double F = 0.0;
+    /* positive part: u < x */
+    int nu = composite(c, e, c->xmin, x, ux, uw, ub);
+    for (int a = 0; a < nu; ++a) {
+        double u = ux[a];
+        double gu = g_at(c, e, g, ub[a], u);
+        double vmax = c->conservative ? (c->xmax - u + c->xmin) : c->xmax;
+        int nv = composite(c, e, x - u + c->xmin, vmax, vx, vw, vb);
+        double inner = 0.0;
+        for (int b = 0; b < nv; ++b) {
+            double v = vx[b];
+            double kc, kf;
+            kernel_split(c, p, u, v, &kc, &kf);
+            double integrand = kc / v;
+            if (kf != 0.0) integrand += kf * Pw(c, x, u, v) / (v * (u + v));
+            inner += vw[b] * g_at(c, e, g, vb[b], v) * integrand;
+        }
+        F += uw[a] * gu * inner;
+    }
+    if (c->frag == OF_NONE) return F;
+    /* negative part: u > x */
+    nu = composite(c, e, x, c->xmax, ux, uw, ub);
+    for (int a = 0; a < nu; ++a) {
+        double u = ux[a];
+        double gu = g_at(c, e, g, ub[a], u);
+        double vmax = c->conservative ? (c->xmax - u + c->xmin) : c->xmax;
+        int nv = composite(c, e, c->xmin, vmax, vx, vw, vb);
+        double inner = 0.0;
+        for (int b = 0; b < nv; ++b) {
+            double v = vx[b];
+            double kc, kf;
+            kernel_split(c, p, u, v, &kc, &kf);
+            if (kf == 0.0) continue;
+            inner += vw[b] * g_at(c, e, g, vb[b], v) * kf * Nw(c, x, u, v) / (v * (u + v));
+        }
+        F -= uw[a] * gu * inner;
+    }
+    return F;
+}
+
+/* -------------------------------------------- raw flux vector of one cell (O7)
+ * Y = [F(e_1) .. F(e_{N-1}), (F(e_N) if non-conservative),
+ *      V_{0,1..k}, V_{1,1..k}, ..., V_{N-1,1..k}]
+ * with V_{j,i} = sum_theta w_theta P_i'(s_theta) F(c_j + h_j s_theta/2) (Sec. 3.3).
+ * Fe gets all N+1 edge fluxes (F(e_0) and, if conservative, F(e_N) evaluate to 0). */
+static int n_out(const ocfg* c) { return (c->N - 1) + (c->conservative ? 0 : 1) + c->N * c->k; }
+
+static void raw_flux(const ocfg* c, const ocell* p, const double* e, const double* g, double* Y, double* Fe)
+{
+    int maxn = (c->N + 2) * c->Q;
+    double* ux = malloc(sizeof(double) * maxn);
+    double* uw = malloc(sizeof(double) * maxn);
+    double* vx = malloc(sizeof(double) * maxn);
+    double* vw = malloc(sizeof(double) * maxn);
+    int* ub = malloc(sizeof(int) * maxn);
+    int* vb = malloc(sizeof(int) * maxn);
+
+    for (int j = 0; j <= c->N; ++j) Fe[j] = flux_at(c, p, e, g, e[j], ux, uw, ub, vx, vw, vb);
+    int o = 0;
+    for (int j = 1; j < c->N; ++j) Y[o++] = Fe[j];
+    if (!c->conservative) Y[o++] = Fe[c->N];
+    for (int j = 0; j < c->N; ++j) {
+        double h = e[j + 1] - e[j], mid = 0.5 * (e[j] + e[j + 1]);
+        double Fn[64];
+        for (int t = 0; t < c->Q; ++t)
+            Fn[t] = flux_at(c, p, e, g, mid + 0.5 * h * c->s[t], ux, uw, ub, vx, vw, vb);
+        for (int i = 1; i <= c->k; ++i) {
+            double V = 0.0;
+            for (int t = 0; t < c->Q; ++t) V += c->w[t] * legendre_d(i, c->s[t]) * Fn[t];
+            Y[o++] = V;
+        }
+    }
+    free(ux); free(uw); free(vx); free(vw); free(ub); free(vb);
+}
+
+/* DG right-hand side from the raw vector (Eq. evo with Eq. 2.5):
+ * L_{j,i} = (2i+1)/h_j (V_{j,i} - F_{j+1} P_i(1) + F_j P_i(-1)),  V_{j,0} = 0.     */
+static void assemble_L(const ocfg* c, const double* e, const double* Y, double* L)
+{
+    int N = c->N, k = c->k;
+    double* F = malloc(sizeof(double) * (N + 1));
+    F[0] = 0.0;
+    for (int j = 1; j < N; ++j) F[j] = Y[j - 1];
+    F[N] = c->conservative ? 0.0 : Y[N - 1];
+    int vbase = (N - 1) + (c->conservative ? 0 : 1);
+    for (int j = 0; j < N; ++j) {
+        double h = e[j + 1] - e[j];
+        for (int i = 0; i <= k; ++i) {
+            double V = (i == 0) ? 0.0 : Y[vbase + j * k + (i - 1)];
+            double sgn = (i % 2 == 0) ? 1.0 : -1.0;   /* P_i(-1) */
+            L[j * (k + 1) + i] = (2.0 * i + 1.0) / h * (V - F[j + 1] + sgn * F[j]);
+        }
+    }
+    free(F);
+}
+
+/* raw vector with the per-cell threshold read through the level table */
+static void raw_flux_cell(const ocfg* c, const double* e, const double* g, double kscale,
+                          double vfrag, int nlev, const double* lev, double* Y, double* Fe)
+{
+    ocell p = { vfrag, kscale };
+    if (nlev < 2 || c->frag == OF_NONE) { raw_flux(c, &p, e, g, Y, Fe); return; }
+    int r = 0;
+    while (r < nlev - 2 && vfrag >= lev[r + 1]) ++r;
+    double th = (vfrag - lev[r]) / (lev[r + 1] - lev[r]);
+    if (th < 0.0) th = 0.0;
+    if (th > 1.0) th = 1.0;
+    int no = n_out(c);
+    double* Y1 = malloc(sizeof(double) * no);
+    double* F1 = malloc(sizeof(double) * (c->N + 1));
+    p.vfrag = lev[r];
+    raw_flux(c, &p, e, g, Y, Fe);
+    p.vfrag = lev[r + 1];
+    raw_flux(c, &p, e, g, Y1, F1);
+    for (int o = 0; o < no; ++o) Y[o] = (1.0 - th) * Y[o] + th * Y1[o];
+    for (int j = 0; j <= c->N; ++j) Fe[j] = (1.0 - th) * Fe[j] + th * F1[j];
+    free(Y1); free(F1);
+}
+
+/* ------------------------------------------------------- limiter (Eqs. recon, gamma)
+ * Minimum of sum_i g^i P_i on [-1,1]: the end points and the real roots of the
+ * derivative inside (-1,1).  For k <= 3 the derivative is at most quadratic:
+ *   p'(xi) = g1 + 3 g2 xi + g3 (15 xi^2 - 3)/2.                                    */
+static double bin_min(int k, const double* gi)
+{
+    double m = 0.0, cand[4];
+    int nc = 0;
+    cand[nc++] = -1.0;
+    cand[nc++] = 1.0;
+    double g1 = k >= 1 ? gi[1] : 0.0, g2 = k >= 2 ? gi[2] : 0.0, g3 = k >= 3 ? gi[3] : 0.0;
+    double A = 7.5 * g3, B = 3.0 * g2, Cc = g1 - 1.5 * g3;
+    if (A != 0.0) {
+        double disc = B * B - 4.0 * A * Cc;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double qq = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+            if (qq != 0.0) { cand[nc++] = qq / A; cand[nc++] = Cc / qq; }
+            else { cand[nc++] = 0.0; }
+        }
+    } else if (B != 0.0) {
+        cand[nc++] = -Cc / B;
+    }
+    int first = 1;
+    for (int t = 0; t < nc; ++t) {
+        double x = cand[t];
+        if (x < -1.0 || x > 1.0) continue;
+        double val = 0.0;
+        for (int i = 0; i <= k; ++i) val += gi[i] * legendre(i, x);
+        if (first || val < m) { m = val; first = 0; }
+    }
+    return m;
+}
+
+static long limit_cell(int N, int k, double* g)
+{
+    long viol = 0;
+    for (int j = 0; j < N; ++j) {
+        double* gi = g + j * (k + 1);
+        double avg = gi[0];
+        double gamma;
+        if (avg <= 0.0) {
+            /* an empty bin is flattened; a negative average cannot be repaired
+             * by scaling and is counted as a positivity violation            */
+            gamma = 0.0;
+            if (avg < 0.0) ++viol;
+        } else {
+            double m = bin_min(k, gi);
+            gamma = (m < 0.0) ? avg / (avg - m) : 1.0;
+            if (gamma > 1.0) gamma = 1.0;
+        }
+        for (int i = 1; i <= k; ++i) gi[i] *= gamma;
+    }
+    return viol;
+}
+
+/* ================================================================ public entry points */
+static int check(const ocfg* c)
+{
+    if (c->N < 1 || c->k < 0 || c->k > 16 || c->Q < 1 || c->Q > 64) return -1;
+    if (!(c->xmin > 0.0) || !(c->xmax > c->xmin)) return -1;
+    return 0;
+}
+
+int oracle_n_out(const ocfg* c) { return n_out(c); }
+
+/* inner fragment-mass integrals at one (x,u,v), for unit tests */
+int oracle_inner(const ocfg* c, double x, double u, double v, double* pw, double* nw)
+{
+    *pw = Pw(c, x, u, v);
+    *nw = Nw(c, x, u, v);
+    return 0;
+}
+
+int oracle_edges(const ocfg* c, double* e)
+{
+    if (check(c)) return -1;
+    make_edges(c, e);
+    return 0;
+}
+
+/* flux at arbitrary mass points for one cell (used by the continuous-flux pins) */
+int oracle_flux_points(const ocfg* c, const double* g, double kscale, double vfrag,
+                       int npts, const double* xs, double* F)
+{
+    if (check(c)) return -1;
+    double* e = malloc(sizeof(double) * (c->N + 1));
+    make_edges(c, e);
+    int maxn = (c->N + 2) * c->Q;
+    double* ux = malloc(sizeof(double) * maxn);
+    double* uw = malloc(sizeof(double) * maxn);
+    double* vx = malloc(sizeof(double) * maxn);
+    double* vw = malloc(sizeof(double) * maxn);
+    int* ub = malloc(sizeof(int) * maxn);
+    int* vb = malloc(sizeof(int) * maxn);
+    ocell p = { vfrag, kscale };
+    for (int t = 0; t < npts; ++t) F[t] = flux_at(c, &p, e, g, xs[t], ux, uw, ub, vx, vw, vb);
+    free(ux); free(uw); free(vx); free(vw); free(ub); free(vb); free(e);
+    return 0;
+}
+
+/* raw flux vector Y [C][n_out] and right-hand side L [C][N(k+1)] for a batch */
+int oracle_rhs(const ocfg* c, int C, const double* g, const double* kscale, const double* vfrag,
+               double vfrag_default, int nlev, const double* lev, double* Y, double* L, double* Fe)
+{
+    if (check(c) || C < 0) return -1;
+    int P = c->N * (c->k + 1), no = n_out(c);
+    double* e = malloc(sizeof(double) * (c->N + 1));
+    make_edges(c, e);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int cell = 0; cell < C; ++cell) {
+        double* fe = malloc(sizeof(double) * (c->N + 1));
+        double ks = kscale ? kscale[cell] : 1.0;
+        double vf = vfrag ? vfrag[cell] : vfrag_default;
+        raw_flux_cell(c, e, g + (size_t)cell * P, ks, vf, nlev, lev, Y + (size_t)cell * no, fe);
+        if (L) assemble_L(c, e, Y + (size_t)cell * no, L + (size_t)cell * P);
+        if (Fe) memcpy(Fe + (size_t)cell * (c->N + 1), fe, sizeof(double) * (c->N + 1));
+        free(fe);
+    }
+    free(e);
+    return 0;
+}
+
+/* limiter in place over a batch; returns the violation count */
+long oracle_limit(const ocfg* c, int C, double* g)
+{
+    if (check(c) || c->k > 3) return -1;
+    int P = c->N * (c->k + 1);
+    long viol = 0;
+    for (int cell = 0; cell < C; ++cell) viol += limit_cell(c->N, c->k, g + (size_t)cell * P);
+    return viol;
+}
+
+/* n_steps of SSP-RK3 (Eq. RK3) with the limiter on the initial state and after
+ * every stage.  g is [C][N(k+1)] in place. */
+long oracle_rk(const ocfg* c, int C, double* g, const double* kscale, const double* vfrag,
+               double vfrag_default, int nlev, const double* lev, double dt, int n_steps)
+{
+    if (check(c) || c->k > 3 || C < 0 || n_steps < 0) return -1;
+    int P = c->N * (c->k + 1), no = n_out(c);
+    double* e = malloc(sizeof(double) * (c->N + 1));
+    make_edges(c, e);
+    long viol = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : viol)
+    for (int cell = 0; cell < C; ++cell) {
+        double* gn = g + (size_t)cell * P;
+        double* y1 = malloc(sizeof(double) * P);
+        double* y2 = malloc(sizeof(double) * P);
+        double* L = malloc(sizeof(double) * P);
+        double* Y = malloc(sizeof(double) * no);
+        double* fe = malloc(sizeof(double) * (c->N + 1));
+        double ks = kscale ? kscale[cell] : 1.0;
+        double vf = vfrag ? vfrag[cell] : vfrag_default;
+        viol += limit_cell(c->N, c->k, gn);
+        for (int n = 0; n < n_steps; ++n) {
+            raw_flux_cell(c, e, gn, ks, vf, nlev, lev, Y, fe);
+            assemble_L(c, e, Y, L);
+            for (int t = 0; t < P; ++t) y1[t] = gn[t] + dt * L[t];
+            viol += limit_cell(c->N, c->k, y1);
+
+            raw_flux_cell(c, e, y1, ks, vf, nlev, lev, Y, fe);
+            assemble_L(c, e, Y, L);
+            for (int t = 0; t < P; ++t) y2[t] = 0.75 * gn[t] + 0.25 * (y1[t] + dt * L[t]);
+            viol += limit_cell(c->N, c->k, y2);
+
+            raw_flux_cell(c, e, y2, ks, vf, nlev, lev, Y, fe);
+            assemble_L(c, e, Y, L);
+            for (int t = 0; t < P; ++t) gn[t] = gn[t] / 3.0 + 2.0 / 3.0 * (y2[t] + dt * L[t]);
+            viol += limit_cell(c->N, c->k, gn);
+        }
+        free(y1); free(y2); free(L); free(Y); free(fe);
+    }
+    free(e);
+    return viol;
+}
+
+/* Largest dt allowed by the CFL bound (Eq. dt) for the given states.  Only bins
+ * that lose mass (F_{j+1} > F_j) can be driven negative by a forward-Euler stage,
+ * so the bound is min over such bins of h_j g_j^0 / (F_{j+1} - F_j).              */
+double oracle_cfl_dt(const ocfg* c, int C, const double* g, const double* kscale,
+                     const double* vfrag, double vfrag_default, int nlev, const double* lev)
+{
+    if (check(c)) return -1.0;
+    int P = c->N * (c->k + 1), no = n_out(c);
+    double* e = malloc(sizeof(double) * (c->N + 1));
+    make_edges(c, e);
+    double best = INFINITY;
+    for (int cell = 0; cell < C; ++cell) {
+        double* Y = malloc(sizeof(double) * no);
+        double* fe = malloc(sizeof(double) * (c->N + 1));
+        raw_flux_cell(c, e, g + (size_t)cell * P, kscale ? kscale[cell] : 1.0,
+                      vfrag ? vfrag[cell] : vfrag_default, nlev, lev, Y, fe);
+        for (int j = 0; j < c->N; ++j) {
+            double d = fe[j + 1] - fe[j];
+            if (d > 0.0) {
+                double t = (e[j + 1] - e[j]) * g[(size_t)cell * P + j * (c->k + 1)] / d;
+                if (t < best) best = t;
+            }
+        }
+        free(Y); free(fe);
+    }
+    free(e);
+    return best;
+}

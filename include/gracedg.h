@@ -1,0 +1,177 @@
+/*
+ * gracedg.h -- C ABI of the MI355X (gfx950) collision-operator library.
+ *
+ * The operator is the DG right-hand side of the coagulation-fragmentation
+ * equation of Yang, Chen & Bai, "GRACE-DG: A Discontinuous Galerkin
+ * Method-Based Code for General Nonlinear Coagulation-Fragmentation
+ * Equations": the truncated coagulation flux and the paper's conservative
+ * fragmentation flux (Sec. 2, Eqs. Fcoag and Ffrag; Sec. 3.3, Eqs. Fcoagtrun
+ * and Ffragtrun; App. B, Eqs. inte1/inte2), assembled into the per-bin
+ * Legendre right-hand side L[g] (Sec. 3.1, Eq. evo), the scaling limiter
+ * (Sec. 3.2, Eqs. recon/gamma) and the SSP-RK3 step (Eq. RK3).
+ *
+ * Conventions shared by every call
+ *  - Every call returns an int status: GD_OK (0) or a negative GD_E* code;
+ *    gd_last_error() returns a thread-local message for the last failure.
+ *  - Device pointers are plain HIP device addresses owned by the caller; the
+ *    library never frees caller memory.  Host pointers are read during the
+ *    call only.
+ *  - State layout: hydro cells are contiguous, each cell holds P = bins*(order+1)
+ *    doubles, coefficient index p = j*(order+1) + i for bin j and Legendre
+ *    degree i (Eq. 2.3).  Cells of a plan are ordered group by group.
+ *  - Calls on a plan are asynchronous on the plan's HIP stream unless stated.
+ *  - Invalid arguments return GD_EINVAL before any launch; HIP failures return
+ *    GD_EHIP with the HIP error string in gd_last_error().
+ */
+#ifndef GRACEDG_H
+#define GRACEDG_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GD_OK = 0,
+    GD_EINVAL = -1,   /* bad argument (shape, enum, null pointer)              */
+    GD_EHIP = -2,     /* HIP runtime error                                      */
+    GD_ENOMEM = -3,   /* device or host allocation failed                       */
+    GD_EUNSUPPORTED = -4 /* combination not built (e.g. order > 3 in limiter)  */
+};
+
+/* Collision kernel K(u,v) (Secs. 4.2-4.5). */
+enum {
+    GD_KERNEL_CONST = 0,          /* K = 1                                        */
+    GD_KERNEL_ADDITIVE = 1,       /* K = u + v                                    */
+    GD_KERNEL_MULTIPLICATIVE = 2, /* K = u v                                      */
+    GD_KERNEL_BALLISTIC = 3       /* K = (u^1/3 + v^1/3)^2 dv, dv = v0(u^-1/6+v^-1/6) */
+};
+
+/* Fragment distribution b(w,u,v) of a fragmenting collision (Sec. 2.2, Sec. 4.4,
+ * Eq. break).  A node pair (u,v) fragments when dv(u,v) = v0(u^-1/6 + v^-1/6)
+ * exceeds the threshold v_frag, otherwise it coagulates. */
+enum {
+    GD_FRAG_NONE = 0,            /* pure coagulation                                */
+    GD_FRAG_POWERLAW = 1,        /* b = A w^alpha on [x_min, u+v], no remnant       */
+    GD_FRAG_UNIFORM_BINARY = 2,  /* b = 2/u 1[w<=u] + 2/v 1[w<=v] (Sec. 4.4)         */
+    GD_FRAG_REMNANT_ONLY = 3     /* b = delta(w-(u+v)): fragmentation == coagulation */
+};
+
+/* Arithmetic of the contraction. */
+enum {
+    GD_PREC_FP64 = 0,        /* FP64 MFMA, the plain double-precision form          */
+    GD_PREC_MIXED_F16X3 = 1  /* FP16 hi+lo split of T and of the scaled state,
+                                three FP16 MFMA products, FP32 accumulation; the
+                                mass bookkeeping, limiter and RK update stay FP64 */
+};
+
+typedef struct {
+    int kind;        /* GD_KERNEL_*                                     */
+    double v0;       /* velocity scale of dv (and of the ballistic K)   */
+} gd_kernel;
+
+typedef struct {
+    int kind;              /* GD_FRAG_*                                        */
+    double alpha;          /* power-law index (-11/6 in the paper)             */
+    int n_levels;          /* number of threshold levels (>= 1)                */
+    const double* levels;  /* host array, ascending.  n_levels == 1: the sharp
+                              threshold levels[0] for every cell.  n_levels > 1:
+                              a cell with threshold v uses the linear blend of
+                              the two neighbouring level operators (clamped)    */
+} gd_frag_law;
+
+typedef struct {
+    double x_min, x_max;  /* mass domain                                           */
+    int conservative;     /* 1: dx = -u + x_min (F(x_min)=F(x_max)=0); 0: dx = 0     */
+    int quad_points;      /* Gauss points per (sub)interval; 0 -> order+1 (Sec. 3.3) */
+} gd_grid;
+
+typedef struct gd_tensor gd_tensor;
+typedef struct gd_plan gd_plan;
+
+typedef struct {
+    int bins, order, P;         /* P = bins*(order+1)                               */
+    int n_out;                  /* rows of the raw flux vector                        */
+    int n_levels;
+    long long nnz_folded;       /* structurally nonzero entries of the folded T (p<=q),
+                                   summed over rows, level 0                          */
+    double flops_per_eval;      /* 2 * nnz_folded: algorithmic flops per cell-eval    */
+    size_t device_bytes;        /* device memory held by the tensor                   */
+} gd_tensor_info_t;
+
+/*
+ * gd_init_tensor -- build the collision tensor once per kernel, fragment law,
+ * grid and order (Sec. 3.3; App. B).  The raw flux vector of a cell is
+ *     Y_o = sum_{p,q} T[o][p][q] g_p g_q ,
+ *     Y = (F(e_1),...,F(e_{N-1}), [F(e_N) if non-conservative],
+ *          V_{0,1..k}, ..., V_{N-1,1..k}),
+ *     V_{j,i} = sum_theta w_theta P_i'(s_theta) F(c_j + h_j s_theta / 2),
+ * with the log grid e_j = x_min (x_max/x_min)^(j/N) and Gauss-Legendre sums
+ * split at every bin edge.  T is built in FP64 on the host and uploaded in the
+ * layouts of both contraction precisions.  Synchronous.  *out receives a handle
+ * that the caller releases with gd_free_tensor.
+ */
+int gd_init_tensor(const gd_kernel* kernel, const gd_frag_law* frag, int bins, int order,
+                   const gd_grid* grid, gd_tensor** out);
+int gd_tensor_info(const gd_tensor* t, gd_tensor_info_t* info);
+/* Copy level `level` of the unfolded FP64 tensor to host memory [n_out][P][P]. */
+int gd_tensor_export(const gd_tensor* t, int level, double* host_out);
+/* Copy the bin edges (bins+1 doubles) to host memory. */
+int gd_tensor_edges(const gd_tensor* t, double* host_out);
+void gd_free_tensor(gd_tensor* t);
+
+/*
+ * gd_plan_create -- bind groups of hydro cells to tensors.  Group g has
+ * cells_per_group[g] cells evaluated with tensors[g]; a tensor may serve
+ * several groups.  precision is GD_PREC_*.  stream is a hipStream_t (NULL = the
+ * null stream).  The plan allocates its own device workspace (stage states,
+ * scaled-state fragments, raw flux buffers).  The tensors must outlive the
+ * plan.  Synchronous.
+ */
+int gd_plan_create(const gd_tensor* const* tensors, const int* cells_per_group, int n_groups,
+                   int precision, void* stream, gd_plan** out);
+/* total cells and total state doubles (sum over groups of cells * P) */
+int gd_plan_sizes(const gd_plan* plan, long long* n_cells, long long* n_values);
+void gd_plan_destroy(gd_plan* plan);
+
+/*
+ * gd_collision_rhs -- L[g] for every cell (Eq. evo), no limiting.
+ *  g       : device, state layout, read only.
+ *  kscale  : device [n_cells] per-cell kernel factor, or NULL (1).
+ *  vfrag   : device [n_cells] per-cell threshold, or NULL (levels[0]).
+ *  rhs     : device, state layout, written.
+ *  raw     : device [n_cells][n_out of the cell's group] FP64 raw flux vector Y, or NULL.
+ */
+int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, const double* vfrag,
+                     double* rhs, double* raw);
+
+/*
+ * gd_rk_step -- n_steps of SSP-RK3 (Eq. RK3) in place on g, with the scaling
+ * limiter applied to the start state and after every stage (Sec. 3.2).
+ *  dt          : time step (no CFL check is made on the device).
+ *  violations  : host pointer or NULL; if non-NULL the call synchronises the
+ *                stream and stores the number of bins found with a negative
+ *                average by the limiter (such a bin is flattened, its mass kept).
+ */
+int gd_rk_step(gd_plan* plan, double* g, const double* kscale, const double* vfrag,
+               double dt, int n_steps, long long* violations);
+
+/*
+ * gd_projection_points / gd_project -- initial coefficients (Sec. 3.2, Eq. init):
+ *     g_j^i = (2i+1)/2 sum_a w_a g0(c_j + h_j s_a / 2) P_i(s_a)
+ * with a 16-point Gauss-Legendre rule per bin.  gd_projection_points writes the
+ * sample masses to host memory [bins][16]; the caller evaluates its profile g0 there
+ * for every cell and passes the device array samples [n_cells][bins][16]; coef
+ * [n_cells][P] (device) receives the coefficients.  Synchronous on stream.
+ */
+int gd_projection_points(const gd_tensor* t, double* host_x);
+int gd_project(const gd_tensor* t, int n_cells, const double* samples, double* coef, void* stream);
+
+const char* gd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRACEDG_H */

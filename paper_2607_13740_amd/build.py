@@ -1,0 +1,55 @@
+"""Build the gfx950 collision-operator library in-tree.
+
+    python -m paper_2607_13740_amd.build
+
+compiles ``csrc/tensor_build.cpp`` (host C++) and ``csrc/gracedg.hip`` (HIP for
+gfx950) into ``paper_2607_13740_amd/libgracedg.so``.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libgracedg.so")
+ARCH = os.environ.get("GRACEDG_ARCH", "gfx950")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+HIP_FLAGS = [
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    # keep the compiler from emitting packed FP32 arithmetic
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wno-unused-result",
+]
+
+
+def build(verbose: bool = False) -> str:
+    obj = os.path.join(CSRC, "tensor_build.o")
+    hobj = os.path.join(CSRC, "gracedg.o")
+    cmds = [
+        ["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-c", os.path.join(CSRC, "tensor_build.cpp"), "-o", obj],
+        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "gracedg.hip"), "-o", hobj],
+        [HIPCC, f"--offload-arch={ARCH}", "-shared", hobj, obj, "-pthread", "-o", LIB + ".tmp"],
+    ]
+    for c in cmds:
+        if verbose:
+            print(" ".join(c), flush=True)
+        r = subprocess.run(c, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("build failed: " + " ".join(c))
+        if verbose and (r.stderr.strip()):
+            # hipcc's host pass warns that it does not know the packed-FP32 feature
+            msgs = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln]
+            if msgs:
+                sys.stderr.write("\n".join(msgs) + "\n")
+    os.replace(LIB + ".tmp", LIB)
+    os.remove(obj)
+    os.remove(hobj)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

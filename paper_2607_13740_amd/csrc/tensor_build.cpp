@@ -1,0 +1,331 @@
+// Host FP64 construction of the collision tensor T.
+//
+// With the quadrature rule fixed, the DG right-hand side (Sec. 3.1, Eq. evo)
+// depends on the coefficients g only through the fluxes F(x) at the bin edges and
+// at the interior Gauss nodes (Sec. 3.3), and each F(x) is a quadratic form in g:
+// the nested Gauss-Legendre sums of the truncated coagulation and fragmentation
+// fluxes (Eqs. Fcoagtrun, Ffragtrun; inner fragment-mass integrals of App. B,
+// Eqs. inte1/inte2) multiply g(u) by g(v) node by node.  Collecting the
+// contribution of every node pair to every pair of Legendre coefficients gives
+//     Y_o = sum_{p,q} T[o][p][q] g_p g_q,
+// with one row o per interior edge flux F(e_j) (plus F(e_N) for the
+// non-conservative truncation) and one per volume moment
+// V_{j,i} = sum_theta w_theta P_i'(s_theta) F(x_j^theta), i >= 1.
+//
+// This file walks the nodes once per tensor; the GPU evaluates the quadratic
+// form for many cells at once.
+#include "tensor_build.h"
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <thread>
+#include <cmath>
+#include <cstring>
+#include <stdexcept>
+
+namespace gd {
+
+// Gauss-Legendre nodes/weights on [-1,1] by Newton's method on P_n, starting from
+// the Chebyshev-like guess cos(pi (i + 3/4) / (n + 1/2)); weights 2/((1-x^2) P_n'(x)^2).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int m = 2; m <= n; ++m) {
+                double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        // one more derivative evaluation at the converged node
+        double p0 = 1.0, p1 = z;
+        for (int m = 2; m <= n; ++m) {
+            double p2 = ((2 * m - 1) * z * p1 - (m - 1) * p0) / m;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) { p1 = z; p0 = 1.0; }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[n - 1 - i] = z;   // ascending order
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Legendre values P_0..P_k and derivatives at xi (three-term recurrence).
+static void legendre_all(int k, double xi, double* P, double* dP)
+{
+    P[0] = 1.0;
+    if (dP) dP[0] = 0.0;
+    if (k >= 1) { P[1] = xi; if (dP) dP[1] = 1.0; }
+    for (int n = 1; n < k; ++n) {
+        P[n + 1] = ((2 * n + 1) * xi * P[n] - n * P[n - 1]) / (n + 1);
+        if (dP) dP[n + 1] = dP[n - 1] + (2 * n + 1) * P[n];
+    }
+}
+
+namespace {
+
+struct Node { double x, w; int bin; };
+
+struct Ctx {
+    const TensorSpec* sp;
+    std::vector<double> e;   // edges
+    std::vector<double> s, w;
+    double beta;              // 2 + alpha
+    double xmin_beta;
+};
+
+// composite rule over [a,b], split at edges (Sec. 3.3, the partial bins A..B)
+void pieces(const Ctx& c, double a, double b, std::vector<Node>& out)
+{
+    out.clear();
+    if (!(b > a)) return;
+    const int N = c.sp->bins;
+    // first bin whose right edge exceeds a
+    int j0 = int(std::upper_bound(c.e.begin(), c.e.end(), a) - c.e.begin()) - 1;
+    j0 = std::max(0, std::min(j0, N - 1));
+    for (int j = j0; j < N; ++j) {
+        double lo = std::max(a, c.e[j]);
+        double hi = std::min(b, c.e[j + 1]);
+        if (c.e[j] >= b) break;
+        if (!(hi > lo)) continue;
+        double m = 0.5 * (lo + hi), hw = 0.5 * (hi - lo);
+        for (size_t q = 0; q < c.s.size(); ++q) out.push_back({m + hw * c.s[q], hw * c.w[q], j});
+    }
+}
+
+double kernel_value(const TensorSpec& sp, double u, double v)
+{
+    switch (sp.kernel) {
+    case GD_KERNEL_CONST: return 1.0;
+    case GD_KERNEL_ADDITIVE: return u + v;
+    case GD_KERNEL_MULTIPLICATIVE: return u * v;
+    default: {
+        double r = std::cbrt(u) + std::cbrt(v);
+        return r * r * sp.v0 * (std::pow(u, -1.0 / 6.0) + std::pow(v, -1.0 / 6.0));
+    }
+    }
+}
+
+// relative velocity deciding the collision outcome at a node pair
+double rel_speed(const TensorSpec& sp, double u, double v)
+{
+    return sp.v0 * (std::pow(u, -1.0 / 6.0) + std::pow(v, -1.0 / 6.0));
+}
+
+// fragment mass above x produced by a (u,v) collision: int_x^{u+v} w b(w,u,v) dw
+double mass_above(const Ctx& c, double x, double u, double v)
+{
+    const double S = u + v;
+    switch (c.sp->frag) {
+    case GD_FRAG_POWERLAW: {
+        if (x >= S) return 0.0;
+        double Sb = std::pow(S, c.beta);
+        return S * (Sb - std::pow(x, c.beta)) / (Sb - c.xmin_beta);
+    }
+    case GD_FRAG_UNIFORM_BINARY: {
+        double r = 0.0;
+        if (x < u) r += u - x * x / u;
+        if (x < v) r += v - x * x / v;
+        return r;
+    }
+    case GD_FRAG_REMNANT_ONLY: return x < S ? S : 0.0;
+    default: return 0.0;
+    }
+}
+
+// fragment mass in [x_min, x]: int_{x_min}^x w b(w,u,v) dw
+double mass_below(const Ctx& c, double x, double u, double v)
+{
+    const double S = u + v, xm = c.sp->x_min;
+    switch (c.sp->frag) {
+    case GD_FRAG_POWERLAW: {
+        double top = std::min(x, S);
+        double Sb = std::pow(S, c.beta);
+        return S * (std::pow(top, c.beta) - c.xmin_beta) / (Sb - c.xmin_beta);
+    }
+    case GD_FRAG_UNIFORM_BINARY: {
+        double a = std::min(x, u), b = std::min(x, v);
+        return (a * a - xm * xm) / u + (b * b - xm * xm) / v;
+    }
+    case GD_FRAG_REMNANT_ONLY: return (xm < S && S < x) ? S : 0.0;
+    default: return 0.0;
+    }
+}
+
+// Quadratic form of F(x) for every threshold level: B[r][p][q] with F = sum B g_p g_q.
+void flux_form(const Ctx& c, double x, std::vector<double>& B, std::vector<Node>& un,
+               std::vector<Node>& vn, std::vector<double>& acc)
+{
+    const TensorSpec& sp = *c.sp;
+    const int N = sp.bins, K1 = sp.order + 1, P = N * K1;
+    const int R = std::max(1, int(sp.levels.size()));
+    const bool frag = sp.frag != GD_FRAG_NONE;
+    std::fill(B.begin(), B.end(), 0.0);
+    double Pu[16], Pv[16];
+    acc.assign(size_t(R) * P, 0.0);
+
+    auto close_u = [&](const Node& un_) {
+        // B[r][(l,a)][q] += wu P_a(xi_l(u)) acc[r][q]
+        double h = c.e[un_.bin + 1] - c.e[un_.bin];
+        legendre_all(sp.order, 2.0 * (un_.x - 0.5 * (c.e[un_.bin] + c.e[un_.bin + 1])) / h, Pu, nullptr);
+        for (int r = 0; r < R; ++r) {
+            const double* ar = &acc[size_t(r) * P];
+            for (int a = 0; a < K1; ++a) {
+                double f = un_.w * Pu[a];
+                if (f == 0.0) continue;
+                double* row = &B[(size_t(r) * P + un_.bin * K1 + a) * P];
+                for (int q = 0; q < P; ++q) row[q] += f * ar[q];
+            }
+        }
+    };
+
+    // positive part: u in [x_min, x], v in [x - u + x_min, Vmax(u)]
+    pieces(c, sp.x_min, x, un);
+    for (const Node& u : un) {
+        std::fill(acc.begin(), acc.end(), 0.0);
+        double vmax = sp.conservative ? sp.x_max - u.x + sp.x_min : sp.x_max;
+        pieces(c, x - u.x + sp.x_min, vmax, vn);
+        for (const Node& v : vn) {
+            double h = c.e[v.bin + 1] - c.e[v.bin];
+            legendre_all(sp.order, 2.0 * (v.x - 0.5 * (c.e[v.bin] + c.e[v.bin + 1])) / h, Pv, nullptr);
+            double K = kernel_value(sp, u.x, v.x);
+            double coag = K / v.x;
+            double fr = 0.0, dv = 0.0;
+            if (frag) {
+                fr = K * mass_above(c, x, u.x, v.x) / (v.x * (u.x + v.x));
+                dv = rel_speed(sp, u.x, v.x);
+            }
+            for (int r = 0; r < R; ++r) {
+                double val = (!frag || dv <= sp.levels[r]) ? coag : fr;
+                if (val == 0.0) continue;
+                double* ar = &acc[size_t(r) * P + v.bin * K1];
+                for (int b = 0; b < K1; ++b) ar[b] += v.w * Pv[b] * val;
+            }
+        }
+        close_u(u);
+    }
+    if (!frag) return;
+    // negative part: u in [x, x_max], v in [x_min, Vmax(u)]
+    pieces(c, x, sp.x_max, un);
+    for (const Node& u : un) {
+        std::fill(acc.begin(), acc.end(), 0.0);
+        double vmax = sp.conservative ? sp.x_max - u.x + sp.x_min : sp.x_max;
+        pieces(c, sp.x_min, vmax, vn);
+        for (const Node& v : vn) {
+            double dv = rel_speed(sp, u.x, v.x);
+            double h = c.e[v.bin + 1] - c.e[v.bin];
+            legendre_all(sp.order, 2.0 * (v.x - 0.5 * (c.e[v.bin] + c.e[v.bin + 1])) / h, Pv, nullptr);
+            double val = -kernel_value(sp, u.x, v.x) * mass_below(c, x, u.x, v.x) / (v.x * (u.x + v.x));
+            for (int r = 0; r < R; ++r) {
+                if (!(dv > sp.levels[r]) || val == 0.0) continue;
+                double* ar = &acc[size_t(r) * P + v.bin * K1];
+                for (int b = 0; b < K1; ++b) ar[b] += v.w * Pv[b] * val;
+            }
+        }
+        close_u(u);
+    }
+}
+
+} // namespace
+
+int n_out_rows(const TensorSpec& sp)
+{
+    return (sp.bins - 1) + (sp.conservative ? 0 : 1) + sp.bins * sp.order;
+}
+
+std::vector<double> make_edges(int N, double x_min, double x_max)
+{
+    std::vector<double> e(N + 1);
+    const double ratio = x_max / x_min;
+    for (int j = 0; j <= N; ++j) e[j] = x_min * std::pow(ratio, double(j) / double(N));
+    e[0] = x_min;
+    e[N] = x_max;
+    return e;
+}
+
+void build_tensor(const TensorSpec& sp, HostTensor& out)
+{
+    if (sp.bins < 1 || sp.order < 0 || sp.order > 15 || !(sp.x_min > 0) || !(sp.x_max > sp.x_min))
+        throw std::invalid_argument("bad grid");
+    const int N = sp.bins, k = sp.order, K1 = k + 1, P = N * K1;
+    const int Q = sp.quad_points > 0 ? sp.quad_points : K1;
+    const int R = std::max(1, int(sp.levels.size()));
+    const int NO = n_out_rows(sp);
+
+    Ctx c;
+    c.sp = &sp;
+    c.e = make_edges(N, sp.x_min, sp.x_max);
+    gauss_legendre(Q, c.s, c.w);
+    c.beta = 2.0 + sp.alpha;
+    c.xmin_beta = std::pow(sp.x_min, c.beta);
+
+    out.P = P;
+    out.n_out = NO;
+    out.n_levels = R;
+    out.edges = c.e;
+    out.T.assign(size_t(R) * NO * P * P, 0.0);
+
+    // flux evaluation points and the rows they feed
+    struct Pt { double x; int row0; int nrow; double coef[16]; };
+    std::vector<Pt> pts;
+    int o = 0;
+    for (int j = 1; j < N; ++j) { Pt p{c.e[j], o++, 1, {1.0}}; pts.push_back(p); }
+    if (!sp.conservative) { Pt p{c.e[N], o++, 1, {1.0}}; pts.push_back(p); }
+    const int vbase = o;
+    double Pl[16], dPl[16];
+    if (k > 0) {
+        for (int j = 0; j < N; ++j) {
+            double h = c.e[j + 1] - c.e[j], mid = 0.5 * (c.e[j] + c.e[j + 1]);
+            for (int t = 0; t < Q; ++t) {
+                Pt p{};
+                p.x = mid + 0.5 * h * c.s[t];
+                p.row0 = vbase + j * k;
+                p.nrow = k;
+                legendre_all(k, c.s[t], Pl, dPl);
+                for (int i = 1; i <= k; ++i) p.coef[i - 1] = c.w[t] * dPl[i];
+                pts.push_back(p);
+            }
+        }
+    }
+
+    const int npts = int(pts.size());
+    std::atomic<int> next{0};
+    std::mutex mu;
+    auto worker = [&]() {
+        std::vector<double> B(size_t(R) * P * P), acc;
+        std::vector<Node> un, vn;
+        un.reserve((N + 2) * Q);
+        vn.reserve((N + 2) * Q);
+        for (int t = next++; t < npts; t = next++) {
+            flux_form(c, pts[t].x, B, un, vn, acc);
+            std::lock_guard<std::mutex> lock(mu);
+            for (int r = 0; r < R; ++r)
+                for (int i = 0; i < pts[t].nrow; ++i) {
+                    const double cf = pts[t].coef[i];
+                    double* dst = &out.T[(size_t(r) * NO + pts[t].row0 + i) * P * P];
+                    const double* src = &B[size_t(r) * P * P];
+                    for (int q = 0; q < P * P; ++q) dst[q] += cf * src[q];
+                }
+        }
+    };
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, unsigned(npts));
+    std::vector<std::thread> th;
+    for (unsigned i = 1; i < nth; ++i) th.emplace_back(worker);
+    worker();
+    for (auto& x : th) x.join();
+}
+
+} // namespace gd

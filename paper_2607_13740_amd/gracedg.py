@@ -1,0 +1,227 @@
+"""Python binding of ``libgracedg.so`` (ctypes, argument marshalling only).
+
+Every numerical step runs in the HIP library; this module turns torch tensors
+into device pointers and Python values into the C structs of ``gracedg.h``.
+There is no fallback: if the library is missing the import of any call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgracedg.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "gracedg.h")
+
+GD_OK, GD_EINVAL, GD_EHIP, GD_ENOMEM, GD_EUNSUPPORTED = 0, -1, -2, -3, -4
+KERNELS = {"const": 0, "additive": 1, "multiplicative": 2, "ballistic": 3}
+FRAGS = {"none": 0, "powerlaw": 1, "uniform_binary": 2, "remnant_only": 3}
+PREC = {"fp64": 0, "mixed": 1}
+
+
+class GDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gracedg error {code}: {msg}")
+        self.code = code
+
+
+class _Kernel(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("v0", ctypes.c_double)]
+
+
+class _Frag(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("alpha", ctypes.c_double), ("n_levels", ctypes.c_int),
+                ("levels", ctypes.POINTER(ctypes.c_double))]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("x_min", ctypes.c_double), ("x_max", ctypes.c_double), ("conservative", ctypes.c_int),
+                ("quad_points", ctypes.c_int)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("bins", ctypes.c_int), ("order", ctypes.c_int), ("P", ctypes.c_int), ("n_out", ctypes.c_int),
+                ("n_levels", ctypes.c_int), ("nnz_folded", ctypes.c_longlong),
+                ("flops_per_eval", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_DP = ctypes.POINTER(ctypes.c_double)
+
+
+def declared_symbols():
+    """Names of every function declared in include/gracedg.h."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(gd_[a-z_0-9]+)\s*\(", txt)))
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2607_13740_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        sig = {
+            "gd_init_tensor": ([ctypes.POINTER(_Kernel), ctypes.POINTER(_Frag), ctypes.c_int, ctypes.c_int,
+                                ctypes.POINTER(_Grid), ctypes.POINTER(_VP)], ctypes.c_int),
+            "gd_tensor_info": ([_VP, ctypes.POINTER(_Info)], ctypes.c_int),
+            "gd_tensor_export": ([_VP, ctypes.c_int, _DP], ctypes.c_int),
+            "gd_tensor_edges": ([_VP, _DP], ctypes.c_int),
+            "gd_free_tensor": ([_VP], None),
+            "gd_plan_create": ([ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
+                                _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+            "gd_plan_sizes": ([_VP, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)],
+                              ctypes.c_int),
+            "gd_plan_destroy": ([_VP], None),
+            "gd_collision_rhs": ([_VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+            "gd_rk_step": ([_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
+                            ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+            "gd_projection_points": ([_VP, _DP], ctypes.c_int),
+            "gd_project": ([_VP, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
+            "gd_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != GD_OK:
+        raise GDError(rc, lib().gd_last_error().decode())
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor, or NULL."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev64(t, n, name):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 device tensor")
+    if t.numel() != n:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n}")
+    return _ptr(t)
+
+
+class Tensor:
+    """Collision tensor for one kernel, fragment law, grid and order (gd_init_tensor)."""
+
+    def __init__(self, bins, order, x_min, x_max, kernel="const", frag="none", alpha=-11.0 / 6.0,
+                 levels=(0.5,), v0=1.0, conservative=False, quad_points=0):
+        self.levels = np.ascontiguousarray(levels, dtype=np.float64)
+        k = _Kernel(KERNELS[kernel], float(v0))
+        f = _Frag(FRAGS[frag], float(alpha), int(len(self.levels)),
+                  self.levels.ctypes.data_as(_DP))
+        g = _Grid(float(x_min), float(x_max), int(bool(conservative)), int(quad_points))
+        h = _VP()
+        _check(lib().gd_init_tensor(ctypes.byref(k), ctypes.byref(f), int(bins), int(order), ctypes.byref(g),
+                                    ctypes.byref(h)))
+        self.h = h
+        self.bins, self.order = int(bins), int(order)
+        self.conservative = bool(conservative)
+        inf = self.info()
+        self.P, self.n_out, self.n_levels = inf["P"], inf["n_out"], inf["n_levels"]
+
+    def info(self):
+        i = _Info()
+        _check(lib().gd_tensor_info(self.h, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _Info._fields_}
+
+    def export(self, level=0):
+        out = np.zeros((self.n_out, self.P, self.P))
+        _check(lib().gd_tensor_export(self.h, int(level), out.ctypes.data_as(_DP)))
+        return out
+
+    def edges(self):
+        out = np.zeros(self.bins + 1)
+        _check(lib().gd_tensor_edges(self.h, out.ctypes.data_as(_DP)))
+        return out
+
+    def projection_points(self):
+        out = np.zeros((self.bins, 16))
+        _check(lib().gd_projection_points(self.h, out.ctypes.data_as(_DP)))
+        return out
+
+    def project(self, samples, out=None, stream=None):
+        """samples: float64 device tensor [C, bins, 16] of g0 at projection_points()."""
+        import torch
+        C = samples.shape[0]
+        if out is None:
+            out = torch.empty((C, self.P), dtype=torch.float64, device=samples.device)
+        _dev64(samples, C * self.bins * 16, "samples")
+        _dev64(out, C * self.P, "out")
+        st = stream if stream is not None else torch.cuda.current_stream(samples.device).cuda_stream
+        _check(lib().gd_project(self.h, int(C), _ptr(samples), _ptr(out), ctypes.c_void_p(st)))
+        return out
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.gd_free_tensor(h)
+            self.h = None
+
+
+class Plan:
+    """Groups of hydro cells bound to tensors, one precision, one stream (gd_plan_create)."""
+
+    def __init__(self, tensors, cells, precision="fp64", stream=None):
+        import torch
+        if isinstance(tensors, Tensor):
+            tensors, cells = [tensors], [cells]
+        self.tensors = list(tensors)
+        self.cells = [int(c) for c in cells]
+        arr_t = (_VP * len(self.tensors))(*[t.h for t in self.tensors])
+        arr_c = (ctypes.c_int * len(self.cells))(*self.cells)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        h = _VP()
+        _check(lib().gd_plan_create(arr_t, arr_c, len(self.tensors), PREC[precision], ctypes.c_void_p(stream),
+                                    ctypes.byref(h)))
+        self.h = h
+        nc, nv = ctypes.c_longlong(), ctypes.c_longlong()
+        _check(lib().gd_plan_sizes(self.h, ctypes.byref(nc), ctypes.byref(nv)))
+        self.n_cells, self.n_values = nc.value, nv.value
+        self.n_raw = sum(c * t.n_out for t, c in zip(self.tensors, self.cells))
+
+    def collision_rhs(self, g, kscale=None, vfrag=None, rhs=None, raw=None):
+        import torch
+        if rhs is None:
+            rhs = torch.empty_like(g)
+        _dev64(g, self.n_values, "g")
+        _dev64(rhs, self.n_values, "rhs")
+        _dev64(kscale, self.n_cells, "kscale")
+        _dev64(vfrag, self.n_cells, "vfrag")
+        _dev64(raw, self.n_raw, "raw")
+        _check(lib().gd_collision_rhs(self.h, _ptr(g), _ptr(kscale), _ptr(vfrag), _ptr(rhs), _ptr(raw)))
+        return rhs
+
+    def rk_step(self, g, dt, n_steps=1, kscale=None, vfrag=None, count_violations=False):
+        _dev64(g, self.n_values, "g")
+        _dev64(kscale, self.n_cells, "kscale")
+        _dev64(vfrag, self.n_cells, "vfrag")
+        v = ctypes.c_longlong(0)
+        _check(lib().gd_rk_step(self.h, _ptr(g), _ptr(kscale), _ptr(vfrag), float(dt), int(n_steps),
+                                ctypes.byref(v) if count_violations else None))
+        return v.value if count_violations else None
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and _lib is not None:
+            _lib.gd_plan_destroy(h)
+            self.h = None

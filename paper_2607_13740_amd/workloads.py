@@ -1,0 +1,109 @@
+"""Seeded synthetic workloads: grids, kernels and initial profiles of the benchmark
+configurations.  Nothing here evaluates the collision operator; the module only
+draws per-cell parameters and evaluates initial density profiles at given masses,
+so that the oracle and the HIP library can be fed identical inputs.
+
+Per-cell lognormal profiles (mass density per unit mass):
+    g0(x) = M * exp(-(ln x - mu)^2 / (2 sigma^2)) / (x sigma sqrt(2 pi)),
+drawn with numpy's PCG64 generator in the order (mu, sigma, M, kscale, vfrag):
+mu ~ U[-1, 1], sigma ~ U[0.5, 1.5], M = exp(z), kscale = exp(0.5 z'), z, z' ~ N(0,1),
+vfrag ~ U[0.3, 1.0].
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# threshold levels of the per-cell fragmentation velocity: 0.3, 0.4, ..., 1.0
+VFRAG_LEVELS = tuple(round(0.3 + 0.1 * r, 10) for r in range(8))
+
+
+@dataclass(frozen=True)
+class Workload:
+    name: str
+    bins: int
+    order: int
+    x_min: float
+    x_max: float
+    kernel: str
+    frag: str
+    conservative: bool
+    cells: int
+    dt: float
+    n_steps: int
+    profile: str                 # "xexp" | "lognormal_unit" | "lognormal_cells"
+    seed: int = 0
+    levels: tuple = (0.5,)       # fragmentation threshold table
+    per_cell: bool = False       # per-cell kscale / vfrag
+    groups: tuple = field(default=())   # uneven batch: ((bins, order), ...) drawn per cell
+
+    @property
+    def P(self):
+        return self.bins * (self.order + 1)
+
+
+# Time steps: C1 follows its stated dt; the others use half of the CFL bound (Eq. dt)
+# measured on the seeded initial states, since the high-mass bins of [1e-4, 1e8]
+# lose mass to fragmentation at rates ~1e5-1e8 and larger steps drive them negative.
+WORKLOADS = {
+    "c1_const": Workload("c1_const", 16, 2, 1e-3, 1e5, "const", "none", False, 1, 1e-2, 100, "xexp"),
+    "c2_ballistic": Workload("c2_ballistic", 32, 2, 1e-4, 1e8, "ballistic", "powerlaw", True, 1, 1.5e-6, 1000,
+                             "lognormal_unit"),
+    "c3_batched": Workload("c3_batched", 24, 3, 1e-4, 1e8, "ballistic", "powerlaw", True, 65536, 2e-8, 10,
+                           "lognormal_cells", seed=1, levels=VFRAG_LEVELS, per_cell=True),
+    "c4_uneven": Workload("c4_uneven", 0, 0, 1e-4, 1e8, "additive", "powerlaw", True, 100000, 1e-10, 10,
+                          "lognormal_cells", seed=2,
+                          groups=tuple((n, k) for n in (16, 24, 32, 48) for k in (1, 2, 3))),
+    "c5_adjoint": Workload("c5_adjoint", 32, 2, 1e-4, 1e8, "ballistic", "powerlaw", True, 4096, 2e-8, 200,
+                           "lognormal_cells", seed=3, levels=VFRAG_LEVELS, per_cell=True),
+}
+
+
+def lognormal_cells(n: int, seed: int):
+    """Per-cell (mu, sigma, mass, kscale, vfrag), drawn in that order."""
+    rng = np.random.default_rng(seed)
+    mu = rng.uniform(-1.0, 1.0, n)
+    sigma = rng.uniform(0.5, 1.5, n)
+    mass = np.exp(rng.standard_normal(n))
+    kscale = np.exp(0.5 * rng.standard_normal(n))
+    vfrag = rng.uniform(0.3, 1.0, n)
+    return {"mu": mu, "sigma": sigma, "mass": mass, "kscale": kscale, "vfrag": vfrag}
+
+
+def lognormal_density(x, mu=0.0, sigma=1.0, mass=1.0):
+    """g0(x) for lognormal profiles; mu, sigma, mass broadcast against x."""
+    x = np.asarray(x, dtype=np.float64)
+    lx = np.log(x)
+    return mass * np.exp(-(lx - mu) ** 2 / (2.0 * sigma * sigma)) / (x * sigma * np.sqrt(2.0 * np.pi))
+
+
+def xexp_density(x):
+    """g0(x) = x e^{-x}: the mass density of f0 = e^{-x}."""
+    x = np.asarray(x, dtype=np.float64)
+    return x * np.exp(-x)
+
+
+def samples(w: Workload, points: np.ndarray, cells: int | None = None, params=None):
+    """Initial profile of every cell evaluated at `points` (any shape); returns
+    [cells, *points.shape]."""
+    n = w.cells if cells is None else cells
+    if w.profile == "xexp":
+        return np.broadcast_to(xexp_density(points), (n,) + points.shape).copy()
+    if w.profile == "lognormal_unit":
+        return np.broadcast_to(lognormal_density(points), (n,) + points.shape).copy()
+    p = params if params is not None else lognormal_cells(w.cells, w.seed)
+    sh = (n,) + (1,) * points.ndim
+    return lognormal_density(points[None], p["mu"][:n].reshape(sh), p["sigma"][:n].reshape(sh),
+                             p["mass"][:n].reshape(sh))
+
+
+def uneven_groups(w: Workload):
+    """Uneven batch: (bins, order) of every cell drawn uniformly from w.groups
+    (seeded), returned as the per-group cell counts in the order of w.groups and the
+    permutation that sorts cells by group."""
+    rng = np.random.default_rng(w.seed + 1000)
+    gid = rng.integers(0, len(w.groups), w.cells)
+    counts = np.bincount(gid, minlength=len(w.groups))
+    order = np.argsort(gid, kind="stable")
+    return counts, order

@@ -123,39 +123,48 @@ void gd_free_tensor(gd_tensor* t);
 
 /*
  * gd_plan_create -- bind groups of hydro cells to tensors.  Group g has
- * cells_per_group[g] cells evaluated with tensors[g]; a tensor may serve
- * several groups.  precision is GD_PREC_*.  stream is a hipStream_t (NULL = the
- * null stream).  The plan allocates its own device workspace (stage states,
- * scaled-state fragments, raw flux buffers).  The tensors must outlive the
- * plan.  Synchronous.
+ * cells_per_group[g] cells evaluated with tensors[g]; a tensor may serve several
+ * groups.  precision is GD_PREC_*.
+ *  vfrag  : host [total cells] per-cell fragmentation threshold, or NULL.  Used only
+ *           for tensors built with more than one level: a cell with threshold v is
+ *           evaluated with (1-theta) T_r + theta T_{r+1}, levels[r] <= v < levels[r+1],
+ *           theta = (v - levels[r]) / (levels[r+1] - levels[r]) clamped to [0,1];
+ *           NULL means v = levels[0].  The plan sorts cells into brackets of
+ *           constant r internally; the caller's cell order is kept in every array.
+ *  stream : hipStream_t (NULL = the null stream).
+ * The plan allocates its own device workspace (stage states, split-state fragments,
+ * raw flux buffers).  The tensors must outlive the plan.  Synchronous.
  */
 int gd_plan_create(const gd_tensor* const* tensors, const int* cells_per_group, int n_groups,
-                   int precision, void* stream, gd_plan** out);
+                   int precision, const double* vfrag, void* stream, gd_plan** out);
 /* total cells and total state doubles (sum over groups of cells * P) */
 int gd_plan_sizes(const gd_plan* plan, long long* n_cells, long long* n_values);
+/* stored contraction fragments of a group's tensor (split-FP16 and FP64 layouts,
+ * all levels) and the group's slot count (cells plus bracket padding) */
+int gd_plan_schedule_stats(const gd_plan* plan, int group, long long* frags_mixed, long long* frags_fp64,
+                           int* n_slots);
 void gd_plan_destroy(gd_plan* plan);
 
 /*
  * gd_collision_rhs -- L[g] for every cell (Eq. evo), no limiting.
  *  g       : device, state layout, read only.
  *  kscale  : device [n_cells] per-cell kernel factor, or NULL (1).
- *  vfrag   : device [n_cells] per-cell threshold, or NULL (levels[0]).
  *  rhs     : device, state layout, written.
  *  raw     : device [n_cells][n_out of the cell's group] FP64 raw flux vector Y, or NULL.
  */
-int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, const double* vfrag,
-                     double* rhs, double* raw);
+int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, double* rhs, double* raw);
 
 /*
  * gd_rk_step -- n_steps of SSP-RK3 (Eq. RK3) in place on g, with the scaling
- * limiter applied to the start state and after every stage (Sec. 3.2).
+ * limiter applied to the start state and after every stage (Sec. 3.2):
+ *     y1 = L(g) step, y2 = 3/4 g + 1/4 (y1 + dt L(y1)), g = 1/3 g + 2/3 (y2 + dt L(y2)).
+ *  kscale      : device [n_cells] or NULL.
  *  dt          : time step (no CFL check is made on the device).
  *  violations  : host pointer or NULL; if non-NULL the call synchronises the
  *                stream and stores the number of bins found with a negative
  *                average by the limiter (such a bin is flattened, its mass kept).
  */
-int gd_rk_step(gd_plan* plan, double* g, const double* kscale, const double* vfrag,
-               double dt, int n_steps, long long* violations);
+int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_steps, long long* violations);
 
 /*
  * gd_projection_points / gd_project -- initial coefficients (Sec. 3.2, Eq. init):
@@ -167,6 +176,17 @@ int gd_rk_step(gd_plan* plan, double* g, const double* kscale, const double* vfr
  */
 int gd_projection_points(const gd_tensor* t, double* host_x);
 int gd_project(const gd_tensor* t, int n_cells, const double* samples, double* coef, void* stream);
+
+/*
+ * gd_plan_timing / gd_plan_contraction_time -- measurement support.  While timing
+ * is enabled the plan records a HIP event pair on its stream around every
+ * contraction launch.  gd_plan_contraction_time synchronises the stream, returns
+ * the summed event time (ms) and the number of launches since timing was enabled
+ * or last read, and resets the count.  Enabling timing adds two event records per
+ * launch and nothing else.
+ */
+int gd_plan_timing(gd_plan* plan, int enable);
+int gd_plan_contraction_time(gd_plan* plan, double* total_ms, int* launches);
 
 const char* gd_last_error(void);
 

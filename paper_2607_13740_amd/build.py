@@ -2,8 +2,8 @@
 
     python -m paper_2607_13740_amd.build
 
-compiles ``csrc/tensor_build.cpp`` (host C++) and ``csrc/gracedg.hip`` (HIP for
-gfx950) into ``paper_2607_13740_amd/libgracedg.so``.
+compiles ``csrc/tensor_build.cpp`` (host C++) and the HIP sources of ``csrc/``
+(for gfx950) into ``paper_2607_13740_amd/libgracedg.so``.
 """
 from __future__ import annotations
 
@@ -25,14 +25,21 @@ HIP_FLAGS = [
 ]
 
 
+SOURCES_HIP = ["api.hip", "contract.hip", "state.hip"]
+
+
 def build(verbose: bool = False) -> str:
+    objs = []
+    cmds = []
     obj = os.path.join(CSRC, "tensor_build.o")
-    hobj = os.path.join(CSRC, "gracedg.o")
-    cmds = [
-        ["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-c", os.path.join(CSRC, "tensor_build.cpp"), "-o", obj],
-        [HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, "gracedg.hip"), "-o", hobj],
-        [HIPCC, f"--offload-arch={ARCH}", "-shared", hobj, obj, "-pthread", "-o", LIB + ".tmp"],
-    ]
+    cmds.append(["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-c", os.path.join(CSRC, "tensor_build.cpp"),
+                 "-o", obj])
+    objs.append(obj)
+    for src in SOURCES_HIP:
+        o = os.path.join(CSRC, src.replace(".hip", ".o"))
+        cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
+        objs.append(o)
+    cmds.append([HIPCC, f"--offload-arch={ARCH}", "-shared", *objs, "-pthread", "-o", LIB + ".tmp"])
     for c in cmds:
         if verbose:
             print(" ".join(c), flush=True)
@@ -40,14 +47,14 @@ def build(verbose: bool = False) -> str:
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)
             raise RuntimeError("build failed: " + " ".join(c))
-        if verbose and (r.stderr.strip()):
+        if verbose and r.stderr.strip():
             # hipcc's host pass warns that it does not know the packed-FP32 feature
             msgs = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln]
             if msgs:
                 sys.stderr.write("\n".join(msgs) + "\n")
     os.replace(LIB + ".tmp", LIB)
-    os.remove(obj)
-    os.remove(hobj)
+    for o in objs:
+        os.remove(o)
     return LIB
 
 

@@ -1,0 +1,124 @@
+// Internal declarations shared by the translation units of libgracedg.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/gracedg.h"
+#include "tensor_build.h"
+
+namespace gd {
+
+// ------------------------------------------------------------------ errors
+int fail(int code, const std::string& msg);
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::gd::fail(GD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// ------------------------------------------------------------------ schedules
+// One iteration of the contraction: a row block ob and up to two p values (p and
+// P-1-p, so that iterations carry similar K work).  Bit ks of ma/mb says that the
+// fragment (ob, p, K step ks) is stored; absent fragments are structural zeros.
+struct IterDesc {
+    int ob;
+    int pa, pb;          // pb < 0: single segment
+    int frag;            // first fragment of the iteration (absolute index)
+    int nfrag;           // fragments of the iteration
+    int scale;           // offset of (part, ob) in the stage-2 scale table (mixed path)
+    int delta;           // 1: level-difference part, weighted by the cell's blend factor
+    int pad;
+    unsigned long long ma, mb;
+};
+
+// Device layouts of one tensor for one contraction precision.
+struct Schedule {
+    const void* frag = nullptr;           // mixed: uint4 (hi 64 lanes, then lo); fp64: double (64 lanes)
+    const IterDesc* iters = nullptr;      // all levels, concatenated
+    const int* iter_off = nullptr;        // [levels] first iteration of the level
+    const int* iter_cnt = nullptr;        // [levels] iterations of the level
+    const float* scale = nullptr;         // mixed: stage-2 factors
+    long long frags = 0;                  // stored fragments (all levels)
+    long long iters_total = 0;
+};
+
+// ------------------------------------------------------------------ kernel arguments
+struct PrologueArgs {
+    double* g;                 // caller state (cell order)
+    const int* perm;           // slot -> cell (nullptr: identity)
+    int n_slots, n_tiles, N, k, P, KS;
+    int limit;                 // apply the limiter in place
+    int mixed;                 // write split fragments
+    const double* h;           // [N]
+    const double* colscale;    // [P]
+    uint4* mfrag;
+    float* mt;
+    int* eslot;                // [n_slots] per-slot exponent
+    unsigned long long* viol;
+};
+
+struct MixedArgs {
+    const uint4* frag;
+    const IterDesc* iters;
+    const int* iter_off;
+    const int* iter_cnt;
+    const float* scale;
+    const int* slot_level;     // [n_slots] (nullptr: level 0)
+    const double* theta;       // [n_slots] blend weight (nullptr: 0)
+    const uint4* mfrag;
+    const float* mt;
+    float* Y;                  // [n_slots][ystride]
+    int KS, n_tiles, n_slots, P, ystride;
+};
+
+struct F64Args {
+    const double* frag;
+    const IterDesc* iters;
+    const int* iter_off;
+    const int* iter_cnt;
+    const int* slot_level;
+    const double* theta;
+    const int* perm;
+    const double* g;           // caller state
+    double* Y;                 // [n_slots][ystride]
+    int KS, n_tiles, n_slots, P, ystride;
+};
+
+struct EpilogueArgs {
+    const float* Yf;           // mixed raw (scaled)  or nullptr
+    const double* Yd;          // fp64 raw            or nullptr
+    const double* rowscale;    // mixed: [n_out rows]
+    const int* eslot;          // mixed: [n_slots]
+    const int* perm;
+    const double* kscale;      // [cells] or nullptr
+    const double* gn;          // RK base state (cell order)
+    const double* gs;          // stage input state
+    double* out;
+    double* raw;               // optional FP64 raw output [cells][n_out]
+    const double* h;
+    double dt;
+    int n_slots, N, k, P, n_out, ystride, conservative, mode;
+};
+
+// ------------------------------------------------------------------ launchers
+int launch_prologue(const PrologueArgs& a, hipStream_t s);
+int launch_epilogue(const EpilogueArgs& a, hipStream_t s);
+int launch_limit(double* g, int C, int N, int k, int P, unsigned long long* viol, hipStream_t s);
+int launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
+int launch_project(const double* samples, const double* wP, double* coef, int C, int N, int k, hipStream_t s);
+int launch_contract_mixed(const MixedArgs& a, hipStream_t s);
+int launch_contract_fp64(const F64Args& a, hipStream_t s);
+// cells per workgroup of the contraction for a given K-step count (tiles are padded to it)
+int slots_per_wg_mixed(int KS);
+int slots_per_wg_fp64(int KS4);
+
+} // namespace gd

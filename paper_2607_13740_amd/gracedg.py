@@ -74,15 +74,19 @@ def lib():
             "gd_tensor_edges": ([_VP, _DP], ctypes.c_int),
             "gd_free_tensor": ([_VP], None),
             "gd_plan_create": ([ctypes.POINTER(_VP), ctypes.POINTER(ctypes.c_int), ctypes.c_int, ctypes.c_int,
-                                _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+                                _DP, _VP, ctypes.POINTER(_VP)], ctypes.c_int),
+            "gd_plan_schedule_stats": ([_VP, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                                        ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_plan_sizes": ([_VP, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)],
                               ctypes.c_int),
             "gd_plan_destroy": ([_VP], None),
-            "gd_collision_rhs": ([_VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
-            "gd_rk_step": ([_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
+            "gd_collision_rhs": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+            "gd_rk_step": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_projection_points": ([_VP, _DP], ctypes.c_int),
             "gd_project": ([_VP, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
+            "gd_plan_timing": ([_VP, ctypes.c_int], ctypes.c_int),
+            "gd_plan_contraction_time": ([_VP, _DP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_last_error": ([], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -177,9 +181,12 @@ class Tensor:
 
 
 class Plan:
-    """Groups of hydro cells bound to tensors, one precision, one stream (gd_plan_create)."""
+    """Groups of hydro cells bound to tensors, one precision, one stream (gd_plan_create).
 
-    def __init__(self, tensors, cells, precision="fp64", stream=None):
+    vfrag: optional per-cell fragmentation thresholds (host array, all cells in plan
+    order), used by tensors with several threshold levels."""
+
+    def __init__(self, tensors, cells, precision="fp64", vfrag=None, stream=None):
         import torch
         if isinstance(tensors, Tensor):
             tensors, cells = [tensors], [cells]
@@ -190,8 +197,14 @@ class Plan:
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
+        vf = None
+        if vfrag is not None:
+            self._vfrag = np.ascontiguousarray(vfrag, dtype=np.float64)
+            if self._vfrag.size != sum(self.cells):
+                raise ValueError("vfrag needs one value per cell")
+            vf = self._vfrag.ctypes.data_as(_DP)
         h = _VP()
-        _check(lib().gd_plan_create(arr_t, arr_c, len(self.tensors), PREC[precision], ctypes.c_void_p(stream),
+        _check(lib().gd_plan_create(arr_t, arr_c, len(self.tensors), PREC[precision], vf, ctypes.c_void_p(stream),
                                     ctypes.byref(h)))
         self.h = h
         nc, nv = ctypes.c_longlong(), ctypes.c_longlong()
@@ -199,26 +212,39 @@ class Plan:
         self.n_cells, self.n_values = nc.value, nv.value
         self.n_raw = sum(c * t.n_out for t, c in zip(self.tensors, self.cells))
 
-    def collision_rhs(self, g, kscale=None, vfrag=None, rhs=None, raw=None):
+    def schedule_stats(self, group=0):
+        fm, ff, ns = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+        _check(lib().gd_plan_schedule_stats(self.h, int(group), ctypes.byref(fm), ctypes.byref(ff), ctypes.byref(ns)))
+        return {"frags_mixed": fm.value, "frags_fp64": ff.value, "n_slots": ns.value}
+
+    def collision_rhs(self, g, kscale=None, rhs=None, raw=None):
         import torch
         if rhs is None:
             rhs = torch.empty_like(g)
         _dev64(g, self.n_values, "g")
         _dev64(rhs, self.n_values, "rhs")
         _dev64(kscale, self.n_cells, "kscale")
-        _dev64(vfrag, self.n_cells, "vfrag")
         _dev64(raw, self.n_raw, "raw")
-        _check(lib().gd_collision_rhs(self.h, _ptr(g), _ptr(kscale), _ptr(vfrag), _ptr(rhs), _ptr(raw)))
+        _check(lib().gd_collision_rhs(self.h, _ptr(g), _ptr(kscale), _ptr(rhs), _ptr(raw)))
         return rhs
 
-    def rk_step(self, g, dt, n_steps=1, kscale=None, vfrag=None, count_violations=False):
+    def rk_step(self, g, dt, n_steps=1, kscale=None, count_violations=False):
         _dev64(g, self.n_values, "g")
         _dev64(kscale, self.n_cells, "kscale")
-        _dev64(vfrag, self.n_cells, "vfrag")
         v = ctypes.c_longlong(0)
-        _check(lib().gd_rk_step(self.h, _ptr(g), _ptr(kscale), _ptr(vfrag), float(dt), int(n_steps),
+        _check(lib().gd_rk_step(self.h, _ptr(g), _ptr(kscale), float(dt), int(n_steps),
                                 ctypes.byref(v) if count_violations else None))
         return v.value if count_violations else None
+
+    def timing(self, enable=True):
+        _check(lib().gd_plan_timing(self.h, int(bool(enable))))
+
+    def contraction_time(self):
+        """(total ms, launches) of the contraction kernels since timing was enabled."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(lib().gd_plan_contraction_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -58,6 +58,21 @@ def _eps(Yg, Yo):
     return np.max(np.abs(Yg - Yo), axis=1) / np.max(np.abs(Yo), axis=1)
 
 
+def _check_tail_negativity(gg, h, K1, v, prec):
+    """FP64 runs inside the CFL bound keep every bin average nonnegative.  The split-FP16
+    contraction carries an absolute error of ~1e-12 of the largest flux, which can turn
+    bins holding ~1e-20 of the mass slightly negative; the limiter counts them.  Such
+    averages must stay negligible next to the cell's largest bin mass."""
+    gg = np.atleast_2d(gg)
+    h = np.atleast_2d(h)
+    m = (gg * h)[:, ::K1]
+    if prec == "fp64":
+        assert v == 0 and m.min() >= 0.0
+    else:
+        neg = np.minimum(m, 0.0).min(axis=1) / np.abs(m).max(axis=1)
+        assert neg.min() >= -1e-9, neg.min()
+
+
 def _rhs(plan, g, ks=None):
     gd = torch.tensor(g, device=DEV)
     raw = torch.zeros(plan.n_raw, dtype=torch.float64, device=DEV)
@@ -83,12 +98,12 @@ def test_collision_rhs_matches_oracle(oracle, name, prec):
     eps = _eps(Yg, Yo)
     tol = 1e-12 if prec == "fp64" else 1e-6
     assert eps.max() <= tol, (name, prec, eps.max(), np.median(eps))
-    # L: per bin the same normwise comparison on h_j L_{j,i}
+    # L: h_j L_{j,i} / (2i+1) = V_{j,i} - F_{j+1} + (-1)^i F_j combines three raw entries, so
+    # its error is bounded by three times the raw-vector error, in units of max_o |Y_o|
     h = np.diff(O.edges(cfg))
-    hL = (L.reshape(C, cfg.N, -1) * h[None, :, None]).reshape(C, -1)
-    hLo = (Lo.reshape(C, cfg.N, -1) * h[None, :, None]).reshape(C, -1)
-    epsL = np.max(np.abs(hL - hLo), axis=1) / np.max(np.abs(hLo), axis=1)
-    assert epsL.max() <= (4e-12 if prec == "fp64" else 4e-6), epsL.max()
+    w = (h[:, None] / (2 * np.arange(cfg.k + 1) + 1)[None, :])[None]
+    dL = np.abs((L - Lo).reshape(C, cfg.N, -1) * w).reshape(C, -1).max(axis=1)
+    assert (dL / np.abs(Yo).max(axis=1)).max() <= 3 * tol * (1.0 + 1e-9)
     # mass bookkeeping: the bin-mass rates telescope to zero for the conservative flux
     if cfg.conservative:
         dm = (L.reshape(C, cfg.N, -1)[:, :, 0] * h).sum(axis=1)
@@ -152,8 +167,9 @@ def test_rk_matches_oracle_constant_kernel(oracle, prec):
     gg = gd.cpu().numpy().reshape(1, -1)
     h = np.repeat(np.diff(O.edges(cfg)), w.order + 1)
     err = np.max(np.abs((gg - go) * h)) / np.max(np.abs(go * h))
-    assert v == vo == 0
+    assert vo == 0
     assert err <= (1e-11 if prec == "fp64" else 1e-6), err
+    _check_tail_negativity(gg, h, cfg.k + 1, v, prec)
     # the closed form at tau = 1 is reached to the discretisation error
     assert O.error_c(cfg, gg, lambda x: O.g_const(x, 1.0)) < 0.05
 
@@ -167,7 +183,8 @@ def test_rk_matches_oracle_fragmentation(oracle, prec):
     C = 40
     g, p = _states(O, cfg, C, seed=9)
     ks = p["kscale"]
-    dt, n = W.WORKLOADS["c2_ballistic"].dt / 4, 20
+    g, _ = O.limit(cfg, g)
+    dt, n = 0.5 * O.cfl_dt(cfg, g, kscale=ks), 20
     go, vo = O.rk(cfg, g, dt, n, kscale=ks)
     plan = G.Plan(t, C, precision=prec)
     gd = torch.tensor(g, device=DEV).view(-1)
@@ -175,7 +192,8 @@ def test_rk_matches_oracle_fragmentation(oracle, prec):
     gg = gd.cpu().numpy().reshape(C, -1)
     h = np.tile(np.repeat(np.diff(O.edges(cfg)), cfg.k + 1), (C, 1))
     err = np.max(np.abs((gg - go) * h), axis=1) / np.max(np.abs(go * h), axis=1)
-    assert v == vo
+    assert vo == 0
+    _check_tail_negativity(gg, h, cfg.k + 1, v, prec)
     assert err.max() <= (1e-11 if prec == "fp64" else 1e-6), err.max()
     # exact mass conservation of the conservative flux, in FP64 bookkeeping
     m0 = (g * h)[:, ::cfg.k + 1].sum(axis=1)
@@ -207,3 +225,61 @@ def test_projection_matches_oracle(oracle):
     for c in range(8):
         ref = O.project(cfg, lambda xx: W.lognormal_density(xx, p["mu"][c], p["sigma"][c], p["mass"][c]))
         assert np.max(np.abs(coef[c] - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_per_cell_thresholds_match_oracle(oracle, prec):
+    """Per-cell v_frag between tabulated levels: the blend of the two neighbouring
+    level operators, cells sorted into brackets by the plan; the caller's order is kept.
+    Profiles sit near x ~ 300, where like pairs change outcome between the levels."""
+    O = oracle
+    lv = W.VFRAG_LEVELS
+    N, k, C = 12, 3, 300
+    t = G.Tensor(N, k, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=lv, conservative=True)
+    cfg = O.Config(N=N, k=k, xmin=1e-4, xmax=1e8, kernel="ballistic", frag="powerlaw", conservative=True,
+                   levels=lv)
+    rng = np.random.default_rng(21)
+    vf = rng.uniform(0.25, 1.05, C)      # includes values outside the table (clamped)
+    vf[:5] = [0.3, 0.4, 1.0, 0.65, 0.7]
+    g = np.stack([O.project(cfg, lambda x, mu=mu: W.lognormal_density(x, mu, 1.0, 1.0))
+                  for mu in rng.uniform(np.log(30.0), np.log(3000.0), C)])
+    ks = np.exp(0.5 * rng.standard_normal(C))
+    Yo, Lo, _ = O.rhs(cfg, g, kscale=ks, vfrag=vf)
+    plan = G.Plan(t, C, precision=prec, vfrag=vf)
+    assert plan.schedule_stats(0)["n_slots"] % 256 == 0
+    L, raw = _rhs(plan, g, ks)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert _eps(raw.reshape(C, -1), Yo).max() <= tol
+    # the threshold matters for these profiles: levels apart differ by far more than tol
+    Y3, _, _ = O.rhs(cfg, g[:5], kscale=ks[:5], vfrag=np.full(5, 1.0))
+    assert _eps(Y3, Yo[:5]).max() > 1e-3
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_full_size_batched_workload_sampled(oracle, prec):
+    """The benchmark workload at full size in the benchmark's launch configuration:
+    65536 cells, P = 96, per-cell kernel scale and threshold.  Sampled cells are
+    compared with the oracle; mass conservation is checked on every cell."""
+    O = oracle
+    w = W.WORKLOADS["c3_batched"]
+    t = G.Tensor(w.bins, w.order, w.x_min, w.x_max, kernel=w.kernel, frag=w.frag, levels=w.levels,
+                 conservative=w.conservative)
+    p = W.lognormal_cells(w.cells, w.seed)
+    x = t.projection_points()
+    g0 = t.project(torch.tensor(W.samples(w, x, params=p), device=DEV)).reshape(-1)
+    ks = torch.tensor(p["kscale"], device=DEV)
+    plan = G.Plan(t, w.cells, precision=prec, vfrag=p["vfrag"])
+    raw = torch.zeros(plan.n_raw, dtype=torch.float64, device=DEV)
+    L = plan.collision_rhs(g0, kscale=ks, raw=raw)
+    torch.cuda.synchronize()
+    cfg = O.Config(N=w.bins, k=w.order, xmin=w.x_min, xmax=w.x_max, kernel=w.kernel, frag=w.frag,
+                   conservative=w.conservative, levels=w.levels)
+    idx = np.random.default_rng(5).choice(w.cells, 24, replace=False)
+    idx[:2] = [0, w.cells - 1]
+    gs = g0.view(w.cells, -1)[idx].cpu().numpy()
+    Yo, _, _ = O.rhs(cfg, gs, kscale=p["kscale"][idx], vfrag=p["vfrag"][idx])
+    Yg = raw.view(w.cells, -1)[idx].cpu().numpy()
+    assert _eps(Yg, Yo).max() <= (1e-12 if prec == "fp64" else 1e-6)
+    h = torch.tensor(np.diff(t.edges()), device=DEV)
+    L0 = L.view(w.cells, w.bins, w.order + 1)[:, :, 0] * h
+    assert float((L0.sum(1).abs() / L0.abs().sum(1)).max()) <= 1e-13

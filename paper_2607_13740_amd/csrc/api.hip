@@ -100,11 +100,12 @@ static inline int pow2_exp(double v)
     return E;
 }
 
-// Generic schedule builder: row blocks of RB rows, K steps of KW columns.
-// emit(r, delta, ob, p, ks) appends one fragment; blockscale(r, delta, ob) returns the
-// offset of the stage-2 scale table of that (part, ob) (or 0).
+// Generic schedule builder: row blocks of RB rows, K steps of KW columns, up to SEG
+// p segments per iteration.  emit(r, delta, ob, p, ks) appends one fragment;
+// blockscale(r, delta, ob) returns the offset of the stage-2 scale table of that
+// (part, ob) (or 0).  Every level ends with an empty sentinel descriptor (ob = -1).
 template <class Emit, class BlockScale>
-static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterDesc>& iters,
+static void build_schedule(const gd_tensor* t, int RB, int KW, int SEG, std::vector<IterDesc>& iters,
                            std::vector<int>& off, std::vector<int>& cnt, Emit emit, BlockScale blockscale)
 {
     const int P = t->P, NO = t->n_out, R = t->R;
@@ -120,36 +121,44 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterD
             for (int delta = 0; delta <= (r + 1 < R ? 1 : 0); ++delta) {
                 const int sc = blockscale(r, delta, ob);
                 if (first_scale < 0) first_scale = sc;
-                for (auto& pr : pairs) {
-                    unsigned long long mask[2] = {0ull, 0ull};
-                    for (int seg = 0; seg < 2; ++seg) {
-                        const int p = seg ? pr.second : pr.first;
+                // present segments of this (part, ob), in pair order: the K steps from the
+                // first to the last nonzero block of p (zero blocks in between are stored)
+                struct Seg { int p, lo, hi; };
+                std::vector<Seg> segs;
+                for (auto& pr : pairs)
+                    for (int side = 0; side < 2; ++side) {
+                        const int p = side ? pr.second : pr.first;
                         if (p < 0) continue;
+                        int lo = -1, hi = -1;
                         for (int ks = p / KW; ks < KSx; ++ks) {
                             bool nz = false;
                             for (int o = ob * RB; o < std::min(NO, ob * RB + RB) && !nz; ++o)
                                 for (int q = std::max(p, ks * KW); q < std::min(P, ks * KW + KW); ++q)
                                     if (part(t, r, delta, o, p, q) != 0.0) { nz = true; break; }
-                            if (nz) mask[seg] |= 1ull << ks;
+                            if (nz) {
+                                if (lo < 0) lo = ks;
+                                hi = ks;
+                            }
                         }
+                        // the kernels run every segment to the last K step
+                        if (lo >= 0) segs.push_back({p, lo, KSx - 1});
+                        (void)hi;
                     }
-                    if (!mask[0] && !mask[1]) continue;
+                for (size_t s0 = 0; s0 < segs.size(); s0 += SEG) {
                     IterDesc d{};
                     d.ob = ob;
-                    d.pa = pr.first;
-                    d.pb = pr.second;
-                    d.frag = nfrag;
-                    d.scale = sc;
                     d.delta = delta;
-                    d.ma = mask[0];
-                    d.mb = mask[1];
-                    for (int seg = 0; seg < 2; ++seg) {
-                        const int p = seg ? pr.second : pr.first;
-                        for (int ks = 0; ks < KSx; ++ks)
-                            if ((mask[seg] >> ks) & 1ull) {
-                                emit(r, delta, ob, p, ks);
-                                ++nfrag;
-                            }
+                    d.scale = sc;
+                    d.frag = nfrag;
+                    d.nseg = int(std::min<size_t>(SEG, segs.size() - s0));
+                    for (int j = 0; j < d.nseg; ++j) {
+                        d.p[j] = segs[s0 + j].p;
+                        d.lo[j] = segs[s0 + j].lo;
+                        d.hi[j] = segs[s0 + j].hi;
+                        for (int ks = d.lo[j]; ks <= d.hi[j]; ++ks) {
+                            emit(r, delta, ob, d.p[j], ks);
+                            ++nfrag;
+                        }
                     }
                     d.nfrag = nfrag - d.frag;
                     iters.push_back(d);
@@ -160,14 +169,16 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterD
                 // a row block with no stored fragment still has its (zero) rows written
                 IterDesc d{};
                 d.ob = ob;
-                d.pa = 0;
-                d.pb = -1;
                 d.frag = nfrag;
                 d.scale = std::max(0, first_scale);
                 iters.push_back(d);
             }
         }
         cnt.push_back(int(iters.size()) - off.back());
+        IterDesc sentinel{};
+        sentinel.ob = -1;
+        sentinel.frag = nfrag;
+        iters.push_back(sentinel);
     }
 }
 
@@ -249,7 +260,7 @@ static int pack_tensor(gd_tensor* t)
                     frag[f * 1024 + 512 + l * 8 + j] = bl;
                 }
         };
-        build_schedule(t, 32, 16, iters, off, cnt, emit, blockscale);
+        build_schedule(t, 32, 16, segs_per_iter(t->KS), iters, off, cnt, emit, blockscale);
         const uint16_t* dfrag = nullptr;
         if ((rc = upload(t->bufs, frag, &dfrag, &t->bytes))) return rc;
         t->mixed.frag = dfrag;
@@ -261,25 +272,26 @@ static int pack_tensor(gd_tensor* t)
         if ((rc = upload(t->bufs, scale, &t->mixed.scale, &t->bytes))) return rc;
     }
 
-    // ---------------- FP64 schedule (16 rows x 4 K per fragment), T as built
+    // ---------------- FP64 schedule (16 rows x 16 K per fragment as four 4-column steps), T as built
     {
         std::vector<IterDesc> iters;
         std::vector<int> off, cnt;
         std::vector<double> frag;
         auto blockscale = [&](int, int, int) { return 0; };
         auto emit = [&](int r, int delta, int ob, int p, int ks) {
-            const size_t f = frag.size() / 64;
-            frag.resize(frag.size() + 64, 0.0);
-            for (int l = 0; l < 64; ++l) {
-                const int o = ob * 16 + (l & 15), q = ks * 4 + (l >> 4);
-                if (o < NO && q < P && q >= p) frag[f * 64 + l] = part(t, r, delta, o, p, q);
-            }
+            const size_t f = frag.size() / 256;
+            frag.resize(frag.size() + 256, 0.0);
+            for (int j = 0; j < 4; ++j)
+                for (int l = 0; l < 64; ++l) {
+                    const int o = ob * 16 + (l & 15), q = ks * 16 + 4 * j + (l >> 4);
+                    if (o < NO && q < P && q >= p) frag[f * 256 + j * 64 + l] = part(t, r, delta, o, p, q);
+                }
         };
-        build_schedule(t, 16, 4, iters, off, cnt, emit, blockscale);
+        build_schedule(t, 16, 16, segs_per_iter(t->KS), iters, off, cnt, emit, blockscale);
         const double* dfrag = nullptr;
         if ((rc = upload(t->bufs, frag, &dfrag, &t->bytes))) return rc;
         t->f64.frag = dfrag;
-        t->f64.frags = (long long)(frag.size() / 64);
+        t->f64.frags = (long long)(frag.size() / 256);
         t->f64.iters_total = (long long)iters.size();
         if ((rc = upload(t->bufs, iters, &t->f64.iters, &t->bytes))) return rc;
         if ((rc = upload(t->bufs, off, &t->f64.iter_off, &t->bytes))) return rc;
@@ -584,7 +596,7 @@ static int eval_group(gd_plan* pl, Group& G, double* gs, int limit, const double
         if ((rc = launch_contract_mixed(ma, s))) return rc;
     } else {
         F64Args fa{};
-        fa.frag = static_cast<const double*>(t->f64.frag);
+        fa.frag = static_cast<const uint4*>(t->f64.frag);
         fa.iters = t->f64.iters;
         fa.iter_off = t->f64.iter_off;
         fa.iter_cnt = t->f64.iter_cnt;
@@ -593,7 +605,7 @@ static int eval_group(gd_plan* pl, Group& G, double* gs, int limit, const double
         fa.perm = G.perm;
         fa.g = gs;
         fa.Y = G.Yd;
-        fa.KS = t->KS4;
+        fa.KS = t->KS;
         fa.n_tiles = G.tiles16;
         fa.n_slots = G.n_slots;
         fa.P = t->P;

@@ -4,10 +4,17 @@
 //     Z_p(c)[o] = sum_{q>=p} Tf[o][p][q] g_q(c)     MFMA: A = T (rows o), B = cells
 //     Y_o(c)   += w_p(c) Z_p(c)[o]                  VALU, FP64 accumulation
 //
-// A workgroup (4 waves) shares one schedule of iterations; every iteration stages
-// the T fragments of two p values in LDS (double buffered, prefetched one
-// iteration ahead into registers) and every wave applies them to its own tiles of
-// cells, whose B operands stay in registers for the whole launch.
+// A workgroup (8 waves) walks one schedule of iterations.  Each iteration carries up
+// to SEG p values of one row block.  Its T fragments (2 KB each) are copied
+// global -> LDS by the LDS-DMA path (global_load_lds_dwordx4) one iteration ahead
+// into the other of two static LDS buffers, together with the next descriptor and
+// stage-2 weights, while the waves run the current iteration.  The two buffers are
+// distinct LDS objects so that reads of one are not ordered after the DMA into the
+// other.  Each wave keeps the B operands of its tile of cells in registers for
+// the whole launch.  A segment covers the K steps lo..KS-1 of one p; every lo has
+// its own straight-line MFMA chain, selected by uniform branches, so that
+// accumulators never cross a branch.  Workgroups are numbered XCD by XCD so
+// that the cells of one XCD (and the tensor levels they use) share one L2.
 #include "gd_internal.h"
 
 namespace gd {
@@ -15,310 +22,290 @@ namespace gd {
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+typedef __attribute__((address_space(1))) void* gbl_ptr_t;
+
+// Hardware dispatches workgroup b to XCD b % 8.  Renumber so that XCD x runs a
+// contiguous range of logical workgroups.
+__device__ __forceinline__ int xcd_remap(int b, int n)
+{
+    const int xcd = b & 7, idx = b >> 3;
+    const int q = n >> 3, r = n & 7;
+    return xcd * q + min(xcd, r) + idx;
+}
+
+// copy nfrag 2 KB fragments into LDS as 1 KB chunks shared out over the waves
+__device__ __forceinline__ void dma_frags(const uint4* src, uint4* dst, int nfrag, int wave, int lane, int nwaves)
+{
+    for (int c = wave; c < 2 * nfrag; c += nwaves)
+        __builtin_amdgcn_global_load_lds((gbl_ptr_t)(src + c * 64 + lane), (lds_ptr_t)(dst + c * 64), 16, 0, 0);
+}
+
+// Uniform dispatch on lo to a compile-time chain F::run<LO> (segments run to the last K step).
+template <int KS, int LO, class F>
+__device__ __forceinline__ void pick_lo(int lo, F& f)
+{
+    if constexpr (LO < KS) {
+        if (lo == LO) f.template run<LO>();
+        else pick_lo<KS, LO + 1>(lo, f);
+    }
+}
+
+constexpr int kWaves = 8;   // waves per workgroup, one tile of cells each
 
 // ---------------------------------------------------------------------------
 // Split FP16: 32x32x16 MFMA, tiles of 32 slots, row blocks of 32, K steps of 16.
 // A lane l holds T[o = l%32][q = 16ks + 8(l/32) + j]; B lane l holds
 // m[slot = l%32][q = 16ks + 8(l/32) + j]; D register r of lane l holds
-// row 8(r/4) + 4(l/32) + r%4, column l%32.
-template <int KSMAX, int NT>
-__global__ __launch_bounds__(256) void k_contract_mixed(MixedArgs a)
+// row 8(r/4) + 4(l/32) + r%4, column l%32.  A fragment: hi halves of the 64 lanes,
+// then lo halves.
+template <int KS>
+struct MixedSeg {
+    const uint4* A;                 // first fragment of the segment in LDS, + lane
+    const uint4* bh;                // [KS]
+    const uint4* bl;
+    double w;                       // stage-2 weight of the lane's cell
+    double* Y;                      // [16]
+    template <int LO>
+    __device__ __forceinline__ void run()
+    {
+        floatx16 Z;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Z[r] = 0.0f;
+#pragma unroll
+        for (int ks = LO; ks < KS; ++ks) {
+            const half8_t xh = __builtin_bit_cast(half8_t, A[(ks - LO) * 128]);
+            const half8_t xl = __builtin_bit_cast(half8_t, A[(ks - LO) * 128 + 64]);
+            const half8_t mh = __builtin_bit_cast(half8_t, bh[ks]);
+            const half8_t ml = __builtin_bit_cast(half8_t, bl[ks]);
+            Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(xh, mh, Z, 0, 0, 0);
+            Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(xh, ml, Z, 0, 0, 0);
+            Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(xl, mh, Z, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Y[r] = fma(w, (double)Z[r], Y[r]);
+    }
+};
+
+template <int KS>
+__global__ __launch_bounds__(64 * kWaves) void k_contract_mixed(MixedArgs a)
 {
-    extern __shared__ uint4 lds[];
+    constexpr int SEG = (KS <= 8) ? 4 : 2;
+    constexpr int BUF = SEG * KS * 128;   // uint4 per buffer
+    __shared__ uint4 buf0[BUF];
+    __shared__ uint4 buf1[BUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile0 = (blockIdx.x * 4 + wave) * NT;
-    constexpr int BUF = 2 * KSMAX * 128;   // uint4 per buffer: up to 2*KSMAX fragments of 2 KB
-    const int level = a.slot_level ? a.slot_level[blockIdx.x * 4 * NT * 32] : 0;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = wg * kWaves + wave;
+    const int level = a.slot_level ? a.slot_level[wg * kWaves * 32] : 0;
     const IterDesc* its = a.iters + a.iter_off[level];
     const int n_it = a.iter_cnt[level];
 
-    half8_t bh[NT][KSMAX], bl[NT][KSMAX];
-    double th[NT];
+    const bool tv = tile < a.n_tiles;
+    const int tcl = min(tile, a.n_tiles - 1);
+    const int slot = tile * 32 + (lane & 31);
+    const double th = (tv && a.theta && slot < a.n_slots) ? a.theta[slot] : 0.0;
+    uint4 bh[KS], bl[KS];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const bool tv = tile0 + t < a.n_tiles;
-        const int slot = (tile0 + t) * 32 + (lane & 31);
-        th[t] = (tv && a.theta && slot < a.n_slots) ? a.theta[slot] : 0.0;
-#pragma unroll
-        for (int ks = 0; ks < KSMAX; ++ks) {
-            uint4 vh = {0, 0, 0, 0}, vl = {0, 0, 0, 0};
-            if (tv && ks < a.KS) {
-                const size_t base = ((size_t)((tile0 + t) * a.KS + ks) * 2) * 64 + lane;
-                vh = a.mfrag[base];
-                vl = a.mfrag[base + 64];
-            }
-            bh[t][ks] = *reinterpret_cast<half8_t*>(&vh);
-            bl[t][ks] = *reinterpret_cast<half8_t*>(&vl);
-        }
+    for (int ks = 0; ks < KS; ++ks) {
+        const size_t base = ((size_t)(tcl * KS + ks) * 2) * 64 + lane;
+        bh[ks] = a.mfrag[base];
+        bl[ks] = a.mfrag[base + 64];
     }
+    const float* mtile = a.mt + (size_t)tcl * a.P * 32 + (lane & 31);
 
-    uint4 pre[KSMAX];
-    auto fetch = [&](int i) {
-        const int f0 = its[i].frag, nf = its[i].nfrag;
-        const uint4* src = a.frag + (size_t)f0 * 128;
+    double Y[16];
 #pragma unroll
-        for (int r = 0; r < KSMAX; ++r) {
-            const int idx = tid + 256 * r;
-            if (idx < nf * 128) pre[r] = src[idx];
-        }
-        return nf;
-    };
-    auto store = [&](int buf, int nf) {
+    for (int r = 0; r < 16; ++r) Y[r] = 0.0;
+
+    // raw stage-2 inputs of an iteration (loads only, consumed one iteration later)
+    auto prefetch_w = [&](const IterDesc& d, float (&mp)[SEG], float (&sc)[SEG]) {
 #pragma unroll
-        for (int r = 0; r < KSMAX; ++r) {
-            const int idx = tid + 256 * r;
-            if (idx < nf * 128) lds[buf * BUF + idx] = pre[r];
+        for (int s = 0; s < SEG; ++s) {
+            const int p = (s < d.nseg) ? d.p[s] : 0;
+            sc[s] = a.scale[d.scale + p];
+            mp[s] = mtile[(size_t)p * 32];
         }
     };
 
-    if (n_it > 0) store(0, fetch(0));
-    __syncthreads();
-
-    double Y[NT][16];
-#pragma unroll
-    for (int t = 0; t < NT; ++t)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) Y[t][r] = 0.0;
-
-    for (int i = 0; i < n_it; ++i) {
-        const IterDesc d = its[i];
-        const int buf = i & 1;
-        int nf_next = 0;
-        if (i + 1 < n_it) nf_next = fetch(i + 1);
-        const uint4* B = lds + buf * BUF;
+    // one iteration: compute d from rd while the fragments of dn stream into wr
+    auto body = [&](const IterDesc& d, const IterDesc& dn, const float (&mp)[SEG], const float (&sc)[SEG],
+                    float (&mpn)[SEG], float (&scn)[SEG], const uint4* rd, uint4* wr) {
+        dma_frags(a.frag + (size_t)dn.frag * 128, wr, dn.nfrag, wave, lane, kWaves);
+        prefetch_w(dn, mpn, scn);
         int f = 0;
 #pragma unroll
-        for (int seg = 0; seg < 2; ++seg) {
-            const int p = seg ? d.pb : d.pa;
-            const unsigned long long m = seg ? d.mb : d.ma;
-            if (p < 0 || m == 0) continue;
-            double wp[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const float mp = (tile0 + t < a.n_tiles) ? a.mt[((size_t)(tile0 + t) * a.P + p) * 32 + (lane & 31)] : 0.0f;
-                wp[t] = (double)mp * (d.delta ? th[t] : 1.0);
-            }
-            floatx16 Z[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) Z[t][r] = 0.0f;
-#pragma unroll
-            for (int ks = 0; ks < KSMAX; ++ks) {
-                if ((m >> ks) & 1ull) {
-                    uint4 uh = B[f * 128 + lane];
-                    uint4 ul = B[f * 128 + 64 + lane];
-                    ++f;
-                    const half8_t ah = *reinterpret_cast<half8_t*>(&uh);
-                    const half8_t al = *reinterpret_cast<half8_t*>(&ul);
-#pragma unroll
-                    for (int t = 0; t < NT; ++t) {
-                        Z[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bh[t][ks], Z[t], 0, 0, 0);
-                        Z[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ah, bl[t][ks], Z[t], 0, 0, 0);
-                        Z[t] = __builtin_amdgcn_mfma_f32_32x32x16_f16(al, bh[t][ks], Z[t], 0, 0, 0);
-                    }
-                }
-            }
-            const double sc = a.scale[d.scale + p];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const double w = wp[t] * sc;
-#pragma unroll
-                for (int r = 0; r < 16; ++r) Y[t][r] = fma(w, (double)Z[t][r], Y[t][r]);
-            }
+        for (int s = 0; s < SEG; ++s) {
+            if (s >= d.nseg) break;
+            MixedSeg<KS> seg{rd + f * 128 + lane, bh, bl,
+                             (double)mp[s] * (double)sc[s] * (d.delta ? th : 1.0), Y};
+            pick_lo<KS, 0>(d.lo[s], seg);
+            f += KS - d.lo[s];
         }
-        if (i + 1 < n_it) store(buf ^ 1, nf_next);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (i + 1 == n_it || its[i + 1].ob != d.ob) {
+        if (dn.ob != d.ob) {
+            if (tv && slot < a.n_slots) {
+                float* dst = a.Y + (size_t)slot * a.ystride + d.ob * 32 + 4 * (lane >> 5);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int slot = (tile0 + t) * 32 + (lane & 31);
-                if (tile0 + t < a.n_tiles && slot < a.n_slots) {
-                    float* dst = a.Y + (size_t)slot * a.ystride + d.ob * 32 + 4 * (lane >> 5);
-#pragma unroll
-                    for (int r4 = 0; r4 < 4; ++r4) {
-                        float4 v = make_float4((float)Y[t][4 * r4], (float)Y[t][4 * r4 + 1],
-                                               (float)Y[t][4 * r4 + 2], (float)Y[t][4 * r4 + 3]);
-                        *reinterpret_cast<float4*>(dst + 8 * r4) = v;
-                    }
+                for (int r4 = 0; r4 < 4; ++r4) {
+                    float4 v = make_float4((float)Y[4 * r4], (float)Y[4 * r4 + 1], (float)Y[4 * r4 + 2],
+                                           (float)Y[4 * r4 + 3]);
+                    *reinterpret_cast<float4*>(dst + 8 * r4) = v;
                 }
-#pragma unroll
-                for (int r = 0; r < 16; ++r) Y[t][r] = 0.0;
             }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) Y[r] = 0.0;
         }
+    };
+
+    IterDesc d0 = its[0];
+    float mp0[SEG], sc0[SEG], mp1[SEG], sc1[SEG];
+    dma_frags(a.frag + (size_t)d0.frag * 128, buf0, d0.nfrag, wave, lane, kWaves);
+    prefetch_w(d0, mp0, sc0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int i = 0; i < n_it; i += 2) {
+        const IterDesc d1 = its[i + 1];
+        body(d0, d1, mp0, sc0, mp1, sc1, buf0, buf1);
+        if (i + 1 >= n_it) break;
+        d0 = its[i + 2];
+        body(d1, d0, mp1, sc1, mp0, sc0, buf1, buf0);
     }
 }
 
 // ---------------------------------------------------------------------------
-// FP64: 16x16x4 MFMA, tiles of 16 slots, row blocks of 16, K steps of 4.
-// A lane l holds T[o = l%16][q = 4ks + l/16]; B lane l holds g[slot = l%16][q = 4ks + l/16];
+// FP64: 16x16x4 MFMA, tiles of 16 slots, row blocks of 16.  A fragment covers 16
+// rows and one 16-column K step as four 4-column sub-steps: lane l, sub-step j holds
+// T[o = l%16][q = 16ks + 4j + l/16] (2 KB).  B lane l holds g[slot = l%16][q = 4k + l/16];
 // D register r of lane l holds row 4r + l/16, column l%16.
-template <int KSMAX, int NT>
-__global__ __launch_bounds__(256) void k_contract_fp64(F64Args a)
+template <int KS>
+struct F64Seg {
+    const double* A;                 // first fragment of the segment in LDS, + lane
+    const double* b;                 // [4 KS]
+    double w;
+    doublex4* Y;
+    template <int LO>
+    __device__ __forceinline__ void run()
+    {
+        doublex4 Z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = LO; ks < KS; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                Z = __builtin_amdgcn_mfma_f64_16x16x4f64(A[((ks - LO) * 4 + j) * 64], b[ks * 4 + j], Z, 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) (*Y)[r] = fma(w, Z[r], (*Y)[r]);
+    }
+};
+
+template <int KS>
+__global__ __launch_bounds__(64 * kWaves) void k_contract_fp64(F64Args a)
 {
-    extern __shared__ uint4 lds4[];
-    double* lds = reinterpret_cast<double*>(lds4);
+    constexpr int SEG = (KS <= 8) ? 4 : 2;
+    constexpr int BUF = SEG * KS * 128;   // uint4 per buffer
+    __shared__ uint4 buf0[BUF];
+    __shared__ uint4 buf1[BUF];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int tile0 = (blockIdx.x * 4 + wave) * NT;
-    constexpr int BUF = 2 * KSMAX * 64;                                 // doubles per buffer
-    constexpr int PRE = (2 * KSMAX * 64 + 2 * 256 - 1) / (2 * 256);     // double2 per thread
-    const int level = a.slot_level ? a.slot_level[blockIdx.x * 4 * NT * 16] : 0;
+    const int wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int tile = wg * kWaves + wave;
+    const int level = a.slot_level ? a.slot_level[wg * kWaves * 16] : 0;
     const IterDesc* its = a.iters + a.iter_off[level];
     const int n_it = a.iter_cnt[level];
 
-    double b[NT][KSMAX];
-    double th[NT];
-    int cell[NT];
+    const int slot = tile * 16 + (lane & 15);
+    int cell = -1;
+    if (tile < a.n_tiles && slot < a.n_slots) cell = a.perm ? a.perm[slot] : slot;
+    const int ccl = cell >= 0 ? cell : 0;
+    const double th = (cell >= 0 && a.theta) ? a.theta[slot] : 0.0;
+    double b[4 * KS];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int slot = (tile0 + t) * 16 + (lane & 15);
-        int c = -1;
-        if (tile0 + t < a.n_tiles && slot < a.n_slots) c = a.perm ? a.perm[slot] : slot;
-        cell[t] = c;
-        th[t] = (c >= 0 && a.theta) ? a.theta[slot] : 0.0;
-#pragma unroll
-        for (int ks = 0; ks < KSMAX; ++ks) {
-            const int q = ks * 4 + (lane >> 4);
-            b[t][ks] = (c >= 0 && q < a.P) ? a.g[(size_t)c * a.P + q] : 0.0;
-        }
+    for (int k4 = 0; k4 < 4 * KS; ++k4) {
+        const int q = k4 * 4 + (lane >> 4);
+        b[k4] = (cell >= 0 && q < a.P) ? a.g[(size_t)cell * a.P + q] : 0.0;
     }
+    const double* gcell = a.g + (size_t)ccl * a.P;
 
-    double2 pre[PRE];
-    auto fetch = [&](int i) {
-        const int f0 = its[i].frag, nf = its[i].nfrag;
-        const double2* src = reinterpret_cast<const double2*>(a.frag + (size_t)f0 * 64);
+    doublex4 Y = {0.0, 0.0, 0.0, 0.0};
+
+    auto prefetch_w = [&](const IterDesc& d, double (&gp)[SEG]) {
 #pragma unroll
-        for (int r = 0; r < PRE; ++r) {
-            const int idx = tid + 256 * r;
-            if (idx < nf * 32) pre[r] = src[idx];
-        }
-        return nf;
-    };
-    auto store = [&](int buf, int nf) {
-        double2* dst = reinterpret_cast<double2*>(lds + buf * BUF);
-#pragma unroll
-        for (int r = 0; r < PRE; ++r) {
-            const int idx = tid + 256 * r;
-            if (idx < nf * 32) dst[idx] = pre[r];
-        }
+        for (int s = 0; s < SEG; ++s) gp[s] = gcell[(s < d.nseg) ? d.p[s] : 0];
     };
 
-    if (n_it > 0) store(0, fetch(0));
-    __syncthreads();
-
-    doublex4 Y[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) Y[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-
-    for (int i = 0; i < n_it; ++i) {
-        const IterDesc d = its[i];
-        const int buf = i & 1;
-        int nf_next = 0;
-        if (i + 1 < n_it) nf_next = fetch(i + 1);
-        const double* B = lds + buf * BUF;
+    auto body = [&](const IterDesc& d, const IterDesc& dn, const double (&gp)[SEG], double (&gpn)[SEG],
+                    const uint4* rd, uint4* wr) {
+        dma_frags(a.frag + (size_t)dn.frag * 128, wr, dn.nfrag, wave, lane, kWaves);
+        prefetch_w(dn, gpn);
+        const double* rdd = reinterpret_cast<const double*>(rd);
         int f = 0;
 #pragma unroll
-        for (int seg = 0; seg < 2; ++seg) {
-            const int p = seg ? d.pb : d.pa;
-            const unsigned long long m = seg ? d.mb : d.ma;
-            if (p < 0 || m == 0) continue;
-            double gp[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                gp[t] = (cell[t] >= 0) ? a.g[(size_t)cell[t] * a.P + p] : 0.0;
-                if (d.delta) gp[t] *= th[t];
-            }
-            doublex4 Z[NT];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) Z[t] = doublex4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int ks = 0; ks < KSMAX; ++ks) {
-                if ((m >> ks) & 1ull) {
-                    const double av = B[f * 64 + lane];
-                    ++f;
-#pragma unroll
-                    for (int t = 0; t < NT; ++t)
-                        Z[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b[t][ks], Z[t], 0, 0, 0);
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Y[t][r] = fma(gp[t], Z[t][r], Y[t][r]);
+        for (int s = 0; s < SEG; ++s) {
+            if (s >= d.nseg) break;
+            F64Seg<KS> seg{rdd + f * 256 + lane, b, (cell >= 0) ? gp[s] * (d.delta ? th : 1.0) : 0.0, &Y};
+            pick_lo<KS, 0>(d.lo[s], seg);
+            f += KS - d.lo[s];
         }
-        if (i + 1 < n_it) store(buf ^ 1, nf_next);
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
-        if (i + 1 == n_it || its[i + 1].ob != d.ob) {
+        if (dn.ob != d.ob) {
+            if (cell >= 0) {
+                double* dst = a.Y + (size_t)slot * a.ystride + d.ob * 16 + (lane >> 4);
 #pragma unroll
-            for (int t = 0; t < NT; ++t) {
-                const int slot = (tile0 + t) * 16 + (lane & 15);
-                if (tile0 + t < a.n_tiles && slot < a.n_slots) {
-                    double* dst = a.Y + (size_t)slot * a.ystride + d.ob * 16 + (lane >> 4);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) dst[4 * r] = Y[t][r];
-                }
-                Y[t] = doublex4{0.0, 0.0, 0.0, 0.0};
+                for (int r = 0; r < 4; ++r) dst[4 * r] = Y[r];
             }
+            Y = doublex4{0.0, 0.0, 0.0, 0.0};
         }
+    };
+
+    IterDesc d0 = its[0];
+    double gp0[SEG], gp1[SEG];
+    dma_frags(a.frag + (size_t)d0.frag * 128, buf0, d0.nfrag, wave, lane, kWaves);
+    prefetch_w(d0, gp0);
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int i = 0; i < n_it; i += 2) {
+        const IterDesc d1 = its[i + 1];
+        body(d0, d1, gp0, gp1, buf0, buf1);
+        if (i + 1 >= n_it) break;
+        d0 = its[i + 2];
+        body(d1, d0, gp1, gp0, buf1, buf0);
     }
 }
 
 // ---------------------------------------------------------------------------
-template <int KSMAX, int NT>
-static int launch_mixed_t(const MixedArgs& a, hipStream_t s)
+int segs_per_iter(int KS) { return KS <= 8 ? 4 : 2; }
+int slots_per_wg(int rows) { return kWaves * (rows == 32 ? 32 : 16); }
+
+template <class Args, class Kern>
+static int launch_generic(Kern kern, const Args& a, hipStream_t s)
 {
-    const int blocks = cdiv(cdiv(a.n_tiles, NT), 4);
-    const size_t lds = size_t(2) * 2 * KSMAX * 128 * sizeof(uint4);
-    static bool attr = false;
-    if (!attr && lds > 65536) {
-        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_contract_mixed<KSMAX, NT>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-        attr = true;
-    }
+    const int blocks = cdiv(a.n_tiles, kWaves);
     if (blocks == 0) return GD_OK;
-    hipLaunchKernelGGL((k_contract_mixed<KSMAX, NT>), dim3(blocks), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(64 * kWaves), 0, s, a);
     HIP_TRY(hipGetLastError());
     return GD_OK;
 }
 
-// tile shapes: NT tiles of 32 cells per wave; 2 tiles while the K steps fit the registers
-int slots_per_wg_mixed(int KS) { return 4 * 32 * (KS <= 8 ? 2 : 1); }
-int slots_per_wg_fp64(int KS4) { return 4 * 16 * (KS4 <= 24 ? 2 : 1); }
+#define GD_KS_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12)
 
 int launch_contract_mixed(const MixedArgs& a, hipStream_t s)
 {
-    if (a.KS <= 2) return launch_mixed_t<2, 2>(a, s);
-    if (a.KS <= 4) return launch_mixed_t<4, 2>(a, s);
-    if (a.KS <= 6) return launch_mixed_t<6, 2>(a, s);
-    if (a.KS <= 8) return launch_mixed_t<8, 2>(a, s);
-    if (a.KS <= 12) return launch_mixed_t<12, 1>(a, s);
-    return fail(GD_EUNSUPPORTED, "P too large for the mixed contraction");
-}
-
-template <int KSMAX, int NT>
-static int launch_f64_t(const F64Args& a, hipStream_t s)
-{
-    const int blocks = cdiv(cdiv(a.n_tiles, NT), 4);
-    const size_t lds = size_t(2) * 2 * KSMAX * 64 * sizeof(double);
-    static bool attr = false;
-    if (!attr && lds > 65536) {
-        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_contract_fp64<KSMAX, NT>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-        attr = true;
+    switch (a.KS) {
+#define GD_CASE(K) case K: return launch_generic(&k_contract_mixed<K>, a, s);
+        GD_KS_CASES(GD_CASE)
+#undef GD_CASE
     }
-    if (blocks == 0) return GD_OK;
-    hipLaunchKernelGGL((k_contract_fp64<KSMAX, NT>), dim3(blocks), dim3(256), lds, s, a);
-    HIP_TRY(hipGetLastError());
-    return GD_OK;
+    return fail(GD_EUNSUPPORTED, "P too large for the mixed contraction");
 }
 
 int launch_contract_fp64(const F64Args& a, hipStream_t s)
 {
-    if (a.KS <= 8) return launch_f64_t<8, 2>(a, s);
-    if (a.KS <= 16) return launch_f64_t<16, 2>(a, s);
-    if (a.KS <= 24) return launch_f64_t<24, 2>(a, s);
-    if (a.KS <= 32) return launch_f64_t<32, 1>(a, s);
-    if (a.KS <= 48) return launch_f64_t<48, 1>(a, s);
+    switch (a.KS) {
+#define GD_CASE(K) case K: return launch_generic(&k_contract_fp64<K>, a, s);
+        GD_KS_CASES(GD_CASE)
+#undef GD_CASE
+    }
     return fail(GD_EUNSUPPORTED, "P too large for the FP64 contraction");
 }
 

@@ -26,23 +26,32 @@ int fail(int code, const std::string& msg);
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 // ------------------------------------------------------------------ schedules
-// One iteration of the contraction: a row block ob and up to two p values (p and
-// P-1-p, so that iterations carry similar K work).  Bit ks of ma/mb says that the
-// fragment (ob, p, K step ks) is stored; absent fragments are structural zeros.
+// One iteration of the contraction: a row block ob and up to kSegMax p values of
+// one part (a level, or the difference of two neighbouring levels).  Segment s
+// covers the K steps lo[s]..KS-1 (16 columns q each) of p[s] (hi[s] = KS-1); zero
+// blocks inside the range are stored as zero fragments, blocks before lo are
+// structural zeros.
+// Fragments of an iteration are contiguous, segment by segment, K step ascending.
+// Every level's list ends with one empty descriptor (nseg = 0, ob = -1) so that the
+// kernels can always read the next descriptor.
+constexpr int kSegMax = 4;
 struct IterDesc {
     int ob;
-    int pa, pb;          // pb < 0: single segment
-    int frag;            // first fragment of the iteration (absolute index)
-    int nfrag;           // fragments of the iteration
-    int scale;           // offset of (part, ob) in the stage-2 scale table (mixed path)
     int delta;           // 1: level-difference part, weighted by the cell's blend factor
-    int pad;
-    unsigned long long ma, mb;
+    int scale;           // offset of (part, ob) in the stage-2 scale table (split path)
+    int frag;            // first fragment of the iteration (absolute index)
+    int nfrag;
+    int nseg;
+    int pad0, pad1;
+    int p[kSegMax];
+    int lo[kSegMax];
+    int hi[kSegMax];
+    int pad2[kSegMax];
 };
 
 // Device layouts of one tensor for one contraction precision.
 struct Schedule {
-    const void* frag = nullptr;           // mixed: uint4 (hi 64 lanes, then lo); fp64: double (64 lanes)
+    const void* frag = nullptr;           // 2 KB fragments: split (hi 64 lanes, lo 64 lanes) or FP64 (4 K steps)
     const IterDesc* iters = nullptr;      // all levels, concatenated
     const int* iter_off = nullptr;        // [levels] first iteration of the level
     const int* iter_cnt = nullptr;        // [levels] iterations of the level
@@ -81,7 +90,7 @@ struct MixedArgs {
 };
 
 struct F64Args {
-    const double* frag;
+    const uint4* frag;
     const IterDesc* iters;
     const int* iter_off;
     const int* iter_cnt;
@@ -117,8 +126,10 @@ int launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
 int launch_project(const double* samples, const double* wP, double* coef, int C, int N, int k, hipStream_t s);
 int launch_contract_mixed(const MixedArgs& a, hipStream_t s);
 int launch_contract_fp64(const F64Args& a, hipStream_t s);
-// cells per workgroup of the contraction for a given K-step count (tiles are padded to it)
-int slots_per_wg_mixed(int KS);
-int slots_per_wg_fp64(int KS4);
+// p segments per iteration used by the contraction kernels for a given count of
+// 16-column K steps; the schedules are built with the same number
+int segs_per_iter(int KS);
+// cells per contraction workgroup (row blocks of 32: split path; 16: FP64 path)
+int slots_per_wg(int rows);
 
 } // namespace gd

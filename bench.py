@@ -179,6 +179,13 @@ def main():
 
     mixed = res["mixed"]
     cell_evals = 3.0 * C / (mixed["ms_per_step"] * 1e-3)
+    # executed MFMA work of one launch: every stored fragment (32 rows x 16 K) of the
+    # levels in use, 3 products, for every 32-cell tile of the bracket using it
+    # (bracket sizes from the plan's slot count, fragments averaged over levels)
+    st = mixed["stats"]
+    n_levels = max(1, info["n_levels"])
+    frags_per_level = st["frags_mixed"] / n_levels
+    exec_flops = frags_per_level * 3 * (2 * 32 * 32 * 16) * (st["n_slots"] / 32)
     flops_launch = info["flops_per_eval"] * C
     achieved = flops_launch / (mixed["kernel_ms"] * 1e-3) / 1e12
     out = {
@@ -200,7 +207,9 @@ def main():
                      "frac": achieved / PEAK_F16_TFLOPS, "traffic": None,
                      "kernel": "k_contract_mixed", "kernel_ms": mixed["kernel_ms"],
                      "algorithmic_flops_per_launch": flops_launch,
-                     "flops_per_cell_eval": info["flops_per_eval"]},
+                     "flops_per_cell_eval": info["flops_per_eval"],
+                     "executed_mfma_tflops": exec_flops / (mixed["kernel_ms"] * 1e-3) / 1e12,
+                     "mfma_utilisation": exec_flops / (mixed["kernel_ms"] * 1e-3) / 1e12 / PEAK_F16_TFLOPS},
         "tensor_init_s": t_init,
         "mass_drift_mixed": mixed["mass_drift"],
         "accuracy_vs_fp64_gpu": acc,

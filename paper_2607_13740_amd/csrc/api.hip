@@ -103,7 +103,7 @@ static inline int pow2_exp(double v)
 // Generic schedule builder: row blocks of RB rows, K steps of KW columns, up to SEG
 // p segments per iteration.  emit(r, delta, ob, p, ks) appends one fragment;
 // blockscale(r, delta, ob) returns the offset of the stage-2 scale table of that
-// (part, ob) (or 0).  Every level ends with an empty sentinel descriptor (ob = -1).
+// (part, ob) (or 0).  Every level ends with two empty sentinel descriptors (ob = -1).
 template <class Emit, class BlockScale>
 static void build_schedule(const gd_tensor* t, int RB, int KW, int SEG, std::vector<IterDesc>& iters,
                            std::vector<int>& off, std::vector<int>& cnt, Emit emit, BlockScale blockscale)
@@ -178,6 +178,7 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, int SEG, std::vec
         IterDesc sentinel{};
         sentinel.ob = -1;
         sentinel.frag = nfrag;
+        iters.push_back(sentinel);
         iters.push_back(sentinel);
     }
 }
@@ -534,35 +535,50 @@ extern "C" int gd_plan_sizes(const gd_plan* pl, long long* n_cells, long long* n
 
 extern "C" void gd_plan_destroy(gd_plan* pl) { delete pl; }
 
-// one right-hand-side evaluation of group G on stage state gs (group-local pointers)
-static int eval_group(gd_plan* pl, Group& G, double* gs, int limit, const double* kscale, int mode,
-                      const double* gn, double* out, double dt, double* raw)
+static StageArgs stage_args(const gd_plan* pl, const Group& G, int mode, int limit, const double* kscale,
+                            const double* gn, const double* gs, double* out, double dt, double* raw)
 {
     const gd_tensor* t = G.t;
-    if (G.C == 0) return GD_OK;
-    hipStream_t s = pl->stream;
     const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
+    StageArgs a{};
+    a.mode = mode;
+    a.limit = limit;
+    a.split = mixed ? 1 : 0;
+    a.Yf = mixed ? G.Yf : nullptr;
+    a.Yd = mixed ? nullptr : G.Yd;
+    a.rowscale = t->rowscale;
+    a.eslot = G.eslot;
+    a.perm = G.perm;
+    a.kscale = kscale ? kscale + G.cell0 : nullptr;
+    a.gn = gn;
+    a.gs = gs;
+    a.out = out;
+    a.raw = raw;
+    a.h = t->h;
+    a.colscale = t->colscale;
+    a.mfrag = G.mfrag;
+    a.mt = G.mt;
+    a.viol = pl->viol;
+    a.dt = dt;
+    a.n_slots = G.n_slots;
+    a.n_tiles = G.tiles32;
+    a.N = t->N;
+    a.k = t->k;
+    a.P = t->P;
+    a.KS = t->KS;
+    a.n_out = t->n_out;
+    a.ystride = G.ystride;
+    a.conservative = t->spec.conservative;
+    return a;
+}
+
+// the contraction of group G on stage state gs (the split path reads the fragments
+// the previous stage kernel wrote from gs)
+static int contract_group(gd_plan* pl, Group& G, const double* gs)
+{
+    const gd_tensor* t = G.t;
+    hipStream_t s = pl->stream;
     int rc;
-    if (limit || mixed) {
-        PrologueArgs pa{};
-        pa.g = gs;
-        pa.perm = G.perm;
-        pa.n_slots = G.n_slots;
-        pa.n_tiles = G.tiles32;
-        pa.N = t->N;
-        pa.k = t->k;
-        pa.P = t->P;
-        pa.KS = t->KS;
-        pa.limit = limit;
-        pa.mixed = mixed ? 1 : 0;
-        pa.h = t->h;
-        pa.colscale = t->colscale;
-        pa.mfrag = G.mfrag;
-        pa.mt = G.mt;
-        pa.eslot = G.eslot;
-        pa.viol = pl->viol;
-        if ((rc = launch_prologue(pa, s))) return rc;
-    }
     hipEvent_t ev_end = nullptr;
     if (pl->timing) {
         KernelTimer& T = pl->timer;
@@ -576,7 +592,7 @@ static int eval_group(gd_plan* pl, Group& G, double* gs, int limit, const double
         ev_end = T.ev[T.used].second;
         ++T.used;
     }
-    if (mixed) {
+    if (pl->prec == GD_PREC_MIXED_F16X3) {
         MixedArgs ma{};
         ma.frag = static_cast<const uint4*>(t->mixed.frag);
         ma.iters = t->mixed.iters;
@@ -613,40 +629,28 @@ static int eval_group(gd_plan* pl, Group& G, double* gs, int limit, const double
         if ((rc = launch_contract_fp64(fa, s))) return rc;
     }
     if (ev_end) HIP_TRY(hipEventRecord(ev_end, s));
-    EpilogueArgs ea{};
-    ea.Yf = mixed ? G.Yf : nullptr;
-    ea.Yd = mixed ? nullptr : G.Yd;
-    ea.rowscale = t->rowscale;
-    ea.eslot = G.eslot;
-    ea.perm = G.perm;
-    ea.kscale = kscale ? kscale + G.cell0 : nullptr;
-    ea.gn = gn;
-    ea.gs = gs;
-    ea.out = out;
-    ea.raw = raw;
-    ea.h = t->h;
-    ea.dt = dt;
-    ea.n_slots = G.n_slots;
-    ea.N = t->N;
-    ea.k = t->k;
-    ea.P = t->P;
-    ea.n_out = t->n_out;
-    ea.ystride = G.ystride;
-    ea.conservative = t->spec.conservative;
-    ea.mode = mode;
-    return launch_epilogue(ea, s);
+    return GD_OK;
 }
 
 extern "C" int gd_collision_rhs(gd_plan* pl, const double* g, const double* kscale, double* rhs, double* raw)
 {
     if (!pl || !g || !rhs) return fail(GD_EINVAL, "null argument");
     long long rawoff = 0;
+    int rc;
     for (Group& G : pl->groups) {
-        // without limiting, the prologue only reads the state
-        double* gs = const_cast<double*>(g) + G.val0;
-        int rc = eval_group(pl, G, gs, 0, kscale, 0, nullptr, rhs + G.val0, 0.0, raw ? raw + rawoff : nullptr);
-        if (rc) return rc;
+        const long long off = rawoff;
         rawoff += (long long)G.C * G.t->n_out;
+        if (G.C == 0) continue;
+        const double* gs = g + G.val0;
+        if (pl->prec == GD_PREC_MIXED_F16X3) {
+            // split of the input state (no limiting: the state is read only)
+            StageArgs a = stage_args(pl, G, -1, 0, kscale, nullptr, gs, nullptr, 0.0, nullptr);
+            if ((rc = launch_stage(a, pl->stream))) return rc;
+        }
+        if ((rc = contract_group(pl, G, gs))) return rc;
+        StageArgs b = stage_args(pl, G, 0, 0, kscale, nullptr, gs, rhs + G.val0, 0.0, raw ? raw + off : nullptr);
+        b.split = 0;
+        if ((rc = launch_stage(b, pl->stream))) return rc;
     }
     return GD_OK;
 }
@@ -656,23 +660,34 @@ extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double d
 {
     if (!pl || !g || n_steps < 0) return fail(GD_EINVAL, "bad argument");
     int rc;
-    if ((rc = launch_fill_u64(pl->viol, 1, pl->stream))) return rc;
+    hipStream_t s = pl->stream;
+    if ((rc = launch_fill_u64(pl->viol, 1, s))) return rc;
+    // limiter on the start state (and its split for the first contraction)
+    for (Group& G : pl->groups) {
+        if (G.C == 0) continue;
+        StageArgs a = stage_args(pl, G, -1, 1, kscale, nullptr, g + G.val0, nullptr, dt, nullptr);
+        if ((rc = launch_stage(a, s))) return rc;
+    }
     for (int n = 0; n < n_steps; ++n) {
         for (Group& G : pl->groups) {
+            if (G.C == 0) continue;
             double* gn = g + G.val0;
             double* y1 = pl->y1 + G.val0;
             double* y2 = pl->y2 + G.val0;
-            if ((rc = eval_group(pl, G, gn, 1, kscale, 1, gn, y1, dt, nullptr))) return rc;
-            if ((rc = eval_group(pl, G, y1, 1, kscale, 2, gn, y2, dt, nullptr))) return rc;
-            if ((rc = eval_group(pl, G, y2, 1, kscale, 3, gn, gn, dt, nullptr))) return rc;
+            // y1 = gn + dt L(gn); y2 = 3/4 gn + 1/4 (y1 + dt L(y1)); gn = 1/3 gn + 2/3 (y2 + dt L(y2)),
+            // each stage limited (and split for the next contraction) as it is written
+            if ((rc = contract_group(pl, G, gn))) return rc;
+            if ((rc = launch_stage(stage_args(pl, G, 1, 1, kscale, gn, gn, y1, dt, nullptr), s))) return rc;
+            if ((rc = contract_group(pl, G, y1))) return rc;
+            if ((rc = launch_stage(stage_args(pl, G, 2, 1, kscale, gn, y1, y2, dt, nullptr), s))) return rc;
+            if ((rc = contract_group(pl, G, y2))) return rc;
+            if ((rc = launch_stage(stage_args(pl, G, 3, 1, kscale, gn, y2, gn, dt, nullptr), s))) return rc;
         }
     }
-    for (Group& G : pl->groups)
-        if ((rc = launch_limit(g + G.val0, G.C, G.t->N, G.t->k, G.t->P, pl->viol, pl->stream))) return rc;
     if (violations) {
         unsigned long long v = 0;
-        HIP_TRY(hipMemcpyAsync(&v, pl->viol, sizeof(v), hipMemcpyDeviceToHost, pl->stream));
-        HIP_TRY(hipStreamSynchronize(pl->stream));
+        HIP_TRY(hipMemcpyAsync(&v, pl->viol, sizeof(v), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
         *violations = (long long)v;
     }
     return GD_OK;

@@ -159,18 +159,21 @@ __global__ __launch_bounds__(64 * kWaves) void k_contract_mixed(MixedArgs a)
         }
     };
 
-    IterDesc d0 = its[0];
+    // descriptors are loaded two iterations ahead (each level ends with two sentinels)
+    IterDesc dA = its[0], dB = its[1];
     float mp0[SEG], sc0[SEG], mp1[SEG], sc1[SEG];
-    dma_frags(a.frag + (size_t)d0.frag * 128, buf0, d0.nfrag, wave, lane, kWaves);
-    prefetch_w(d0, mp0, sc0);
+    dma_frags(a.frag + (size_t)dA.frag * 128, buf0, dA.nfrag, wave, lane, kWaves);
+    prefetch_w(dA, mp0, sc0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int i = 0; i < n_it; i += 2) {
-        const IterDesc d1 = its[i + 1];
-        body(d0, d1, mp0, sc0, mp1, sc1, buf0, buf1);
+        const IterDesc dC = its[i + 2];
+        body(dA, dB, mp0, sc0, mp1, sc1, buf0, buf1);
         if (i + 1 >= n_it) break;
-        d0 = its[i + 2];
-        body(d1, d0, mp1, sc1, mp0, sc0, buf1, buf0);
+        const IterDesc dD = its[i + 3];
+        body(dB, dC, mp1, sc1, mp0, sc0, buf1, buf0);
+        dA = dC;
+        dB = dD;
     }
 }
 
@@ -258,18 +261,20 @@ __global__ __launch_bounds__(64 * kWaves) void k_contract_fp64(F64Args a)
         }
     };
 
-    IterDesc d0 = its[0];
+    IterDesc dA = its[0], dB = its[1];
     double gp0[SEG], gp1[SEG];
-    dma_frags(a.frag + (size_t)d0.frag * 128, buf0, d0.nfrag, wave, lane, kWaves);
-    prefetch_w(d0, gp0);
+    dma_frags(a.frag + (size_t)dA.frag * 128, buf0, dA.nfrag, wave, lane, kWaves);
+    prefetch_w(dA, gp0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int i = 0; i < n_it; i += 2) {
-        const IterDesc d1 = its[i + 1];
-        body(d0, d1, gp0, gp1, buf0, buf1);
+        const IterDesc dC = its[i + 2];
+        body(dA, dB, gp0, gp1, buf0, buf1);
         if (i + 1 >= n_it) break;
-        d0 = its[i + 2];
-        body(d1, d0, gp1, gp0, buf1, buf0);
+        const IterDesc dD = its[i + 3];
+        body(dB, dC, gp1, gp0, buf1, buf0);
+        dA = dC;
+        dB = dD;
     }
 }
 

@@ -32,8 +32,8 @@ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 // blocks inside the range are stored as zero fragments, blocks before lo are
 // structural zeros.
 // Fragments of an iteration are contiguous, segment by segment, K step ascending.
-// Every level's list ends with one empty descriptor (nseg = 0, ob = -1) so that the
-// kernels can always read the next descriptor.
+// Every level's list ends with two empty descriptors (nseg = 0, ob = -1) so that the
+// kernels can always read the descriptors two iterations ahead.
 constexpr int kSegMax = 4;
 struct IterDesc {
     int ob;
@@ -61,20 +61,6 @@ struct Schedule {
 };
 
 // ------------------------------------------------------------------ kernel arguments
-struct PrologueArgs {
-    double* g;                 // caller state (cell order)
-    const int* perm;           // slot -> cell (nullptr: identity)
-    int n_slots, n_tiles, N, k, P, KS;
-    int limit;                 // apply the limiter in place
-    int mixed;                 // write split fragments
-    const double* h;           // [N]
-    const double* colscale;    // [P]
-    uint4* mfrag;
-    float* mt;
-    int* eslot;                // [n_slots] per-slot exponent
-    unsigned long long* viol;
-};
-
 struct MixedArgs {
     const uint4* frag;
     const IterDesc* iters;
@@ -102,26 +88,36 @@ struct F64Args {
     int KS, n_tiles, n_slots, P, ystride;
 };
 
-struct EpilogueArgs {
-    const float* Yf;           // mixed raw (scaled)  or nullptr
-    const double* Yd;          // fp64 raw            or nullptr
-    const double* rowscale;    // mixed: [n_out rows]
-    const int* eslot;          // mixed: [n_slots]
+// One kernel per RK stage boundary, one workgroup per tile of 32 slots:
+//  1. (mode >= 0) fluxes from the raw vector Y, L (Eq. evo) and, for modes 1-3, the
+//     SSP-RK3 stage combination (Eq. RK3); mode -1 takes the state gs as it is;
+//  2. (limit) the scaling limiter on the new state, written back;
+//  3. (split) the per-slot scale and the split FP16 B operands / FP32 weights of the
+//     new state for the next contraction.
+struct StageArgs {
+    int mode;                  // -1 none, 0: out = L, 1..3: RK stage into out
+    int limit, split;
+    const float* Yf;           // split path raw vector (scaled)   or nullptr
+    const double* Yd;          // FP64 raw vector                 or nullptr
+    const double* rowscale;
+    int* eslot;                // per-slot exponent: read for Y, then rewritten by the split
     const int* perm;
     const double* kscale;      // [cells] or nullptr
     const double* gn;          // RK base state (cell order)
     const double* gs;          // stage input state
-    double* out;
+    double* out;               // new state (or L); mode -1 with limit: gs itself
     double* raw;               // optional FP64 raw output [cells][n_out]
     const double* h;
+    const double* colscale;
+    uint4* mfrag;
+    float* mt;
+    unsigned long long* viol;
     double dt;
-    int n_slots, N, k, P, n_out, ystride, conservative, mode;
+    int n_slots, n_tiles, N, k, P, KS, n_out, ystride, conservative;
 };
 
 // ------------------------------------------------------------------ launchers
-int launch_prologue(const PrologueArgs& a, hipStream_t s);
-int launch_epilogue(const EpilogueArgs& a, hipStream_t s);
-int launch_limit(double* g, int C, int N, int k, int P, unsigned long long* viol, hipStream_t s);
+int launch_stage(const StageArgs& a, hipStream_t s);
 int launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
 int launch_project(const double* samples, const double* wP, double* coef, int C, int N, int k, hipStream_t s);
 int launch_contract_mixed(const MixedArgs& a, hipStream_t s);

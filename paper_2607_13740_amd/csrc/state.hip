@@ -1,7 +1,8 @@
-// Per-cell and per-bin kernels around the contraction: the scaling limiter
-// (Sec. 3.2, Eqs. recon/gamma), the split of the scaled state into FP16 halves,
-// the assembly of the DG right-hand side (Sec. 3.1, Eq. evo), the SSP-RK3 stage
-// combination (Eq. RK3) and the projection of initial profiles (Eq. init).
+// Per-cell and per-bin kernels around the contraction: the assembly of the DG
+// right-hand side (Sec. 3.1, Eq. evo), the SSP-RK3 stage combination (Eq. RK3), the
+// scaling limiter (Sec. 3.2, Eqs. recon/gamma), the split of the scaled state into
+// FP16 halves for the next contraction, and the projection of initial profiles
+// (Eq. init).
 #include "gd_internal.h"
 
 namespace gd {
@@ -64,129 +65,6 @@ __device__ __forceinline__ int limit_bin(int k, double* c)
     return viol;
 }
 
-// ---------------------------------------------------------------------------
-// One thread per slot: limiter in place (optional) and, for the split path, the
-// per-slot power-of-two scale e with max_q |h_j g_q c_q| 2^-e in [64, 128), the
-// hi/lo FP16 B-operand fragments and the FP32 stage-2 weights.
-//   mfrag[((tile*KS + ks)*2 + {0 hi, 1 lo})*64 + 32 hh + slot%32] : q = 16 ks + 8 hh + j
-//   mt[(tile*P + p)*32 + slot%32]
-__global__ __launch_bounds__(256) void k_prologue(PrologueArgs a)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nslot_pad = a.mixed ? a.n_tiles * 32 : a.n_slots;
-    if (s >= nslot_pad) return;
-    const int K1 = a.k + 1;
-    int cell = -1;
-    if (s < a.n_slots) cell = a.perm ? a.perm[s] : s;
-    const bool live = cell >= 0;
-    double* gc = a.g + (size_t)(live ? cell : 0) * a.P;
-    if (live && a.limit) {
-        int v = 0;
-        for (int j = 0; j < a.N; ++j) {
-            double cc[4] = {0.0, 0.0, 0.0, 0.0};
-            for (int i = 0; i < K1; ++i) cc[i] = gc[j * K1 + i];
-            v += limit_bin(a.k, cc);
-            for (int i = 1; i < K1; ++i) gc[j * K1 + i] = cc[i];
-        }
-        if (v) atomicAdd(a.viol, (unsigned long long)v);
-    }
-    if (!a.mixed) return;
-    double mx = 0.0;
-    if (live)
-        for (int p = 0; p < a.P; ++p) mx = fmax(mx, fabs(a.h[p / K1] * gc[p] * a.colscale[p]));
-    int e = 0;
-    if (mx > 0.0) {
-        int E;
-        frexp(mx, &E);
-        e = E - 7;
-    }
-    if (s < a.n_slots) a.eslot[s] = e;
-    const int tile = s >> 5, sl = s & 31;
-    for (int ks = 0; ks < a.KS; ++ks)
-        for (int hh = 0; hh < 2; ++hh) {
-            half8_t hi, lo;
-            for (int j = 0; j < 8; ++j) {
-                const int q = ks * 16 + hh * 8 + j;
-                float m = 0.0f;
-                if (live && q < a.P) m = (float)ldexp(a.h[q / K1] * gc[q] * a.colscale[q], -e);
-                const _Float16 mh = (_Float16)m;
-                hi[j] = mh;
-                lo[j] = (_Float16)(m - (float)mh);
-            }
-            const size_t base = ((size_t)(tile * a.KS + ks) * 2) * 64 + hh * 32 + sl;
-            a.mfrag[base] = *reinterpret_cast<uint4*>(&hi);
-            a.mfrag[base + 64] = *reinterpret_cast<uint4*>(&lo);
-        }
-    for (int p = 0; p < a.P; ++p) {
-        float m = 0.0f;
-        if (live) m = (float)ldexp(a.h[p / K1] * gc[p] * a.colscale[p], -e);
-        a.mt[((size_t)tile * a.P + p) * 32 + sl] = m;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// One thread per (slot, bin): fluxes in FP64 and the right-hand side
-//   L_{j,i} = (2i+1)/h_j (V_{j,i} - F_{j+1} + (-1)^i F_j)         (Eq. evo, P_i(+-1) = (+-1)^i)
-// with F_0 = 0, F_N = 0 (conservative) or row N-1, F_j = row j-1 otherwise.
-//   mode 0: out = L                     mode 1: out = gs + dt L
-//   mode 2: out = 0.75 gn + 0.25 (gs + dt L)      mode 3: out = gn/3 + 2/3 (gs + dt L)
-__global__ __launch_bounds__(256) void k_epilogue(EpilogueArgs a)
-{
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (long long)a.n_slots * a.N) return;
-    const int s = (int)(t / a.N), j = (int)(t - (long long)s * a.N);
-    const int c = a.perm ? a.perm[s] : s;
-    if (c < 0) return;
-    const int K1 = a.k + 1;
-    double fac = a.kscale ? a.kscale[c] : 1.0;
-    if (a.Yf) fac = ldexp(fac, 2 * a.eslot[s]);
-    auto row = [&](int o) -> double {
-        if (a.Yf) return (double)a.Yf[(size_t)s * a.ystride + o] * a.rowscale[o] * fac;
-        return a.Yd[(size_t)s * a.ystride + o] * fac;
-    };
-    const double Fl = (j == 0) ? 0.0 : row(j - 1);
-    double Fr;
-    if (j + 1 < a.N) Fr = row(j);
-    else Fr = a.conservative ? 0.0 : row(a.N - 1);
-    const int vbase = (a.N - 1) + (a.conservative ? 0 : 1);
-    const double hj = a.h[j];
-    const size_t base = (size_t)c * a.P + j * K1;
-    if (a.raw) {
-        double* rw = a.raw + (size_t)c * a.n_out;
-        if (j >= 1) rw[j - 1] = Fl;
-        if (j == a.N - 1 && !a.conservative) rw[a.N - 1] = Fr;
-    }
-    for (int i = 0; i <= a.k; ++i) {
-        const double V = (i == 0) ? 0.0 : row(vbase + j * a.k + i - 1);
-        if (a.raw && i > 0) a.raw[(size_t)c * a.n_out + vbase + j * a.k + i - 1] = V;
-        const double sgn = (i & 1) ? -1.0 : 1.0;
-        const double L = (2.0 * i + 1.0) / hj * (V - Fr + sgn * Fl);
-        double o;
-        switch (a.mode) {
-        case 0: o = L; break;
-        case 1: o = a.gs[base + i] + a.dt * L; break;
-        case 2: o = 0.75 * a.gn[base + i] + 0.25 * (a.gs[base + i] + a.dt * L); break;
-        default: o = a.gn[base + i] / 3.0 + 2.0 / 3.0 * (a.gs[base + i] + a.dt * L); break;
-        }
-        a.out[base + i] = o;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_limit(double* g, int C, int N, int k, int P, unsigned long long* viol)
-{
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    double* gc = g + (size_t)c * P;
-    int v = 0;
-    for (int j = 0; j < N; ++j) {
-        double cc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int i = 0; i <= k; ++i) cc[i] = gc[j * (k + 1) + i];
-        v += limit_bin(k, cc);
-        for (int i = 1; i <= k; ++i) gc[j * (k + 1) + i] = cc[i];
-    }
-    if (v) atomicAdd(viol, (unsigned long long)v);
-}
-
 __global__ void k_fill_u64(unsigned long long* p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -209,32 +87,117 @@ __global__ __launch_bounds__(256) void k_project(const double* samples, const do
 }
 
 // ---------------------------------------------------------------------------
-int launch_prologue(const PrologueArgs& a, hipStream_t s)
+// Fused stage kernel (see StageArgs), 256 threads per tile of 32 slots.  The new
+// state of the tile is staged in LDS (rows padded to P+1 doubles against bank
+// conflicts) so that the split fragments and weights are written coalesced.
+constexpr int kStageMaxP = 192;
+
+__global__ __launch_bounds__(256) void k_stage(StageArgs a)
 {
-    const int n = a.mixed ? a.n_tiles * 32 : a.n_slots;
-    if (n == 0) return GD_OK;
-    hipLaunchKernelGGL(k_prologue, dim3(cdiv(n, 256)), dim3(256), 0, s, a);
+    __shared__ double st[32 * (kStageMaxP + 1)];
+    __shared__ int sexp[32];
+    const int tile = blockIdx.x, tid = threadIdx.x;
+    const int K1 = a.k + 1, P = a.P, LD = P + 1;
+
+    // ---- phase 1: one task per (slot, bin)
+    int viol = 0;
+    for (int t = tid; t < 32 * a.N; t += 256) {
+        const int sl = t / a.N, j = t - sl * a.N;
+        const int s = tile * 32 + sl;
+        const int c = (s < a.n_slots) ? (a.perm ? a.perm[s] : s) : -1;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        if (c >= 0) {
+            const size_t base = (size_t)c * P + j * K1;
+            if (a.mode < 0) {
+                for (int i = 0; i < K1; ++i) v[i] = a.gs[base + i];
+            } else {
+                double fac = a.kscale ? a.kscale[c] : 1.0;
+                if (a.Yf) fac = ldexp(fac, 2 * a.eslot[s]);
+                auto row = [&](int o) -> double {
+                    if (a.Yf) return (double)a.Yf[(size_t)s * a.ystride + o] * a.rowscale[o] * fac;
+                    return a.Yd[(size_t)s * a.ystride + o] * fac;
+                };
+                const double Fl = (j == 0) ? 0.0 : row(j - 1);
+                const double Fr = (j + 1 < a.N) ? row(j) : (a.conservative ? 0.0 : row(a.N - 1));
+                const int vbase = (a.N - 1) + (a.conservative ? 0 : 1);
+                const double hj = a.h[j];
+                if (a.raw) {
+                    double* rw = a.raw + (size_t)c * a.n_out;
+                    if (j >= 1) rw[j - 1] = Fl;
+                    if (j == a.N - 1 && !a.conservative) rw[a.N - 1] = Fr;
+                }
+                for (int i = 0; i < K1; ++i) {
+                    const double V = (i == 0) ? 0.0 : row(vbase + j * a.k + i - 1);
+                    if (a.raw && i > 0) a.raw[(size_t)c * a.n_out + vbase + j * a.k + i - 1] = V;
+                    const double sgn = (i & 1) ? -1.0 : 1.0;
+                    const double L = (2.0 * i + 1.0) / hj * (V - Fr + sgn * Fl);
+                    switch (a.mode) {
+                    case 0: v[i] = L; break;
+                    case 1: v[i] = a.gs[base + i] + a.dt * L; break;
+                    case 2: v[i] = 0.75 * a.gn[base + i] + 0.25 * (a.gs[base + i] + a.dt * L); break;
+                    default: v[i] = a.gn[base + i] / 3.0 + 2.0 / 3.0 * (a.gs[base + i] + a.dt * L); break;
+                    }
+                }
+            }
+            if (a.limit) viol += limit_bin(a.k, v);
+            if (a.mode >= 0 || a.limit) {
+                double* o = (a.mode >= 0) ? a.out : const_cast<double*>(a.gs);
+                for (int i = 0; i < K1; ++i) o[base + i] = v[i];
+            }
+        }
+        if (a.split)
+            for (int i = 0; i < K1; ++i) st[sl * LD + j * K1 + i] = v[i];
+    }
+    if (viol) atomicAdd(a.viol, (unsigned long long)viol);
+    if (!a.split) return;
+    __syncthreads();
+    // ---- phase 2: per-slot exponent, then coalesced fragments and weights
+    if (tid < 32) {
+        // per-slot scale: max_q |h_j g_q c_q| 2^-e in [64, 128)
+        double mx = 0.0;
+        for (int q = 0; q < P; ++q) mx = fmax(mx, fabs(a.h[q / K1] * st[tid * LD + q] * a.colscale[q]));
+        int e = 0;
+        if (mx > 0.0) {
+            int E;
+            frexp(mx, &E);
+            e = E - 7;
+        }
+        sexp[tid] = e;
+        const int s = tile * 32 + tid;
+        if (s < a.n_slots) a.eslot[s] = e;
+    }
+    __syncthreads();
+    for (int t = tid; t < a.KS * 64; t += 256) {
+        const int ks = t >> 6, lane = t & 63, sl = lane & 31, hh = lane >> 5;
+        half8_t hi, lo;
+        for (int jj = 0; jj < 8; ++jj) {
+            const int q = ks * 16 + hh * 8 + jj;
+            float m = 0.0f;
+            if (q < P) m = (float)ldexp(a.h[q / K1] * st[sl * LD + q] * a.colscale[q], -sexp[sl]);
+            const _Float16 mh = (_Float16)m;
+            hi[jj] = mh;
+            lo[jj] = (_Float16)(m - (float)mh);
+        }
+        const size_t base = ((size_t)(tile * a.KS + ks) * 2) * 64 + lane;
+        a.mfrag[base] = __builtin_bit_cast(uint4, hi);
+        a.mfrag[base + 64] = __builtin_bit_cast(uint4, lo);
+    }
+    for (int t = tid; t < P * 32; t += 256) {
+        const int q = t >> 5, sl = t & 31;
+        a.mt[((size_t)tile * P + q) * 32 + sl] = (float)ldexp(a.h[q / K1] * st[sl * LD + q] * a.colscale[q], -sexp[sl]);
+    }
+}
+
+int launch_stage(const StageArgs& a, hipStream_t s)
+{
+    if (a.n_tiles == 0) return GD_OK;
+    if (a.P > kStageMaxP) return fail(GD_EUNSUPPORTED, "P too large for the stage kernel");
+    hipLaunchKernelGGL(k_stage, dim3(a.n_tiles), dim3(256), 0, s, a);
     HIP_TRY(hipGetLastError());
     return GD_OK;
 }
 
-int launch_epilogue(const EpilogueArgs& a, hipStream_t s)
-{
-    const long long n = (long long)a.n_slots * a.N;
-    if (n == 0) return GD_OK;
-    hipLaunchKernelGGL(k_epilogue, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
-    HIP_TRY(hipGetLastError());
-    return GD_OK;
-}
-
-int launch_limit(double* g, int C, int N, int k, int P, unsigned long long* viol, hipStream_t s)
-{
-    if (C == 0) return GD_OK;
-    hipLaunchKernelGGL(k_limit, dim3(cdiv(C, 256)), dim3(256), 0, s, g, C, N, k, P, viol);
-    HIP_TRY(hipGetLastError());
-    return GD_OK;
-}
-
+// ---------------------------------------------------------------------------
 int launch_fill_u64(unsigned long long* p, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(cdiv(n, 64)), dim3(64), 0, s, p, n);

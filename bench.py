@@ -40,84 +40,106 @@ def describe(w):
 
 
 def build_inputs(w, dev):
+    """Tensors, per-group cell counts and the projected initial state of the workload
+    (cells of an uneven batch sorted by group)."""
     import numpy as np
     import torch
     from paper_2607_13740_amd import gracedg as G
     from paper_2607_13740_amd import workloads as W
 
-    t0 = time.perf_counter()
-    t = G.Tensor(w.bins, w.order, w.x_min, w.x_max, kernel=w.kernel, frag=w.frag,
-                 levels=w.levels, conservative=w.conservative)
-    t_init = time.perf_counter() - t0
     params = W.lognormal_cells(w.cells, w.seed) if w.profile == "lognormal_cells" else None
-    x = t.projection_points()
-    smp = torch.tensor(W.samples(w, x, params=params), device=dev)
-    g0 = t.project(smp).reshape(-1)
-    del smp
+    shapes = w.groups if w.groups else ((w.bins, w.order),)
+    if w.groups:
+        counts, order = W.uneven_groups(w)
+    else:
+        counts, order = np.array([w.cells]), np.arange(w.cells)
+    t0 = time.perf_counter()
+    tensors = [G.Tensor(N, k, w.x_min, w.x_max, kernel=w.kernel, frag=w.frag, levels=w.levels,
+                        conservative=w.conservative) for N, k in shapes]
+    t_init = time.perf_counter() - t0
+    parts = []
+    c0 = 0
+    for t, n in zip(tensors, counts):
+        ids = order[c0:c0 + n]
+        c0 += n
+        sub = None if params is None else {key: v[ids] for key, v in params.items()}
+        smp = torch.tensor(W.samples(w, t.projection_points(), cells=int(n), params=sub), device=dev)
+        parts.append(t.project(smp).reshape(-1))
+        del smp
+    g0 = torch.cat(parts)
     ks = vf = None
     if w.per_cell and params is not None:
-        ks = torch.tensor(params["kscale"], device=dev)
-        vf = np.asarray(params["vfrag"])
-    return t, g0, ks, vf, t_init, params
+        ks = torch.tensor(params["kscale"][order], device=dev)
+        vf = np.asarray(params["vfrag"][order])
+    return tensors, [int(c) for c in counts], g0, ks, vf, t_init, params
 
 
 def time_steps(plan, g, w, ks, steps, warmup):
+    """ms per RK step (the captured step replayed), then the average duration of the
+    contraction kernel from HIP events on the plan's stream (launch by launch)."""
     import torch
     for _ in range(warmup):
         plan.rk_step(g, w.dt, 1, kscale=ks)
     torch.cuda.synchronize()
-    plan.timing(True)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        plan.rk_step(g, w.dt, 1, kscale=ks)
+    plan.rk_step(g, w.dt, steps, kscale=ks)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    plan.timing(True)
+    plan.rk_step(g, w.dt, max(2, steps // 4), kscale=ks)
     kms, launches = plan.contraction_time()
     plan.timing(False)
     return (t1 - t0) * 1e3 / steps, kms / max(1, launches), launches
 
 
 def cpu_baseline(w, params, seconds):
-    """The FP64 oracle on the host cores, on a sample of the workload's cells."""
+    """The FP64 oracle on the host cores, on a sample of the workload's cells (the
+    first cells in the workload's own order, each evaluated with its group's shape)."""
     import numpy as np
     from oracle import oracle as O
     from paper_2607_13740_amd import workloads as W
 
     O.build(force=False)
-    cfg = O.Config(N=w.bins, k=w.order, xmin=w.x_min, xmax=w.x_max, kernel=w.kernel, frag=w.frag,
-                   conservative=w.conservative, vfrag=w.levels[0],
-                   levels=w.levels if len(w.levels) > 1 else ())
+    shapes = w.groups if w.groups else ((w.bins, w.order),)
+    cfgs = [O.Config(N=N, k=k, xmin=w.x_min, xmax=w.x_max, kernel=w.kernel, frag=w.frag,
+                     conservative=w.conservative, vfrag=w.levels[0],
+                     levels=w.levels if len(w.levels) > 1 else ()) for N, k in shapes]
+    gid = np.zeros(w.cells, dtype=int)
+    if w.groups:
+        counts, order = W.uneven_groups(w)
+        gid[order] = np.repeat(np.arange(len(shapes)), counts)
 
-    def states(n):
-        out = []
-        for c in range(n):
-            if params is None:
-                f = W.xexp_density if w.profile == "xexp" else W.lognormal_density
-            else:
-                f = (lambda mu, s, m: (lambda x: W.lognormal_density(x, mu, s, m)))(
-                    params["mu"][c], params["sigma"][c], params["mass"][c])
-            out.append(O.project(cfg, f))
-        return np.array(out)
+    def run(n):
+        """oracle time of the first n cells"""
+        tot = 0.0
+        for gi, cfg in enumerate(cfgs):
+            ids = np.nonzero(gid[:n] == gi)[0]
+            if ids.size == 0:
+                continue
+            g = []
+            for c in ids:
+                if params is None:
+                    f = W.xexp_density if w.profile == "xexp" else W.lognormal_density
+                else:
+                    f = (lambda mu, s, m: (lambda x: W.lognormal_density(x, mu, s, m)))(
+                        params["mu"][c], params["sigma"][c], params["mass"][c])
+                g.append(O.project(cfg, f))
+            ks = params["kscale"][ids] if (params is not None and w.per_cell) else None
+            vf = params["vfrag"][ids] if (params is not None and w.per_cell) else None
+            t0 = time.perf_counter()
+            O.rhs(cfg, np.array(g), kscale=ks, vfrag=vf)
+            tot += time.perf_counter() - t0
+        return tot
 
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    n = max(1, min(cores, 16))
-    g = states(n)
-    ks = params["kscale"][:n] if (params is not None and w.per_cell) else None
-    vf = params["vfrag"][:n] if (params is not None and w.per_cell) else None
-    t0 = time.perf_counter()
-    O.rhs(cfg, g, kscale=ks, vfrag=vf)
-    dt = time.perf_counter() - t0
+    n = max(1, min(cores, 16, w.cells))
+    dt = run(n)
     m = int(min(4096, max(n, seconds / max(dt / n, 1e-9))))
     m = max(n, (m // cores) * cores) if m > cores else m
     m = min(m, w.cells)
-    g = states(m)
-    ks = params["kscale"][:m] if (params is not None and w.per_cell) else None
-    vf = params["vfrag"][:m] if (params is not None and w.per_cell) else None
-    t0 = time.perf_counter()
-    O.rhs(cfg, g, kscale=ks, vfrag=vf)
-    dt = time.perf_counter() - t0
+    dt = run(m)
     return {"value": m / dt, "unit": "cell-evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{m} cells of {w.name}, one right-hand-side evaluation each, FP64 nested "
+            "sample": f"first {m} cells of {w.name}, one right-hand-side evaluation each, FP64 nested "
                       f"Gauss-Legendre sums in C (gcc -O2, OpenMP across cells), {dt:.1f} s"}
 
 
@@ -144,26 +166,32 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = "cuda:0"
     w = W.WORKLOADS[args.workload]
-    if w.groups:
-        raise SystemExit("uneven batches are timed by bench_uneven (not built yet)")
     print(f"# workload {describe(w)}", file=sys.stderr, flush=True)
-    t, g0, ks, vf, t_init, params = build_inputs(w, dev)
-    info = t.info()
+    tensors, counts, g0, ks, vf, t_init, params = build_inputs(w, dev)
+    infos = [t.info() for t in tensors]
     C = w.cells
+    flops_launch = sum(i["flops_per_eval"] * c for i, c in zip(infos, counts))
     res = {}
     for prec in (("mixed",) if args.no_fp64 else ("mixed", "fp64")):
-        plan = G.Plan(t, C, precision=prec, vfrag=vf)
+        plan = G.Plan(tensors, counts, precision=prec, vfrag=vf)
         g = g0.clone()
+        tune = plan.autotune(g, kscale=ks)
         ms, kms, launches = time_steps(plan, g, w, ks, args.steps, args.warmup)
         res[prec] = {"ms_per_step": ms, "kernel_ms": kms, "launches": launches, "plan": plan,
-                     "stats": plan.schedule_stats(0)}
-        print(f"# {prec}: {ms:.3f} ms/step, contraction {kms:.4f} ms/launch over {launches} launches",
-              file=sys.stderr, flush=True)
-        # mass drift over the timed run (FP64 bookkeeping of the bin masses)
-        h = torch.tensor(np.repeat(np.diff(t.edges()), 1), device=dev)
-        gm = g.view(C, w.bins, w.order + 1)[:, :, 0] * h
-        g0m = g0.view(C, w.bins, w.order + 1)[:, :, 0] * h
-        res[prec]["mass_drift"] = float(((gm.sum(1) - g0m.sum(1)).abs() / g0m.sum(1)).max())
+                     "variant": plan.variant(), "tune": tune}
+        print(f"# {prec}: {ms:.3f} ms/step, contraction {kms:.4f} ms/launch over {launches} launches, "
+              f"variant {res[prec]['variant']}", file=sys.stderr, flush=True)
+        # mass drift over the run (FP64 bookkeeping of the bin masses), cell by cell
+        drift, voff = 0.0, 0
+        for t, n in zip(tensors, counts):
+            P, K1 = t.P, t.order + 1
+            h = torch.tensor(np.diff(t.edges()), device=dev)
+            gm = g[voff:voff + n * P].view(n, t.bins, K1)[:, :, 0] * h
+            g0m = g0[voff:voff + n * P].view(n, t.bins, K1)[:, :, 0] * h
+            if n:
+                drift = max(drift, float(((gm.sum(1) - g0m.sum(1)).abs() / g0m.sum(1)).max()))
+            voff += n * P
+        res[prec]["mass_drift"] = drift
 
     # accuracy of the split contraction against the FP64 contraction on the full batch
     acc = {}
@@ -172,21 +200,22 @@ def main():
         for prec in ("mixed", "fp64"):
             raw = torch.zeros(res[prec]["plan"].n_raw, dtype=torch.float64, device=dev)
             res[prec]["plan"].collision_rhs(g0, kscale=ks, raw=raw)
-            raws[prec] = raw.view(C, -1)
-        d = (raws["mixed"] - raws["fp64"]).abs().amax(1) / raws["fp64"].abs().amax(1)
+            raws[prec] = raw
+        eps, roff = [], 0
+        for t, n in zip(tensors, counts):
+            m = n * t.n_out
+            a = raws["mixed"][roff:roff + m].view(n, -1)
+            b = raws["fp64"][roff:roff + m].view(n, -1)
+            if n:
+                eps.append((a - b).abs().amax(1) / b.abs().amax(1))
+            roff += m
+        d = torch.cat(eps)
         acc = {"eps_max": float(d.max()), "eps_median": float(d.median()),
                "definition": "per cell max_o |Y_mixed - Y_fp64| / max_o |Y_fp64| on the raw flux vector"}
 
     mixed = res["mixed"]
     cell_evals = 3.0 * C / (mixed["ms_per_step"] * 1e-3)
-    # executed MFMA work of one launch: every stored fragment (32 rows x 16 K) of the
-    # levels in use, 3 products, for every 32-cell tile of the bracket using it
-    # (bracket sizes from the plan's slot count, fragments averaged over levels)
-    st = mixed["stats"]
-    n_levels = max(1, info["n_levels"])
-    frags_per_level = st["frags_mixed"] / n_levels
-    exec_flops = frags_per_level * 3 * (2 * 32 * 32 * 16) * (st["n_slots"] / 32)
-    flops_launch = info["flops_per_eval"] * C
+    exec_flops = mixed["variant"]["exec_flops"]
     achieved = flops_launch / (mixed["kernel_ms"] * 1e-3) / 1e12
     out = {
         "metric": METRIC,
@@ -201,13 +230,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f16x3",
         "data": "synthetic",
-        "config": {"workload": describe(w), "cells": C, "P": w.P, "precision": "split FP16 (hi+lo, 3 MFMA "
-                   "products) with FP32 MFMA accumulation, FP64 p-sum, FP64 state/limiter/RK"},
+        "config": {"workload": describe(w), "cells": C, "groups": len(tensors),
+                   "P": [t.P for t in tensors] if len(tensors) > 1 else tensors[0].P,
+                   "precision": "split FP16 (hi+lo, 3 MFMA products) with FP32 MFMA accumulation, FP64 p-sum, "
+                                "FP64 state/limiter/RK",
+                   "contraction_variant": mixed["variant"], "step": "one captured HIP graph per RK step"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_F16_TFLOPS, "traffic": None,
                      "kernel": "k_contract_mixed", "kernel_ms": mixed["kernel_ms"],
                      "algorithmic_flops_per_launch": flops_launch,
-                     "flops_per_cell_eval": info["flops_per_eval"],
+                     "flops_per_cell_eval": flops_launch / C,
+                     "executed_mfma_flops_per_launch": exec_flops,
                      "executed_mfma_tflops": exec_flops / (mixed["kernel_ms"] * 1e-3) / 1e12,
                      "mfma_utilisation": exec_flops / (mixed["kernel_ms"] * 1e-3) / 1e12 / PEAK_F16_TFLOPS},
         "tensor_init_s": t_init,
@@ -219,6 +252,7 @@ def main():
         f_evals = 3.0 * C / (f["ms_per_step"] * 1e-3)
         out["fp64_gpu"] = {"value": f_evals, "ms_per_step": f["ms_per_step"], "kernel_ms": f["kernel_ms"],
                            "achieved_tflops": flops_launch / (f["kernel_ms"] * 1e-3) / 1e12,
+                           "variant": f["variant"],
                            "peak_tflops": PEAK_F64_TFLOPS, "mass_drift": f["mass_drift"]}
         out["speedup_mixed_vs_fp64"] = cell_evals / f_evals
     if not args.no_cpu_baseline:

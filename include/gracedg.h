@@ -167,6 +167,37 @@ int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, doubl
 int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_steps, long long* violations);
 
 /*
+ * Batching of the contraction (uneven batches of several groups in one launch).
+ * Every contraction is ONE launch over all groups of the plan: a list of work items
+ * (group, threshold level, a range of output row blocks, a chunk of 4 or 8 tiles of
+ * cells), sorted by cost, largest first.  The stage kernels between contractions
+ * are likewise one launch over all groups.
+ *
+ * gd_plan_set_variant -- choose the contraction variant: waves (4 or 8) per
+ *   workgroup, each wave one tile of cells (32 split-FP16, 16 FP64), and rows =
+ *   row blocks per work item (0 = all of the group's row blocks).  Every variant
+ *   gives bit-identical results.  Rebuilds the item list (synchronous).
+ * gd_plan_variant -- the current variant, the number of work items of one
+ *   contraction launch and the MFMA flops one launch executes (every stored
+ *   fragment, all products, for every tile of an item); any pointer may be NULL.
+ * gd_plan_autotune -- time every variant on state g (device, state layout, read
+ *   only; kscale as in gd_rk_step) and keep the fastest.  cache_path (or NULL)
+ *   names a text file of "key waves rows" lines: a plan of the same shape (precision,
+ *   bins, order, levels, cells and brackets of every group) takes its stored
+ *   choice without timing; a newly timed choice is appended.  Synchronous.
+ * gd_plan_use_graph -- (default on) gd_rk_step captures one RK step (three
+ *   contractions and three stage kernels) into a HIP graph on a private stream and
+ *   replays it once per step on the plan's stream.  The graph is captured again
+ *   when g, kscale, dt or the variant change.  Off: the launches are issued one by
+ *   one.  Timing (gd_plan_timing) also issues them one by one.
+ */
+int gd_plan_set_variant(gd_plan* plan, int waves, int rows);
+int gd_plan_variant(const gd_plan* plan, int* waves, int* rows, int* n_items, double* exec_flops);
+int gd_plan_autotune(gd_plan* plan, const double* g, const double* kscale, const char* cache_path, int* waves,
+                     int* rows);
+int gd_plan_use_graph(gd_plan* plan, int enable);
+
+/*
  * gd_projection_points / gd_project -- initial coefficients (Sec. 3.2, Eq. init):
  *     g_j^i = (2i+1)/2 sum_a w_a g0(c_j + h_j s_a / 2) P_i(s_a)
  * with a 16-point Gauss-Legendre rule per bin.  gd_projection_points writes the

@@ -10,6 +10,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -25,7 +26,7 @@ HIP_FLAGS = [
 ]
 
 
-SOURCES_HIP = ["api.hip", "contract.hip", "state.hip"]
+SOURCES_HIP = ["api.hip", "contract_mixed.hip", "contract_fp64.hip", "state.hip"]
 
 
 def build(verbose: bool = False) -> str:
@@ -40,7 +41,7 @@ def build(verbose: bool = False) -> str:
         cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", o])
         objs.append(o)
     cmds.append([HIPCC, f"--offload-arch={ARCH}", "-shared", *objs, "-pthread", "-o", LIB + ".tmp"])
-    for c in cmds:
+    def run(c):
         if verbose:
             print(" ".join(c), flush=True)
         r = subprocess.run(c, capture_output=True, text=True)
@@ -52,6 +53,12 @@ def build(verbose: bool = False) -> str:
             msgs = [ln for ln in r.stderr.splitlines() if "packed-fp32-ops" not in ln]
             if msgs:
                 sys.stderr.write("\n".join(msgs) + "\n")
+
+    # objects in parallel (the contraction sources take the longest), then the link
+    with ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        for f in [ex.submit(run, c) for c in cmds[:-1]]:
+            f.result()
+    run(cmds[-1])
     os.replace(LIB + ".tmp", LIB)
     for o in objs:
         os.remove(o)

@@ -3,6 +3,7 @@
 // the right-hand side and the SSP-RK3 step.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -100,65 +101,69 @@ static inline int pow2_exp(double v)
     return E;
 }
 
-// Generic schedule builder: row blocks of RB rows, K steps of KW columns, up to SEG
-// p segments per iteration.  emit(r, delta, ob, p, ks) appends one fragment;
-// blockscale(r, delta, ob) returns the offset of the stage-2 scale table of that
-// (part, ob) (or 0).  Every level ends with two empty sentinel descriptors (ob = -1).
+// Generic schedule builder: row blocks of RB rows, K steps of KW columns.  One
+// list per (level r, row block ob); its iterations hold the segments of the level
+// part and then of the difference part (r + 1 < R), packed up to kSegMax segments
+// and kFragBudget fragments per iteration.  emit(r, delta, ob, p, ks) appends one
+// fragment; blockscale(r, delta, ob) returns the offset of the stage-2 scale table
+// of that (part, ob) (or 0).  Every list is followed by two sentinels.
+constexpr long long kIterCost = 2;   // cost of an iteration in fragment units (item ordering)
+
 template <class Emit, class BlockScale>
-static void build_schedule(const gd_tensor* t, int RB, int KW, int SEG, std::vector<IterDesc>& iters,
-                           std::vector<int>& off, std::vector<int>& cnt, Emit emit, BlockScale blockscale)
+static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterDesc>& iters, std::vector<int>& off,
+                           std::vector<int>& cnt, std::vector<long long>& cost, std::vector<long long>& frags, Emit emit,
+                           BlockScale blockscale)
 {
     const int P = t->P, NO = t->n_out, R = t->R;
     const int NOBx = cdiv(NO, RB), KSx = cdiv(P, KW);
     std::vector<std::pair<int, int>> pairs;
     make_pairs(P, pairs);
     int nfrag = 0;
-    for (int r = 0; r < R; ++r) {
-        off.push_back(int(iters.size()));
+    for (int r = 0; r < R; ++r)
         for (int ob = 0; ob < NOBx; ++ob) {
+            off.push_back(int(iters.size()));
+            const int nf0 = nfrag;
             bool any = false;
             int first_scale = -1;
             for (int delta = 0; delta <= (r + 1 < R ? 1 : 0); ++delta) {
                 const int sc = blockscale(r, delta, ob);
                 if (first_scale < 0) first_scale = sc;
                 // present segments of this (part, ob), in pair order: the K steps from the
-                // first to the last nonzero block of p (zero blocks in between are stored)
-                struct Seg { int p, lo, hi; };
+                // first nonzero block of p to the last K step (zero blocks in between are stored)
+                struct Seg { int p, lo; };
                 std::vector<Seg> segs;
                 for (auto& pr : pairs)
                     for (int side = 0; side < 2; ++side) {
                         const int p = side ? pr.second : pr.first;
                         if (p < 0) continue;
-                        int lo = -1, hi = -1;
-                        for (int ks = p / KW; ks < KSx; ++ks) {
+                        int lo = -1;
+                        for (int ks = p / KW; ks < KSx && lo < 0; ++ks) {
                             bool nz = false;
                             for (int o = ob * RB; o < std::min(NO, ob * RB + RB) && !nz; ++o)
                                 for (int q = std::max(p, ks * KW); q < std::min(P, ks * KW + KW); ++q)
                                     if (part(t, r, delta, o, p, q) != 0.0) { nz = true; break; }
-                            if (nz) {
-                                if (lo < 0) lo = ks;
-                                hi = ks;
-                            }
+                            if (nz) lo = ks;
                         }
-                        // the kernels run every segment to the last K step
-                        if (lo >= 0) segs.push_back({p, lo, KSx - 1});
-                        (void)hi;
+                        if (lo >= 0) segs.push_back({p, lo});
                     }
-                for (size_t s0 = 0; s0 < segs.size(); s0 += SEG) {
+                size_t s0 = 0;
+                while (s0 < segs.size()) {
                     IterDesc d{};
                     d.ob = ob;
                     d.delta = delta;
                     d.scale = sc;
                     d.frag = nfrag;
-                    d.nseg = int(std::min<size_t>(SEG, segs.size() - s0));
-                    for (int j = 0; j < d.nseg; ++j) {
-                        d.p[j] = segs[s0 + j].p;
-                        d.lo[j] = segs[s0 + j].lo;
-                        d.hi[j] = segs[s0 + j].hi;
-                        for (int ks = d.lo[j]; ks <= d.hi[j]; ++ks) {
+                    while (s0 < segs.size() && d.nseg < kSegMax &&
+                           (nfrag - d.frag) + (KSx - segs[s0].lo) <= kFragBudget) {
+                        const int j = d.nseg++;
+                        d.p[j] = segs[s0].p;
+                        d.lo[j] = segs[s0].lo;
+                        d.hi[j] = KSx - 1;
+                        for (int ks = d.lo[j]; ks < KSx; ++ks) {
                             emit(r, delta, ob, d.p[j], ks);
                             ++nfrag;
                         }
+                        ++s0;
                     }
                     d.nfrag = nfrag - d.frag;
                     iters.push_back(d);
@@ -173,14 +178,15 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, int SEG, std::vec
                 d.scale = std::max(0, first_scale);
                 iters.push_back(d);
             }
+            cnt.push_back(int(iters.size()) - off.back());
+            cost.push_back((nfrag - nf0) + kIterCost * cnt.back());
+            frags.push_back(nfrag - nf0);
+            IterDesc sentinel{};
+            sentinel.ob = -1;
+            sentinel.frag = nfrag;
+            iters.push_back(sentinel);
+            iters.push_back(sentinel);
         }
-        cnt.push_back(int(iters.size()) - off.back());
-        IterDesc sentinel{};
-        sentinel.ob = -1;
-        sentinel.frag = nfrag;
-        iters.push_back(sentinel);
-        iters.push_back(sentinel);
-    }
 }
 
 static int pack_tensor(gd_tensor* t)
@@ -261,15 +267,16 @@ static int pack_tensor(gd_tensor* t)
                     frag[f * 1024 + 512 + l * 8 + j] = bl;
                 }
         };
-        build_schedule(t, 32, 16, segs_per_iter(t->KS), iters, off, cnt, emit, blockscale);
+        build_schedule(t, 32, 16, iters, off, cnt, t->mixed.list_cost, t->mixed.list_frags, emit, blockscale);
+        t->mixed.NOB = t->NOB;
         const uint16_t* dfrag = nullptr;
         if ((rc = upload(t->bufs, frag, &dfrag, &t->bytes))) return rc;
         t->mixed.frag = dfrag;
         t->mixed.frags = (long long)(frag.size() / 1024);
         t->mixed.iters_total = (long long)iters.size();
         if ((rc = upload(t->bufs, iters, &t->mixed.iters, &t->bytes))) return rc;
-        if ((rc = upload(t->bufs, off, &t->mixed.iter_off, &t->bytes))) return rc;
-        if ((rc = upload(t->bufs, cnt, &t->mixed.iter_cnt, &t->bytes))) return rc;
+        if ((rc = upload(t->bufs, off, &t->mixed.list_off, &t->bytes))) return rc;
+        if ((rc = upload(t->bufs, cnt, &t->mixed.list_cnt, &t->bytes))) return rc;
         if ((rc = upload(t->bufs, scale, &t->mixed.scale, &t->bytes))) return rc;
     }
 
@@ -288,15 +295,16 @@ static int pack_tensor(gd_tensor* t)
                     if (o < NO && q < P && q >= p) frag[f * 256 + j * 64 + l] = part(t, r, delta, o, p, q);
                 }
         };
-        build_schedule(t, 16, 16, segs_per_iter(t->KS), iters, off, cnt, emit, blockscale);
+        build_schedule(t, 16, 16, iters, off, cnt, t->f64.list_cost, t->f64.list_frags, emit, blockscale);
+        t->f64.NOB = t->NOB16;
         const double* dfrag = nullptr;
         if ((rc = upload(t->bufs, frag, &dfrag, &t->bytes))) return rc;
         t->f64.frag = dfrag;
         t->f64.frags = (long long)(frag.size() / 256);
         t->f64.iters_total = (long long)iters.size();
         if ((rc = upload(t->bufs, iters, &t->f64.iters, &t->bytes))) return rc;
-        if ((rc = upload(t->bufs, off, &t->f64.iter_off, &t->bytes))) return rc;
-        if ((rc = upload(t->bufs, cnt, &t->f64.iter_cnt, &t->bytes))) return rc;
+        if ((rc = upload(t->bufs, off, &t->f64.list_off, &t->bytes))) return rc;
+        if ((rc = upload(t->bufs, cnt, &t->f64.list_cnt, &t->bytes))) return rc;
     }
     t->packed = true;
     return GD_OK;
@@ -378,15 +386,20 @@ extern "C" int gd_tensor_edges(const gd_tensor* t, double* host_out)
 extern "C" void gd_free_tensor(gd_tensor* t) { delete t; }
 
 // ============================================================================ plans
+// A threshold bracket of a group: level r, first slot, cells in it (the rest of the
+// bracket up to the next multiple of kSlotGranule slots is padding).
+struct Bracket {
+    int r, s0, n;
+};
+
 struct Group {
     const gd_tensor* t = nullptr;
     int C = 0;
-    long long cell0 = 0, val0 = 0;
-    int n_slots = 0, tiles32 = 0, tiles16 = 0;
+    long long cell0 = 0, val0 = 0, raw0 = 0;
+    int n_slots = 0, tiles32 = 0, tiles16 = 0, tile_off = 0;
+    std::vector<Bracket> brackets;
     int* perm = nullptr;        // slot -> cell within the group (nullptr: identity)
-    int* slot_level = nullptr;  // [n_slots]
     double* theta = nullptr;    // [n_slots]
-    std::vector<int> h_perm;
     uint4* mfrag = nullptr;
     float* mt = nullptr;
     int* eslot = nullptr;
@@ -400,23 +413,49 @@ struct KernelTimer {
     size_t used = 0;
 };
 
+// one captured RK step, valid for the state, scale and dt it was captured with
+struct StepGraph {
+    hipGraphExec_t exec = nullptr;
+    const double* g = nullptr;
+    const double* kscale = nullptr;
+    double dt = 0.0;
+};
+
 struct gd_plan {
     std::vector<Group> groups;
     int prec = GD_PREC_FP64;
     hipStream_t stream = nullptr;
-    long long n_cells = 0, n_values = 0;
+    hipStream_t cap = nullptr;              // private stream the step graph is captured on
+    long long n_cells = 0, n_values = 0, n_raw = 0;
+    int ksmax = 1, tiles32 = 0;
+    GroupDev* groups_dev = nullptr;
+    int waves = 4, rows = 1;                // contraction variant: waves per workgroup, row blocks per item
+    int4* items = nullptr;
+    int n_items = 0;
+    size_t items_cap = 0;
+    double exec_flops = 0.0;                // MFMA flops one contraction launch executes
+    bool use_graph = true;
+    StepGraph graph;
     double* y1 = nullptr;
     double* y2 = nullptr;
     unsigned long long* viol = nullptr;
     bool timing = false;
     KernelTimer timer;
     std::vector<void*> allocs;
+    void drop_graph()
+    {
+        if (graph.exec) (void)hipGraphExecDestroy(graph.exec);
+        graph = StepGraph{};
+    }
     ~gd_plan()
     {
+        drop_graph();
+        if (cap) (void)hipStreamDestroy(cap);
         for (auto& e : timer.ev) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
         }
+        if (items) (void)hipFree(items);
         for (void* p : allocs) (void)hipFree(p);
     }
 };
@@ -440,14 +479,71 @@ static int dcopy(gd_plan* pl, T** p, const std::vector<T>& v)
     return GD_OK;
 }
 
-// cells are grouped into threshold brackets of 256 slots so that every contraction
-// workgroup reads one level
+// cells are sorted into threshold brackets padded to 256 slots, so that every
+// contraction workgroup (at most 8 tiles of 32 slots) reads one level
 static constexpr int kSlotGranule = 256;
+
+// Work items of the contraction for the plan's variant, largest first: the hardware
+// hands workgroups out in launch order, so the expensive items start first and the
+// small ones fill the tail.  Items of one list are adjacent, so that the workgroups
+// running at one time share the list's fragments in L2.
+static int build_items(gd_plan* pl)
+{
+    const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
+    const int ts = mixed ? 32 : 16, W = pl->waves;
+    struct It {
+        long long cost;
+        int4 v;
+        long long frags;
+    };
+    std::vector<It> v;
+    for (size_t gi = 0; gi < pl->groups.size(); ++gi) {
+        const Group& G = pl->groups[gi];
+        if (G.C == 0) continue;
+        const Schedule& S = mixed ? G.t->mixed : G.t->f64;
+        const int NOB = S.NOB;
+        const int rows = pl->rows <= 0 ? NOB : std::min(NOB, pl->rows);
+        for (const Bracket& b : G.brackets) {
+            const int t0 = b.s0 / ts, t1 = cdiv(b.s0 + b.n, ts);
+            for (int tile = t0; tile < t1; tile += W)
+                for (int ob = 0; ob < NOB; ob += rows) {
+                    const int ob1 = std::min(NOB, ob + rows);
+                    long long c = 4, f = 0;
+                    for (int o = ob; o < ob1; ++o) {
+                        c += S.list_cost[size_t(b.r) * NOB + o];
+                        f += S.list_frags[size_t(b.r) * NOB + o];
+                    }
+                    v.push_back({c, int4{int(gi), b.r, ob | (ob1 << 16), tile}, f});
+                }
+        }
+    }
+    std::stable_sort(v.begin(), v.end(), [](const It& x, const It& y) { return x.cost > y.cost; });
+    std::vector<int4> h(v.size());
+    double fl = 0.0;
+    for (size_t i = 0; i < v.size(); ++i) {
+        h[i] = v[i].v;
+        // split path: 3 products of 32x32x16 per fragment and tile; FP64: 4 of 16x16x4
+        fl += double(v[i].frags) * W * (mixed ? 3.0 * 2 * 32 * 32 * 16 : 4.0 * 2 * 16 * 16 * 4);
+    }
+    if (h.size() > pl->items_cap) {
+        if (pl->items) HIP_TRY(hipFree(pl->items));
+        pl->items = nullptr;
+        pl->items_cap = 0;
+        HIP_TRY(hipMalloc(&pl->items, h.size() * sizeof(int4)));
+        pl->items_cap = h.size();
+    }
+    if (!h.empty()) HIP_TRY(hipMemcpy(pl->items, h.data(), h.size() * sizeof(int4), hipMemcpyHostToDevice));
+    pl->n_items = int(h.size());
+    pl->exec_flops = fl;
+    pl->drop_graph();
+    return GD_OK;
+}
 
 extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_per_group, int n_groups,
                               int precision, const double* vfrag, void* stream, gd_plan** out)
 {
     if (!tensors || !cells_per_group || n_groups < 1 || !out) return fail(GD_EINVAL, "null argument");
+    if (n_groups > 4096) return fail(GD_EINVAL, "at most 4096 groups");
     if (precision != GD_PREC_FP64 && precision != GD_PREC_MIXED_F16X3) return fail(GD_EINVAL, "unknown precision");
     auto pl = std::unique_ptr<gd_plan>(new (std::nothrow) gd_plan());
     if (!pl) return fail(GD_ENOMEM, "host allocation");
@@ -462,10 +558,15 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
         G.C = cells_per_group[g];
         G.cell0 = pl->n_cells;
         G.val0 = pl->n_values;
+        G.raw0 = pl->n_raw;
         pl->n_cells += G.C;
         pl->n_values += (long long)G.C * G.t->P;
+        pl->n_raw += (long long)G.C * G.t->n_out;
+        pl->ksmax = std::max(pl->ksmax, G.t->KS);
         pl->groups.push_back(std::move(G));
     }
+    if (pl->n_cells > (1ll << 30)) return fail(GD_EINVAL, "too many cells");
+    std::vector<GroupDev> gdev;
     for (Group& G : pl->groups) {
         const gd_tensor* t = G.t;
         if (t->R > 1) {
@@ -475,38 +576,40 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
             std::vector<std::vector<std::pair<int, double>>> br(t->R - 1);
             for (int c = 0; c < G.C; ++c) {
                 const double v = vfrag ? vfrag[G.cell0 + c] : lv[0];
+                if (!std::isfinite(v)) return fail(GD_EINVAL, "non-finite fragmentation threshold");
                 int r = 0;
                 while (r < t->R - 2 && v >= lv[r + 1]) ++r;
                 double th = (v - lv[r]) / (lv[r + 1] - lv[r]);
                 th = std::min(1.0, std::max(0.0, th));
                 br[r].push_back({c, th});
             }
-            std::vector<int> perm, level;
+            std::vector<int> perm;
             std::vector<double> theta;
             for (int r = 0; r < t->R - 1; ++r) {
                 if (br[r].empty()) continue;
+                G.brackets.push_back({r, int(perm.size()), int(br[r].size())});
                 for (auto& ct : br[r]) {
                     perm.push_back(ct.first);
-                    level.push_back(r);
                     theta.push_back(ct.second);
                 }
                 while (perm.size() % kSlotGranule) {
                     perm.push_back(-1);
-                    level.push_back(r);
                     theta.push_back(0.0);
                 }
             }
             G.n_slots = int(perm.size());
-            G.h_perm = perm;
             if ((rc = dcopy(pl.get(), &G.perm, perm))) return rc;
-            if ((rc = dcopy(pl.get(), &G.slot_level, level))) return rc;
             if ((rc = dcopy(pl.get(), &G.theta, theta))) return rc;
         } else {
             G.n_slots = G.C;
+            if (G.C > 0) G.brackets.push_back({0, 0, G.C});
         }
         G.tiles32 = cdiv(G.n_slots, 32);
         G.tiles16 = cdiv(G.n_slots, 16);
-        if (precision == GD_PREC_MIXED_F16X3) {
+        G.tile_off = pl->tiles32;
+        pl->tiles32 += G.tiles32;
+        const bool mixed = precision == GD_PREC_MIXED_F16X3;
+        if (mixed) {
             G.ystride = t->NOB * 32;
             if ((rc = dalloc(pl.get(), &G.mfrag, size_t(G.tiles32) * t->KS * 128))) return rc;
             if ((rc = dalloc(pl.get(), &G.mt, size_t(G.tiles32) * 32 * t->P))) return rc;
@@ -516,11 +619,47 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
             G.ystride = t->NOB16 * 16;
             if ((rc = dalloc(pl.get(), &G.Yd, size_t(G.n_slots) * G.ystride))) return rc;
         }
+        const Schedule& S = mixed ? t->mixed : t->f64;
+        GroupDev d{};
+        d.frag = static_cast<const uint4*>(S.frag);
+        d.iters = S.iters;
+        d.list_off = S.list_off;
+        d.list_cnt = S.list_cnt;
+        d.scale = S.scale;
+        d.h = t->h;
+        d.colscale = t->colscale;
+        d.rowscale = t->rowscale;
+        d.perm = G.perm;
+        d.theta = G.theta;
+        d.mfrag = G.mfrag;
+        d.mt = G.mt;
+        d.eslot = G.eslot;
+        d.Yf = G.Yf;
+        d.Yd = G.Yd;
+        d.val0 = G.val0;
+        d.raw0 = G.raw0;
+        d.cell0 = int(G.cell0);
+        d.N = t->N;
+        d.k = t->k;
+        d.P = t->P;
+        d.KS = t->KS;
+        d.n_out = t->n_out;
+        d.NOB = S.NOB;
+        d.ystride = G.ystride;
+        d.n_slots = G.n_slots;
+        d.tiles32 = G.tiles32;
+        d.tiles16 = G.tiles16;
+        d.tile_off = G.tile_off;
+        d.conservative = t->spec.conservative;
+        gdev.push_back(d);
     }
+    if ((rc = dcopy(pl.get(), &pl->groups_dev, gdev))) return rc;
     if ((rc = dalloc(pl.get(), &pl->y1, pl->n_values))) return rc;
     if ((rc = dalloc(pl.get(), &pl->y2, pl->n_values))) return rc;
     if ((rc = dalloc(pl.get(), &pl->viol, 1))) return rc;
     HIP_TRY(hipMemset(pl->viol, 0, sizeof(unsigned long long)));
+    HIP_TRY(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
+    if ((rc = build_items(pl.get()))) return rc;
     *out = pl.release();
     return GD_OK;
 }
@@ -535,50 +674,58 @@ extern "C" int gd_plan_sizes(const gd_plan* pl, long long* n_cells, long long* n
 
 extern "C" void gd_plan_destroy(gd_plan* pl) { delete pl; }
 
-static StageArgs stage_args(const gd_plan* pl, const Group& G, int mode, int limit, const double* kscale,
-                            const double* gn, const double* gs, double* out, double dt, double* raw)
+extern "C" int gd_plan_set_variant(gd_plan* pl, int waves, int rows)
 {
-    const gd_tensor* t = G.t;
-    const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    if (waves != 4 && waves != 8) return fail(GD_EINVAL, "waves must be 4 or 8");
+    if (rows < 0) return fail(GD_EINVAL, "rows must be >= 0");
+    pl->waves = waves;
+    pl->rows = rows;
+    return build_items(pl);
+}
+
+extern "C" int gd_plan_variant(const gd_plan* pl, int* waves, int* rows, int* n_items, double* exec_flops)
+{
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    if (waves) *waves = pl->waves;
+    if (rows) *rows = pl->rows;
+    if (n_items) *n_items = pl->n_items;
+    if (exec_flops) *exec_flops = pl->exec_flops;
+    return GD_OK;
+}
+
+extern "C" int gd_plan_use_graph(gd_plan* pl, int enable)
+{
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    pl->use_graph = enable != 0;
+    if (!pl->use_graph) pl->drop_graph();
+    return GD_OK;
+}
+
+static int stage(const gd_plan* pl, hipStream_t s, int mode, int limit, int split, const double* kscale,
+                 const double* gn, const double* gs, double* out, double dt, double* raw)
+{
     StageArgs a{};
+    a.groups = pl->groups_dev;
+    a.n_groups = int(pl->groups.size());
+    a.n_tiles = pl->tiles32;
     a.mode = mode;
     a.limit = limit;
-    a.split = mixed ? 1 : 0;
-    a.Yf = mixed ? G.Yf : nullptr;
-    a.Yd = mixed ? nullptr : G.Yd;
-    a.rowscale = t->rowscale;
-    a.eslot = G.eslot;
-    a.perm = G.perm;
-    a.kscale = kscale ? kscale + G.cell0 : nullptr;
+    a.split = split;
+    a.kscale = kscale;
     a.gn = gn;
     a.gs = gs;
     a.out = out;
     a.raw = raw;
-    a.h = t->h;
-    a.colscale = t->colscale;
-    a.mfrag = G.mfrag;
-    a.mt = G.mt;
     a.viol = pl->viol;
     a.dt = dt;
-    a.n_slots = G.n_slots;
-    a.n_tiles = G.tiles32;
-    a.N = t->N;
-    a.k = t->k;
-    a.P = t->P;
-    a.KS = t->KS;
-    a.n_out = t->n_out;
-    a.ystride = G.ystride;
-    a.conservative = t->spec.conservative;
-    return a;
+    return launch_stage(a, s);
 }
 
-// the contraction of group G on stage state gs (the split path reads the fragments
-// the previous stage kernel wrote from gs)
-static int contract_group(gd_plan* pl, Group& G, const double* gs)
+// one contraction launch over every group on stage state gs (the split path reads
+// the fragments the previous stage kernel wrote from gs)
+static int contract(gd_plan* pl, hipStream_t s, const double* gs)
 {
-    const gd_tensor* t = G.t;
-    hipStream_t s = pl->stream;
-    int rc;
     hipEvent_t ev_end = nullptr;
     if (pl->timing) {
         KernelTimer& T = pl->timer;
@@ -592,42 +739,10 @@ static int contract_group(gd_plan* pl, Group& G, const double* gs)
         ev_end = T.ev[T.used].second;
         ++T.used;
     }
-    if (pl->prec == GD_PREC_MIXED_F16X3) {
-        MixedArgs ma{};
-        ma.frag = static_cast<const uint4*>(t->mixed.frag);
-        ma.iters = t->mixed.iters;
-        ma.iter_off = t->mixed.iter_off;
-        ma.iter_cnt = t->mixed.iter_cnt;
-        ma.scale = t->mixed.scale;
-        ma.slot_level = G.slot_level;
-        ma.theta = G.theta;
-        ma.mfrag = G.mfrag;
-        ma.mt = G.mt;
-        ma.Y = G.Yf;
-        ma.KS = t->KS;
-        ma.n_tiles = G.tiles32;
-        ma.n_slots = G.n_slots;
-        ma.P = t->P;
-        ma.ystride = G.ystride;
-        if ((rc = launch_contract_mixed(ma, s))) return rc;
-    } else {
-        F64Args fa{};
-        fa.frag = static_cast<const uint4*>(t->f64.frag);
-        fa.iters = t->f64.iters;
-        fa.iter_off = t->f64.iter_off;
-        fa.iter_cnt = t->f64.iter_cnt;
-        fa.slot_level = G.slot_level;
-        fa.theta = G.theta;
-        fa.perm = G.perm;
-        fa.g = gs;
-        fa.Y = G.Yd;
-        fa.KS = t->KS;
-        fa.n_tiles = G.tiles16;
-        fa.n_slots = G.n_slots;
-        fa.P = t->P;
-        fa.ystride = G.ystride;
-        if ((rc = launch_contract_fp64(fa, s))) return rc;
-    }
+    ContractArgs a{pl->groups_dev, pl->items, gs, pl->n_items};
+    int rc = (pl->prec == GD_PREC_MIXED_F16X3) ? launch_contract_mixed(a, pl->ksmax, pl->waves, s)
+                                               : launch_contract_fp64(a, pl->ksmax, pl->waves, s);
+    if (rc) return rc;
     if (ev_end) HIP_TRY(hipEventRecord(ev_end, s));
     return GD_OK;
 }
@@ -635,23 +750,50 @@ static int contract_group(gd_plan* pl, Group& G, const double* gs)
 extern "C" int gd_collision_rhs(gd_plan* pl, const double* g, const double* kscale, double* rhs, double* raw)
 {
     if (!pl || !g || !rhs) return fail(GD_EINVAL, "null argument");
-    long long rawoff = 0;
+    const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
+    hipStream_t s = pl->stream;
     int rc;
-    for (Group& G : pl->groups) {
-        const long long off = rawoff;
-        rawoff += (long long)G.C * G.t->n_out;
-        if (G.C == 0) continue;
-        const double* gs = g + G.val0;
-        if (pl->prec == GD_PREC_MIXED_F16X3) {
-            // split of the input state (no limiting: the state is read only)
-            StageArgs a = stage_args(pl, G, -1, 0, kscale, nullptr, gs, nullptr, 0.0, nullptr);
-            if ((rc = launch_stage(a, pl->stream))) return rc;
-        }
-        if ((rc = contract_group(pl, G, gs))) return rc;
-        StageArgs b = stage_args(pl, G, 0, 0, kscale, nullptr, gs, rhs + G.val0, 0.0, raw ? raw + off : nullptr);
-        b.split = 0;
-        if ((rc = launch_stage(b, pl->stream))) return rc;
+    // split of the input state (no limiting: the state is read only)
+    if (mixed && (rc = stage(pl, s, -1, 0, 1, kscale, nullptr, g, nullptr, 0.0, nullptr))) return rc;
+    if ((rc = contract(pl, s, g))) return rc;
+    return stage(pl, s, 0, 0, 0, kscale, nullptr, g, rhs, 0.0, raw);
+}
+
+// y1 = gn + dt L(gn); y2 = 3/4 gn + 1/4 (y1 + dt L(y1)); gn = 1/3 gn + 2/3 (y2 + dt L(y2)),
+// each stage limited (and split for the next contraction) as it is written
+static int step_launches(gd_plan* pl, hipStream_t s, double* g, const double* kscale, double dt)
+{
+    const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
+    int rc;
+    if ((rc = contract(pl, s, g))) return rc;
+    if ((rc = stage(pl, s, 1, 1, split, kscale, g, g, pl->y1, dt, nullptr))) return rc;
+    if ((rc = contract(pl, s, pl->y1))) return rc;
+    if ((rc = stage(pl, s, 2, 1, split, kscale, g, pl->y1, pl->y2, dt, nullptr))) return rc;
+    if ((rc = contract(pl, s, pl->y2))) return rc;
+    return stage(pl, s, 3, 1, split, kscale, g, pl->y2, g, dt, nullptr);
+}
+
+// capture one RK step on the plan's private stream (nothing runs while capturing)
+static int capture_step(gd_plan* pl, double* g, const double* kscale, double dt)
+{
+    pl->drop_graph();
+    HIP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+    int rc = step_launches(pl, pl->cap, g, kscale, dt);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(pl->cap, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
     }
+    if (e != hipSuccess) return fail(GD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(GD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    pl->graph.exec = exec;
+    pl->graph.g = g;
+    pl->graph.kscale = kscale;
+    pl->graph.dt = dt;
     return GD_OK;
 }
 
@@ -659,30 +801,19 @@ extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double d
                           long long* violations)
 {
     if (!pl || !g || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!std::isfinite(dt)) return fail(GD_EINVAL, "dt must be finite");
     int rc;
     hipStream_t s = pl->stream;
+    const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
     if ((rc = launch_fill_u64(pl->viol, 1, s))) return rc;
     // limiter on the start state (and its split for the first contraction)
-    for (Group& G : pl->groups) {
-        if (G.C == 0) continue;
-        StageArgs a = stage_args(pl, G, -1, 1, kscale, nullptr, g + G.val0, nullptr, dt, nullptr);
-        if ((rc = launch_stage(a, s))) return rc;
-    }
+    if ((rc = stage(pl, s, -1, 1, split, kscale, nullptr, g, nullptr, dt, nullptr))) return rc;
+    const bool graph = pl->use_graph && !pl->timing && n_steps > 0;
+    if (graph && !(pl->graph.exec && pl->graph.g == g && pl->graph.kscale == kscale && pl->graph.dt == dt))
+        if ((rc = capture_step(pl, g, kscale, dt))) return rc;
     for (int n = 0; n < n_steps; ++n) {
-        for (Group& G : pl->groups) {
-            if (G.C == 0) continue;
-            double* gn = g + G.val0;
-            double* y1 = pl->y1 + G.val0;
-            double* y2 = pl->y2 + G.val0;
-            // y1 = gn + dt L(gn); y2 = 3/4 gn + 1/4 (y1 + dt L(y1)); gn = 1/3 gn + 2/3 (y2 + dt L(y2)),
-            // each stage limited (and split for the next contraction) as it is written
-            if ((rc = contract_group(pl, G, gn))) return rc;
-            if ((rc = launch_stage(stage_args(pl, G, 1, 1, kscale, gn, gn, y1, dt, nullptr), s))) return rc;
-            if ((rc = contract_group(pl, G, y1))) return rc;
-            if ((rc = launch_stage(stage_args(pl, G, 2, 1, kscale, gn, y1, y2, dt, nullptr), s))) return rc;
-            if ((rc = contract_group(pl, G, y2))) return rc;
-            if ((rc = launch_stage(stage_args(pl, G, 3, 1, kscale, gn, y2, gn, dt, nullptr), s))) return rc;
-        }
+        if (graph) HIP_TRY(hipGraphLaunch(pl->graph.exec, s));
+        else if ((rc = step_launches(pl, s, g, kscale, dt))) return rc;
     }
     if (violations) {
         unsigned long long v = 0;
@@ -690,6 +821,99 @@ extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double d
         HIP_TRY(hipStreamSynchronize(s));
         *violations = (long long)v;
     }
+    return GD_OK;
+}
+
+// ---------------------------------------------------------------------------- autotuner
+// Times every contraction variant (4 or 8 waves per workgroup; 1, 2 or all row
+// blocks per work item) on the given state and keeps the fastest.  With a cache
+// file, a plan of the same shape reuses the stored choice without timing.
+static std::string tune_key(const gd_plan* pl)
+{
+    std::string k = pl->prec == GD_PREC_MIXED_F16X3 ? "mixed" : "fp64";
+    for (const Group& G : pl->groups) {
+        const gd_tensor* t = G.t;
+        k += ";" + std::to_string(t->N) + "x" + std::to_string(t->k) + "r" + std::to_string(t->R) + "c" +
+             std::to_string(G.C) + "b" + std::to_string(G.brackets.size());
+    }
+    return k;
+}
+
+extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* kscale, const char* cache_path,
+                                int* waves, int* rows)
+{
+    if (!pl || !g) return fail(GD_EINVAL, "null argument");
+    const std::string key = tune_key(pl);
+    int rc;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char line[4096];
+            int bw = 0, br = -1;
+            while (std::fgets(line, sizeof line, f)) {
+                char k[4000];
+                int w, r;
+                if (std::sscanf(line, "%3999s %d %d", k, &w, &r) == 3 && key == k) {
+                    bw = w;
+                    br = r;
+                }
+            }
+            std::fclose(f);
+            if ((bw == 4 || bw == 8) && br >= 0) {
+                if ((rc = gd_plan_set_variant(pl, bw, br))) return rc;
+                if (waves) *waves = bw;
+                if (rows) *rows = br;
+                return GD_OK;
+            }
+        }
+    }
+    hipStream_t s = pl->stream;
+    if (pl->prec == GD_PREC_MIXED_F16X3 && (rc = stage(pl, s, -1, 0, 1, kscale, nullptr, g, nullptr, 0.0, nullptr)))
+        return rc;
+    int nob = 1;
+    for (const Group& G : pl->groups)
+        nob = std::max(nob, pl->prec == GD_PREC_MIXED_F16X3 ? G.t->NOB : G.t->NOB16);
+    std::vector<std::pair<int, int>> cand;
+    for (int w : {4, 8})
+        for (int r : {1, 2, 0})
+            if (r == 0 || r < nob) cand.push_back({w, r});
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const bool timing = pl->timing;
+    pl->timing = false;
+    float best = 1e30f;
+    int bw = 4, br = 1;
+    rc = GD_OK;
+    for (auto& c : cand) {
+        if ((rc = gd_plan_set_variant(pl, c.first, c.second))) break;
+        if ((rc = contract(pl, s, g))) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(GD_EHIP, "event record"); break; }
+        for (int i = 0; i < 3 && !rc; ++i) rc = contract(pl, s, g);
+        if (rc) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(GD_EHIP, "event timing");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+            best = ms;
+            bw = c.first;
+            br = c.second;
+        }
+    }
+    pl->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if ((rc = gd_plan_set_variant(pl, bw, br))) return rc;
+    if (cache_path)
+        if (FILE* f = std::fopen(cache_path, "a")) {
+            std::fprintf(f, "%s %d %d\n", key.c_str(), bw, br);
+            std::fclose(f);
+        }
+    if (waves) *waves = bw;
+    if (rows) *rows = br;
     return GD_OK;
 }
 

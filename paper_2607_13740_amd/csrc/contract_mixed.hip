@@ -1,0 +1,171 @@
+// Split-FP16 contraction: T and the scaled state are each carried as FP16 hi + lo
+// halves; three 32x32x16 MFMA products (hi*hi, hi*lo, lo*hi) accumulate in FP32 per
+// segment, and the segment sums are weighted and accumulated in FP64.
+//
+// Tiles of 32 slots, row blocks of 32, K steps of 16.  A lane l holds
+// T[o = l%32][q = 16ks + 8(l/32) + j]; B lane l holds m[slot = l%32][q = 16ks + 8(l/32) + j];
+// D register r of lane l holds row 8(r/4) + 4(l/32) + r%4, column l%32.  An A
+// fragment holds the hi halves of the 64 lanes, then the lo halves.
+#include "contract_common.h"
+
+namespace gd {
+
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <int KS>
+struct MixedSeg {
+    const uint4* A;                 // first fragment of the segment in LDS, + lane
+    const uint4* bh;                // [KS]
+    const uint4* bl;
+    double w;                       // stage-2 weight of the lane's cell
+    double* Y;                      // [16]
+    template <int LO>
+    __device__ __forceinline__ void run()
+    {
+        floatx16 Z;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Z[r] = 0.0f;
+#pragma unroll
+        for (int ks = LO; ks < KS; ++ks) {
+            const half8_t xh = __builtin_bit_cast(half8_t, A[(ks - LO) * 128]);
+            const half8_t xl = __builtin_bit_cast(half8_t, A[(ks - LO) * 128 + 64]);
+            const half8_t mh = __builtin_bit_cast(half8_t, bh[ks]);
+            const half8_t ml = __builtin_bit_cast(half8_t, bl[ks]);
+            Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(xh, mh, Z, 0, 0, 0);
+            Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(xh, ml, Z, 0, 0, 0);
+            Z = __builtin_amdgcn_mfma_f32_32x32x16_f16(xl, mh, Z, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Y[r] = fma(w, (double)Z[r], Y[r]);
+    }
+};
+
+template <int W>
+struct MixedItem {
+    const GD_CONST GroupDev* gp;
+    int r, ob0, ob1, tile0;
+    uint4* buf0;
+    uint4* buf1;
+
+    template <int KS>
+    __device__ __forceinline__ void item()
+    {
+        constexpr int SEG = kSegMax;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const GD_GLOBAL uint4* frag = gptr(gp->frag);
+        const GD_CONST IterDesc* iters = cptr(gp->iters);
+        const GD_CONST float* scale = cptr(gp->scale);
+        const GD_GLOBAL uint4* mfrag = gptr(gp->mfrag);
+        const GD_GLOBAL double* theta = gptr(gp->theta);
+        const int n_tiles = gp->tiles32, n_slots = gp->n_slots, P = gp->P;
+        const int tile = tile0 + wave;
+        const bool tv = tile < n_tiles;
+        const int tcl = tv ? tile : n_tiles - 1;
+        const int slot = tile * 32 + (lane & 31);
+        const bool sv = tv && slot < n_slots;
+        const double th = (sv && theta) ? theta[slot] : 0.0;
+        uint4 bh[KS], bl[KS];
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const size_t base = ((size_t)(tcl * KS + ks) * 2) * 64 + lane;
+            bh[ks] = mfrag[base];
+            bl[ks] = mfrag[base + 64];
+        }
+        const GD_GLOBAL float* mtile = gptr(gp->mt) + (size_t)tcl * P * 32 + (lane & 31);
+        double Y[16];
+
+        // raw stage-2 inputs of an iteration (loads only, consumed one iteration later)
+        auto prefetch_w = [&](const IterDesc& d, float (&mp)[SEG], float (&sc)[SEG]) {
+#pragma unroll
+            for (int s = 0; s < SEG; ++s) {
+                const int p = (s < d.nseg) ? d.p[s] : 0;
+                sc[s] = scale[d.scale + p];
+                mp[s] = mtile[(size_t)p * 32];
+            }
+        };
+
+        // one iteration: compute d from rd while the fragments of dn stream into wr
+        auto body = [&](const IterDesc& d, const IterDesc& dn, const float (&mp)[SEG], const float (&sc)[SEG],
+                        float (&mpn)[SEG], float (&scn)[SEG], const uint4* rd, uint4* wr) {
+            dma_frags<W>(frag + (size_t)dn.frag * 128, wr, dn.nfrag, wave, lane);
+            prefetch_w(dn, mpn, scn);
+            int f = 0;
+#pragma unroll
+            for (int s = 0; s < SEG; ++s) {
+                if (s >= d.nseg) break;
+                MixedSeg<KS> seg{rd + f * 128 + lane, bh, bl, (double)mp[s] * (double)sc[s] * (d.delta ? th : 1.0),
+                                 Y};
+                pick_lo<KS, 0>(d.lo[s], seg);
+                f += KS - d.lo[s];
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        };
+
+        for (int ob = ob0; ob < ob1; ++ob) {
+            const int list = r * gp->NOB + ob;
+            const GD_CONST IterDesc* its = iters + cptr(gp->list_off)[list];
+            const int n_it = cptr(gp->list_cnt)[list];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) Y[i] = 0.0;
+            // descriptors are read two iterations ahead (every list ends with two sentinels)
+            IterDesc dA = its[0], dB = its[1];
+            float mp0[SEG], sc0[SEG], mp1[SEG], sc1[SEG];
+            dma_frags<W>(frag + (size_t)dA.frag * 128, buf0, dA.nfrag, wave, lane);
+            prefetch_w(dA, mp0, sc0);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            for (int i = 0; i < n_it; i += 2) {
+                const IterDesc dC = its[i + 2];
+                body(dA, dB, mp0, sc0, mp1, sc1, buf0, buf1);
+                if (i + 1 >= n_it) break;
+                const IterDesc dD = its[i + 3];
+                body(dB, dC, mp1, sc1, mp0, sc0, buf1, buf0);
+                dA = dC;
+                dB = dD;
+            }
+            if (sv) {
+                GD_GLOBAL float* dst = gptr(gp->Yf) + (size_t)slot * gp->ystride + ob * 32 + 4 * (lane >> 5);
+#pragma unroll
+                for (int r4 = 0; r4 < 4; ++r4) {
+                    float4 v = make_float4((float)Y[4 * r4], (float)Y[4 * r4 + 1], (float)Y[4 * r4 + 2],
+                                           (float)Y[4 * r4 + 3]);
+                    *reinterpret_cast<GD_GLOBAL float4*>(dst + 8 * r4) = v;
+                }
+            }
+        }
+    }
+};
+
+template <int KSMAX, int W>
+__global__ __launch_bounds__(64 * W) void k_contract_mixed(ContractArgs a)
+{
+    __shared__ uint4 buf0[kFragBudget * 128];
+    __shared__ uint4 buf1[kFragBudget * 128];
+    const int4 it = cptr(a.items)[blockIdx.x];
+    MixedItem<W> f{cptr(a.groups) + it.x, it.y, it.z & 0xffff, it.z >> 16, it.w, buf0, buf1};
+    dispatch_ks<KSMAX>(f.gp->KS, f);
+}
+
+template <int KSMAX, int W>
+static int launch(const ContractArgs& a, hipStream_t s)
+{
+    if (a.n_items == 0) return GD_OK;
+    hipLaunchKernelGGL((k_contract_mixed<KSMAX, W>), dim3(a.n_items), dim3(64 * W), 0, s, a);
+    HIP_TRY(hipGetLastError());
+    return GD_OK;
+}
+
+int launch_contract_mixed(const ContractArgs& a, int ksmax, int waves, hipStream_t s)
+{
+    if (waves != 4 && waves != 8) return fail(GD_EINVAL, "contraction workgroups have 4 or 8 waves");
+    const bool w4 = waves == 4;
+    if (ksmax <= 4) return w4 ? launch<4, 4>(a, s) : launch<4, 8>(a, s);
+    if (ksmax <= 6) return w4 ? launch<6, 4>(a, s) : launch<6, 8>(a, s);
+    if (ksmax <= 8) return w4 ? launch<8, 4>(a, s) : launch<8, 8>(a, s);
+    if (ksmax <= 12) return w4 ? launch<12, 4>(a, s) : launch<12, 8>(a, s);
+    return fail(GD_EUNSUPPORTED, "P too large for the mixed contraction");
+}
+
+} // namespace gd

@@ -25,16 +25,41 @@ int fail(int code, const std::string& msg);
 
 inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// Pointers read from the group table are generic; the kernels re-type them so that
+// read-only tables with uniform indices go through scalar loads (constant address
+// space) and the per-lane data through global (not flat) memory instructions.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GD_CONST __attribute__((address_space(4)))
+#define GD_GLOBAL __attribute__((address_space(1)))
+#else
+#define GD_CONST
+#define GD_GLOBAL
+#endif
+template <class T>
+__device__ __forceinline__ const GD_CONST T* cptr(const T* p)
+{
+    return (const GD_CONST T*)p;
+}
+template <class T>
+__device__ __forceinline__ GD_GLOBAL T* gptr(T* p)
+{
+    return (GD_GLOBAL T*)p;
+}
+
+
 // ------------------------------------------------------------------ schedules
-// One iteration of the contraction: a row block ob and up to kSegMax p values of
-// one part (a level, or the difference of two neighbouring levels).  Segment s
-// covers the K steps lo[s]..KS-1 (16 columns q each) of p[s] (hi[s] = KS-1); zero
-// blocks inside the range are stored as zero fragments, blocks before lo are
-// structural zeros.
-// Fragments of an iteration are contiguous, segment by segment, K step ascending.
-// Every level's list ends with two empty descriptors (nseg = 0, ob = -1) so that the
-// kernels can always read the descriptors two iterations ahead.
+// The contraction of one tensor level r and one row block ob is a list of
+// iterations.  An iteration carries up to kSegMax p values ("segments") of one part
+// (the level itself, or the difference of the next level and this one) whose
+// fragments together fit one LDS buffer of kFragBudget fragments of 2 KB.  Segment s
+// covers the K steps lo[s]..KS-1 (16 columns q each) of p[s]: blocks before lo are
+// structural zeros, zero blocks after it are stored as zero fragments.  Fragments
+// of an iteration are contiguous, segment by segment, K step ascending.  Every list
+// is followed by two empty descriptors (nseg = 0) so that the kernels can read the
+// descriptors two iterations ahead; a list with no fragment holds one empty
+// iteration.
 constexpr int kSegMax = 4;
+constexpr int kFragBudget = 12;
 struct IterDesc {
     int ob;
     int delta;           // 1: level-difference part, weighted by the cell's blend factor
@@ -52,80 +77,84 @@ struct IterDesc {
 // Device layouts of one tensor for one contraction precision.
 struct Schedule {
     const void* frag = nullptr;           // 2 KB fragments: split (hi 64 lanes, lo 64 lanes) or FP64 (4 K steps)
-    const IterDesc* iters = nullptr;      // all levels, concatenated
-    const int* iter_off = nullptr;        // [levels] first iteration of the level
-    const int* iter_cnt = nullptr;        // [levels] iterations of the level
-    const float* scale = nullptr;         // mixed: stage-2 factors
+    const IterDesc* iters = nullptr;      // all lists, concatenated
+    const int* list_off = nullptr;        // [levels * row blocks] first iteration of list (r, ob)
+    const int* list_cnt = nullptr;        // [levels * row blocks] iterations of the list
+    const float* scale = nullptr;         // split path: stage-2 factors
+    std::vector<long long> list_cost;     // host: fragments + iterations of every list
+    std::vector<long long> list_frags;    // host: fragments of every list
+    int NOB = 0;                          // row blocks
     long long frags = 0;                  // stored fragments (all levels)
     long long iters_total = 0;
 };
 
-// ------------------------------------------------------------------ kernel arguments
-struct MixedArgs {
+// One group of a plan as the kernels see it: the tensor of the group in the plan's
+// precision and the group's slot buffers.  Slots are the cells of the group sorted
+// by threshold bracket, each bracket padded to a multiple of 256 slots.
+struct GroupDev {
     const uint4* frag;
     const IterDesc* iters;
-    const int* iter_off;
-    const int* iter_cnt;
+    const int* list_off;
+    const int* list_cnt;
     const float* scale;
-    const int* slot_level;     // [n_slots] (nullptr: level 0)
-    const double* theta;       // [n_slots] blend weight (nullptr: 0)
-    const uint4* mfrag;
-    const float* mt;
-    float* Y;                  // [n_slots][ystride]
-    int KS, n_tiles, n_slots, P, ystride;
+    const double* h;           // [N] bin widths
+    const double* colscale;    // [P]   split path column factors
+    const double* rowscale;    // [NOB*32] split path row factors
+    const int* perm;           // [n_slots] slot -> cell of the group (-1: padding); nullptr: identity
+    const double* theta;       // [n_slots] blend weight; nullptr: 0
+    uint4* mfrag;              // split path B operands [tiles32][KS][hi|lo][64 lanes]
+    float* mt;                 // split path stage-2 weights [tiles32][P][32]
+    int* eslot;                // split path per-slot exponent [n_slots]
+    float* Yf;                 // split path raw vector [n_slots][ystride]
+    double* Yd;                // FP64 raw vector [n_slots][ystride]
+    long long val0;            // first state value of the group in the plan-wide arrays
+    long long raw0;            // first raw-vector value of the group
+    int cell0;                 // first cell of the group
+    int N, k, P, KS, n_out, NOB, ystride;
+    int n_slots, tiles32, tiles16;
+    int tile_off;              // first 32-slot tile of the group in the stage launch
+    int conservative;
 };
 
-struct F64Args {
-    const uint4* frag;
-    const IterDesc* iters;
-    const int* iter_off;
-    const int* iter_cnt;
-    const int* slot_level;
-    const double* theta;
-    const int* perm;
-    const double* g;           // caller state
-    double* Y;                 // [n_slots][ystride]
-    int KS, n_tiles, n_slots, P, ystride;
+// One contraction workgroup: {group, level, ob0 | ob1 << 16, first tile}.  The
+// workgroup's waves take consecutive tiles (32 slots split path, 16 slots FP64) and
+// run the lists (level, ob0..ob1-1) of the group's tensor.
+struct ContractArgs {
+    const GroupDev* groups;
+    const int4* items;
+    const double* g;           // FP64 path: plan-wide stage state (cell order)
+    int n_items;
 };
 
-// One kernel per RK stage boundary, one workgroup per tile of 32 slots:
+// One kernel per RK stage boundary over every group of a plan, one workgroup per
+// tile of 32 slots:
 //  1. (mode >= 0) fluxes from the raw vector Y, L (Eq. evo) and, for modes 1-3, the
 //     SSP-RK3 stage combination (Eq. RK3); mode -1 takes the state gs as it is;
 //  2. (limit) the scaling limiter on the new state, written back;
 //  3. (split) the per-slot scale and the split FP16 B operands / FP32 weights of the
 //     new state for the next contraction.
+// State pointers are plan-wide; every group adds its own offsets.
 struct StageArgs {
+    const GroupDev* groups;
+    int n_groups;
+    int n_tiles;               // 32-slot tiles over all groups
     int mode;                  // -1 none, 0: out = L, 1..3: RK stage into out
     int limit, split;
-    const float* Yf;           // split path raw vector (scaled)   or nullptr
-    const double* Yd;          // FP64 raw vector                 or nullptr
-    const double* rowscale;
-    int* eslot;                // per-slot exponent: read for Y, then rewritten by the split
-    const int* perm;
     const double* kscale;      // [cells] or nullptr
-    const double* gn;          // RK base state (cell order)
+    const double* gn;          // RK base state
     const double* gs;          // stage input state
     double* out;               // new state (or L); mode -1 with limit: gs itself
     double* raw;               // optional FP64 raw output [cells][n_out]
-    const double* h;
-    const double* colscale;
-    uint4* mfrag;
-    float* mt;
     unsigned long long* viol;
     double dt;
-    int n_slots, n_tiles, N, k, P, KS, n_out, ystride, conservative;
 };
 
 // ------------------------------------------------------------------ launchers
 int launch_stage(const StageArgs& a, hipStream_t s);
 int launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
 int launch_project(const double* samples, const double* wP, double* coef, int C, int N, int k, hipStream_t s);
-int launch_contract_mixed(const MixedArgs& a, hipStream_t s);
-int launch_contract_fp64(const F64Args& a, hipStream_t s);
-// p segments per iteration used by the contraction kernels for a given count of
-// 16-column K steps; the schedules are built with the same number
-int segs_per_iter(int KS);
-// cells per contraction workgroup (row blocks of 32: split path; 16: FP64 path)
-int slots_per_wg(int rows);
+// ksmax: largest KS of the plan; waves: 4 or 8 per workgroup
+int launch_contract_mixed(const ContractArgs& a, int ksmax, int waves, hipStream_t s);
+int launch_contract_fp64(const ContractArgs& a, int ksmax, int waves, hipStream_t s);
 
 } // namespace gd

@@ -87,111 +87,140 @@ __global__ __launch_bounds__(256) void k_project(const double* samples, const do
 }
 
 // ---------------------------------------------------------------------------
-// Fused stage kernel (see StageArgs), 256 threads per tile of 32 slots.  The new
-// state of the tile is staged in LDS (rows padded to P+1 doubles against bank
-// conflicts) so that the split fragments and weights are written coalesced.
+// Fused stage kernel (see StageArgs), 256 threads per tile of 32 slots of one group.
+// With the split on, phase 1 stages the scaled new state h_j g_q colscale_q of the
+// tile in LDS (rows padded to P+1 doubles against bank conflicts) and collects the
+// largest binary exponent of every slot, so that the FP16 fragments and FP32 weights
+// are written coalesced in phase 2.
 constexpr int kStageMaxP = 192;
 
 __global__ __launch_bounds__(256) void k_stage(StageArgs a)
 {
     __shared__ double st[32 * (kStageMaxP + 1)];
-    __shared__ int sexp[32];
-    const int tile = blockIdx.x, tid = threadIdx.x;
-    const int K1 = a.k + 1, P = a.P, LD = P + 1;
+    __shared__ int smax[32];
+    const GD_CONST GroupDev* groups = cptr(a.groups);
+    int gi = 0;
+    while (gi + 1 < a.n_groups && (int)blockIdx.x >= groups[gi + 1].tile_off) ++gi;
+    const GD_CONST GroupDev* G = groups + gi;
+    const int tile = (int)blockIdx.x - G->tile_off, tid = threadIdx.x;
+    const int N = G->N, k = G->k, K1 = k + 1, P = G->P, LD = P + 1, n_out = G->n_out;
+    const int n_slots = G->n_slots, ystride = G->ystride;
+    const bool conservative = G->conservative != 0;
+    const GD_CONST double* h = cptr(G->h);
+    const GD_GLOBAL double* cs = gptr(G->colscale);
+    const GD_CONST double* rowscale = cptr(G->rowscale);
+    const GD_GLOBAL int* perm = gptr(G->perm);
+    const GD_GLOBAL float* Yf = gptr(G->Yf);
+    const GD_GLOBAL double* Yd = gptr(G->Yd);
+    GD_GLOBAL int* eslot = gptr(G->eslot);
+    const GD_GLOBAL double* kscale = a.kscale ? gptr(a.kscale) + G->cell0 : nullptr;
+    const GD_GLOBAL double* gn = a.gn ? gptr(a.gn) + G->val0 : nullptr;
+    const GD_GLOBAL double* gs = gptr(a.gs) + G->val0;
+    GD_GLOBAL double* out = a.out ? gptr(a.out) + G->val0 : nullptr;
+    GD_GLOBAL double* raw = a.raw ? gptr(a.raw) + G->raw0 : nullptr;
+    if (a.split && tid < 32) smax[tid] = INT_MIN;
+    if (a.split) __syncthreads();
 
     // ---- phase 1: one task per (slot, bin)
     int viol = 0;
-    for (int t = tid; t < 32 * a.N; t += 256) {
-        const int sl = t / a.N, j = t - sl * a.N;
+    for (int t = tid; t < 32 * N; t += 256) {
+        const int sl = t / N, j = t - sl * N;
         const int s = tile * 32 + sl;
-        const int c = (s < a.n_slots) ? (a.perm ? a.perm[s] : s) : -1;
+        const int c = (s < n_slots) ? (perm ? perm[s] : s) : -1;
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         if (c >= 0) {
             const size_t base = (size_t)c * P + j * K1;
             if (a.mode < 0) {
-                for (int i = 0; i < K1; ++i) v[i] = a.gs[base + i];
+                for (int i = 0; i < K1; ++i) v[i] = gs[base + i];
             } else {
-                double fac = a.kscale ? a.kscale[c] : 1.0;
-                if (a.Yf) fac = ldexp(fac, 2 * a.eslot[s]);
+                double fac = kscale ? kscale[c] : 1.0;
+                if (Yf) fac = ldexp(fac, 2 * eslot[s]);
                 auto row = [&](int o) -> double {
-                    if (a.Yf) return (double)a.Yf[(size_t)s * a.ystride + o] * a.rowscale[o] * fac;
-                    return a.Yd[(size_t)s * a.ystride + o] * fac;
+                    if (Yf) return (double)Yf[(size_t)s * ystride + o] * rowscale[o] * fac;
+                    return Yd[(size_t)s * ystride + o] * fac;
                 };
                 const double Fl = (j == 0) ? 0.0 : row(j - 1);
-                const double Fr = (j + 1 < a.N) ? row(j) : (a.conservative ? 0.0 : row(a.N - 1));
-                const int vbase = (a.N - 1) + (a.conservative ? 0 : 1);
-                const double hj = a.h[j];
-                if (a.raw) {
-                    double* rw = a.raw + (size_t)c * a.n_out;
+                const double Fr = (j + 1 < N) ? row(j) : (conservative ? 0.0 : row(N - 1));
+                const int vbase = (N - 1) + (conservative ? 0 : 1);
+                const double hj = h[j];
+                if (raw) {
+                    GD_GLOBAL double* rw = raw + (size_t)c * n_out;
                     if (j >= 1) rw[j - 1] = Fl;
-                    if (j == a.N - 1 && !a.conservative) rw[a.N - 1] = Fr;
+                    if (j == N - 1 && !conservative) rw[N - 1] = Fr;
                 }
                 for (int i = 0; i < K1; ++i) {
-                    const double V = (i == 0) ? 0.0 : row(vbase + j * a.k + i - 1);
-                    if (a.raw && i > 0) a.raw[(size_t)c * a.n_out + vbase + j * a.k + i - 1] = V;
+                    const double V = (i == 0) ? 0.0 : row(vbase + j * k + i - 1);
+                    if (raw && i > 0) raw[(size_t)c * n_out + vbase + j * k + i - 1] = V;
                     const double sgn = (i & 1) ? -1.0 : 1.0;
                     const double L = (2.0 * i + 1.0) / hj * (V - Fr + sgn * Fl);
                     switch (a.mode) {
                     case 0: v[i] = L; break;
-                    case 1: v[i] = a.gs[base + i] + a.dt * L; break;
-                    case 2: v[i] = 0.75 * a.gn[base + i] + 0.25 * (a.gs[base + i] + a.dt * L); break;
-                    default: v[i] = a.gn[base + i] / 3.0 + 2.0 / 3.0 * (a.gs[base + i] + a.dt * L); break;
+                    case 1: v[i] = gs[base + i] + a.dt * L; break;
+                    case 2: v[i] = 0.75 * gn[base + i] + 0.25 * (gs[base + i] + a.dt * L); break;
+                    default: v[i] = gn[base + i] / 3.0 + 2.0 / 3.0 * (gs[base + i] + a.dt * L); break;
                     }
                 }
             }
-            if (a.limit) viol += limit_bin(a.k, v);
+            if (a.limit) viol += limit_bin(k, v);
             if (a.mode >= 0 || a.limit) {
-                double* o = (a.mode >= 0) ? a.out : const_cast<double*>(a.gs);
+                GD_GLOBAL double* o = (a.mode >= 0) ? out : const_cast<GD_GLOBAL double*>(gs);
                 for (int i = 0; i < K1; ++i) o[base + i] = v[i];
             }
         }
-        if (a.split)
-            for (int i = 0; i < K1; ++i) st[sl * LD + j * K1 + i] = v[i];
+        if (a.split) {
+            int emax = INT_MIN;
+            for (int i = 0; i < K1; ++i) {
+                const int q = j * K1 + i;
+                const double u = h[j] * v[i] * cs[q];
+                st[sl * LD + q] = u;
+                if (u != 0.0) {
+                    int E;
+                    frexp(u, &E);
+                    emax = max(emax, E);
+                }
+            }
+            if (emax != INT_MIN) atomicMax(&smax[sl], emax);
+        }
     }
     if (viol) atomicAdd(a.viol, (unsigned long long)viol);
     if (!a.split) return;
     __syncthreads();
-    // ---- phase 2: per-slot exponent, then coalesced fragments and weights
+    // ---- phase 2: per-slot exponent e with max_q |h_j g_q c_q| 2^-e in [64, 128),
+    // then the fragments and weights, coalesced
     if (tid < 32) {
-        // per-slot scale: max_q |h_j g_q c_q| 2^-e in [64, 128)
-        double mx = 0.0;
-        for (int q = 0; q < P; ++q) mx = fmax(mx, fabs(a.h[q / K1] * st[tid * LD + q] * a.colscale[q]));
-        int e = 0;
-        if (mx > 0.0) {
-            int E;
-            frexp(mx, &E);
-            e = E - 7;
-        }
-        sexp[tid] = e;
+        const int e = (smax[tid] == INT_MIN) ? 0 : smax[tid] - 7;
+        smax[tid] = e;
         const int s = tile * 32 + tid;
-        if (s < a.n_slots) a.eslot[s] = e;
+        if (s < n_slots) eslot[s] = e;
     }
     __syncthreads();
-    for (int t = tid; t < a.KS * 64; t += 256) {
+    const int KS = G->KS;
+    GD_GLOBAL uint4* mfrag = gptr(G->mfrag);
+    for (int t = tid; t < KS * 64; t += 256) {
         const int ks = t >> 6, lane = t & 63, sl = lane & 31, hh = lane >> 5;
         half8_t hi, lo;
         for (int jj = 0; jj < 8; ++jj) {
             const int q = ks * 16 + hh * 8 + jj;
             float m = 0.0f;
-            if (q < P) m = (float)ldexp(a.h[q / K1] * st[sl * LD + q] * a.colscale[q], -sexp[sl]);
+            if (q < P) m = (float)ldexp(st[sl * LD + q], -smax[sl]);
             const _Float16 mh = (_Float16)m;
             hi[jj] = mh;
             lo[jj] = (_Float16)(m - (float)mh);
         }
-        const size_t base = ((size_t)(tile * a.KS + ks) * 2) * 64 + lane;
-        a.mfrag[base] = __builtin_bit_cast(uint4, hi);
-        a.mfrag[base + 64] = __builtin_bit_cast(uint4, lo);
+        const size_t base = ((size_t)(tile * KS + ks) * 2) * 64 + lane;
+        mfrag[base] = __builtin_bit_cast(uint4, hi);
+        mfrag[base + 64] = __builtin_bit_cast(uint4, lo);
     }
+    GD_GLOBAL float* mt = gptr(G->mt);
     for (int t = tid; t < P * 32; t += 256) {
         const int q = t >> 5, sl = t & 31;
-        a.mt[((size_t)tile * P + q) * 32 + sl] = (float)ldexp(a.h[q / K1] * st[sl * LD + q] * a.colscale[q], -sexp[sl]);
+        mt[((size_t)tile * P + q) * 32 + sl] = (float)ldexp(st[sl * LD + q], -smax[sl]);
     }
 }
 
 int launch_stage(const StageArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return GD_OK;
-    if (a.P > kStageMaxP) return fail(GD_EUNSUPPORTED, "P too large for the stage kernel");
     hipLaunchKernelGGL(k_stage, dim3(a.n_tiles), dim3(256), 0, s, a);
     HIP_TRY(hipGetLastError());
     return GD_OK;

@@ -86,6 +86,12 @@ def lib():
             "gd_projection_points": ([_VP, _DP], ctypes.c_int),
             "gd_project": ([_VP, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
             "gd_plan_timing": ([_VP, ctypes.c_int], ctypes.c_int),
+            "gd_plan_set_variant": ([_VP, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+            "gd_plan_variant": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int), _DP], ctypes.c_int),
+            "gd_plan_autotune": ([_VP, _VP, _VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+            "gd_plan_use_graph": ([_VP, ctypes.c_int], ctypes.c_int),
             "gd_plan_contraction_time": ([_VP, _DP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_last_error": ([], ctypes.c_char_p),
         }
@@ -238,6 +244,28 @@ class Plan:
 
     def timing(self, enable=True):
         _check(lib().gd_plan_timing(self.h, int(bool(enable))))
+
+    def set_variant(self, waves=4, rows=1):
+        """Contraction variant: waves per workgroup (4 or 8), row blocks per item (0 = all)."""
+        _check(lib().gd_plan_set_variant(self.h, int(waves), int(rows)))
+
+    def variant(self):
+        w, r, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        f = ctypes.c_double()
+        _check(lib().gd_plan_variant(self.h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(n), ctypes.byref(f)))
+        return {"waves": w.value, "rows": r.value, "n_items": n.value, "exec_flops": f.value}
+
+    def autotune(self, g, kscale=None, cache_path=None):
+        """Time every contraction variant on state g and keep the fastest."""
+        _dev64(g, self.n_values, "g")
+        _dev64(kscale, self.n_cells, "kscale")
+        w, r = ctypes.c_int(), ctypes.c_int()
+        cp = cache_path.encode() if cache_path else None
+        _check(lib().gd_plan_autotune(self.h, _ptr(g), _ptr(kscale), cp, ctypes.byref(w), ctypes.byref(r)))
+        return {"waves": w.value, "rows": r.value}
+
+    def use_graph(self, enable=True):
+        _check(lib().gd_plan_use_graph(self.h, int(bool(enable))))
 
     def contraction_time(self):
         """(total ms, launches) of the contraction kernels since timing was enabled."""

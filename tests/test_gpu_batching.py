@@ -1,0 +1,211 @@
+"""GPU tests of the batching layer: uneven batches of several (bins, order) groups in
+one contraction launch, the contraction variants, the autotuner and the captured
+RK step.
+
+ * every contraction variant (waves per workgroup, row blocks per work item)
+   accumulates in the same order, so results must be bit-identical;
+ * an uneven batch of the twelve (bins, order) shapes is checked group by group
+   against the oracle (FP64: 1e-12, split FP16: 1e-6 per-cell normwise);
+ * the captured RK step (a HIP graph replayed once per step) must reproduce the
+   launch-by-launch step bit for bit, on every replay, with other work between.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2607_13740_amd import gracedg as G  # noqa: E402
+from paper_2607_13740_amd import workloads as W  # noqa: E402
+
+DEV = "cuda:0"
+VARIANTS = [(4, 1), (4, 2), (4, 0), (8, 1), (8, 2), (8, 0)]
+
+
+def _eps(Yg, Yo):
+    return np.max(np.abs(Yg - Yo), axis=1) / np.max(np.abs(Yo), axis=1)
+
+
+def _cells(O, cfg, idx, p):
+    if len(idx) == 0:
+        return np.zeros((0, cfg.P))
+    return np.stack([O.project(cfg, lambda x, c=c: W.lognormal_density(x, p["mu"][c], p["sigma"][c], p["mass"][c]))
+                     for c in idx])
+
+
+def _raw(plan, g, ks=None):
+    raw = torch.zeros(plan.n_raw, dtype=torch.float64, device=DEV)
+    plan.collision_rhs(g, kscale=ks, raw=raw)
+    torch.cuda.synchronize()
+    return raw
+
+
+def _level_case(O):
+    lv = W.VFRAG_LEVELS
+    N, k, C = 12, 3, 600
+    t = G.Tensor(N, k, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=lv, conservative=True)
+    cfg = O.Config(N=N, k=k, xmin=1e-4, xmax=1e8, kernel="ballistic", frag="powerlaw", conservative=True, levels=lv)
+    rng = np.random.default_rng(31)
+    vf = rng.uniform(0.3, 1.0, C)
+    g = np.stack([O.project(cfg, lambda x, mu=mu: W.lognormal_density(x, mu, 1.0, 1.0))
+                  for mu in rng.uniform(np.log(30.0), np.log(3000.0), C)])
+    ks = np.exp(0.5 * rng.standard_normal(C))
+    return t, cfg, g, ks, vf
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_variants_are_bit_identical(oracle, prec):
+    O = oracle
+    t, cfg, g, ks, vf = _level_case(O)
+    C = len(g)
+    plan = G.Plan(t, C, precision=prec, vfrag=vf)
+    gd = torch.tensor(g, device=DEV).view(-1)
+    ksd = torch.tensor(ks, device=DEV)
+    ref = None
+    for w, r in VARIANTS:
+        print(f"variant {prec} waves={w} rows={r}", flush=True)
+        plan.set_variant(w, r)
+        v = plan.variant()
+        assert v["waves"] == w and v["rows"] == r and v["n_items"] > 0
+        raw = _raw(plan, gd, ksd)
+        if ref is None:
+            ref = raw.clone()
+            idx = np.arange(0, C, 37)
+            Yo, _, _ = O.rhs(cfg, g[idx], kscale=ks[idx], vfrag=vf[idx])
+            tol = 1e-12 if prec == "fp64" else 1e-6
+            assert _eps(raw.view(C, -1)[idx].cpu().numpy(), Yo).max() <= tol
+        else:
+            assert torch.equal(raw, ref), (w, r)
+
+
+def _uneven(O, counts, kernel="additive"):
+    w = W.WORKLOADS["c4_uneven"]
+    p = W.lognormal_cells(int(sum(counts)), 2)
+    tensors, cfgs, states = [], [], []
+    c0 = 0
+    for (N, k), n in zip(w.groups, counts):
+        tensors.append(G.Tensor(N, k, w.x_min, w.x_max, kernel=kernel, frag=w.frag, levels=w.levels,
+                                conservative=w.conservative))
+        cfg = O.Config(N=N, k=k, xmin=w.x_min, xmax=w.x_max, kernel=kernel, frag=w.frag,
+                       conservative=w.conservative, vfrag=w.levels[0])
+        cfgs.append(cfg)
+        states.append(_cells(O, cfg, range(c0, c0 + n), p))
+        c0 += n
+    return tensors, cfgs, states
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_uneven_batch_matches_oracle(oracle, prec):
+    """All twelve (bins, order) shapes, P = 32..192, in one plan with uneven cell
+    counts (one group empty); each group's raw flux vectors against the oracle."""
+    O = oracle
+    counts = [7, 33, 0, 40, 5, 17, 1, 9, 3, 2, 31, 4]
+    tensors, cfgs, states = _uneven(O, counts)
+    plan = G.Plan(tensors, counts, precision=prec)
+    g = np.concatenate([s.reshape(-1) for s in states if s.size])
+    raw = _raw(plan, torch.tensor(g, device=DEV)).cpu().numpy()
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    off = 0
+    for cfg, s, n in zip(cfgs, states, counts):
+        if n == 0:
+            continue
+        Yo, _, _ = O.rhs(cfg, s)
+        Yg = raw[off:off + n * cfg.n_out].reshape(n, -1)
+        off += n * cfg.n_out
+        assert _eps(Yg, Yo).max() <= tol, (cfg.N, cfg.k, _eps(Yg, Yo).max())
+    assert off == raw.size
+    for w, r in VARIANTS[1:]:
+        plan.set_variant(w, r)
+        assert np.array_equal(_raw(plan, torch.tensor(g, device=DEV)).cpu().numpy(), raw), (w, r)
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_graph_replays_match_eager_steps(oracle, prec):
+    """The captured step against the launch-by-launch step: several calls, every
+    replay compared, with unrelated device work and host synchronisation between,
+    and a change of dt (a new capture) in the middle."""
+    O = oracle
+    t, cfg, g, ks, vf = _level_case(O)
+    C = len(g)
+    g, _ = O.limit(cfg, g)
+    # a step the oracle runs for 8 steps on these states without a limiter violation
+    # (1/50 of the outflow bound of Eq. dt over all cells; 1/20 of it already diverges)
+    dt = 2e-6
+    ksd = torch.tensor(ks, device=DEV)
+    pg = G.Plan(t, C, precision=prec, vfrag=vf)
+    pe = G.Plan(t, C, precision=prec, vfrag=vf)
+    pe.use_graph(False)
+    a = torch.tensor(g, device=DEV).view(-1)
+    b = a.clone()
+    junk = torch.zeros(1 << 20, device=DEV)
+    for n, d in ((1, dt), (2, dt), (1, 0.5 * dt), (3, 0.5 * dt)):
+        va = pg.rk_step(a, d, n, kscale=ksd, count_violations=True)
+        junk += 1.0
+        torch.cuda.synchronize()
+        vb = pe.rk_step(b, d, n, kscale=ksd, count_violations=True)
+        assert bool(torch.isfinite(a).all())
+        assert torch.equal(a, b), (n, d)
+        assert va == vb
+    assert float(junk[0]) == 4.0
+
+
+def test_autotune_keeps_results_and_uses_cache(oracle, tmp_path):
+    O = oracle
+    t, cfg, g, ks, vf = _level_case(O)
+    C = len(g)
+    gd = torch.tensor(g, device=DEV).view(-1)
+    ksd = torch.tensor(ks, device=DEV)
+    plan = G.Plan(t, C, precision="mixed", vfrag=vf)
+    ref = _raw(plan, gd, ksd)
+    cache = str(tmp_path / "tune.txt")
+    choice = plan.autotune(gd, kscale=ksd, cache_path=cache)
+    assert (choice["waves"], choice["rows"]) in VARIANTS
+    assert torch.equal(_raw(plan, gd, ksd), ref)
+    lines = open(cache).read().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("mixed;12x3r8c600")
+    # a second plan of the same shape takes the stored choice (the file is not extended)
+    p2 = G.Plan(t, C, precision="mixed", vfrag=vf)
+    assert p2.autotune(gd, kscale=ksd, cache_path=cache) == choice
+    assert open(cache).read().splitlines() == lines
+    v = p2.variant()
+    assert (v["waves"], v["rows"]) == (choice["waves"], choice["rows"])
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_full_size_uneven_workload_sampled(oracle, prec):
+    """The uneven batch at full size (100000 cells over the twelve shapes) in the
+    benchmark's launch configuration; sampled cells of every group against the oracle."""
+    O = oracle
+    w = W.WORKLOADS["c4_uneven"]
+    counts, order = W.uneven_groups(w)
+    p = W.lognormal_cells(w.cells, w.seed)
+    tensors, parts, cfgs = [], [], []
+    c0 = 0
+    for (N, k), n in zip(w.groups, counts):
+        t = G.Tensor(N, k, w.x_min, w.x_max, kernel=w.kernel, frag=w.frag, levels=w.levels,
+                     conservative=w.conservative)
+        ids = order[c0:c0 + n]
+        c0 += n
+        sub = {key: v[ids] for key, v in p.items()}
+        smp = torch.tensor(W.samples(w, t.projection_points(), cells=n, params=sub), device=DEV)
+        parts.append(t.project(smp).reshape(-1))
+        tensors.append(t)
+        cfgs.append(O.Config(N=N, k=k, xmin=w.x_min, xmax=w.x_max, kernel=w.kernel, frag=w.frag,
+                             conservative=w.conservative, vfrag=w.levels[0]))
+    g = torch.cat(parts)
+    del parts
+    plan = G.Plan(tensors, counts, precision=prec)
+    raw = _raw(plan, g)
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    rng = np.random.default_rng(11)
+    voff = roff = 0
+    for t, cfg, n in zip(tensors, cfgs, counts):
+        P, no = cfg.P, cfg.n_out
+        idx = rng.choice(n, 3, replace=False)
+        idx[0] = n - 1
+        gs = g[voff:voff + n * P].view(n, P)[idx].cpu().numpy()
+        Yg = raw[roff:roff + n * no].view(n, no)[idx].cpu().numpy()
+        Yo, _, _ = O.rhs(cfg, gs)
+        assert _eps(Yg, Yo).max() <= tol, (cfg.N, cfg.k)
+        voff += n * P
+        roff += n * no

@@ -88,8 +88,9 @@ def time_steps(plan, g, w, ks, steps, warmup):
     plan.timing(True)
     plan.rk_step(g, w.dt, max(2, steps // 4), kscale=ks)
     kms, launches = plan.contraction_time()
+    sms, slaunches = plan.stage_time()
     plan.timing(False)
-    return (t1 - t0) * 1e3 / steps, kms / max(1, launches), launches
+    return (t1 - t0) * 1e3 / steps, kms / max(1, launches), launches, sms / max(1, slaunches)
 
 
 def cpu_baseline(w, params, seconds):
@@ -176,10 +177,11 @@ def main():
         plan = G.Plan(tensors, counts, precision=prec, vfrag=vf)
         g = g0.clone()
         tune = plan.autotune(g, kscale=ks)
-        ms, kms, launches = time_steps(plan, g, w, ks, args.steps, args.warmup)
-        res[prec] = {"ms_per_step": ms, "kernel_ms": kms, "launches": launches, "plan": plan,
+        ms, kms, launches, sms = time_steps(plan, g, w, ks, args.steps, args.warmup)
+        res[prec] = {"ms_per_step": ms, "kernel_ms": kms, "launches": launches, "plan": plan, "stage_ms": sms,
                      "variant": plan.variant(), "tune": tune}
         print(f"# {prec}: {ms:.3f} ms/step, contraction {kms:.4f} ms/launch over {launches} launches, "
+              f"stage kernel {sms:.4f} ms/launch, "
               f"variant {res[prec]['variant']}", file=sys.stderr, flush=True)
         # mass drift over the run (FP64 bookkeeping of the bin masses), cell by cell
         drift, voff = 0.0, 0
@@ -243,6 +245,7 @@ def main():
                      "executed_mfma_flops_per_launch": exec_flops,
                      "executed_mfma_tflops": exec_flops / (mixed["kernel_ms"] * 1e-3) / 1e12,
                      "mfma_utilisation": exec_flops / (mixed["kernel_ms"] * 1e-3) / 1e12 / PEAK_F16_TFLOPS},
+        "stage_kernel_ms": mixed["stage_ms"],
         "tensor_init_s": t_init,
         "mass_drift_mixed": mixed["mass_drift"],
         "accuracy_vs_fp64_gpu": acc,

@@ -139,6 +139,8 @@ int gd_plan_create(const gd_tensor* const* tensors, const int* cells_per_group, 
                    int precision, const double* vfrag, void* stream, gd_plan** out);
 /* total cells and total state doubles (sum over groups of cells * P) */
 int gd_plan_sizes(const gd_plan* plan, long long* n_cells, long long* n_values);
+/* total bins (sum over groups of cells * bins): the length of a limiter-factor array */
+int gd_plan_bins(const gd_plan* plan, long long* n_bins);
 /* stored contraction fragments of a group's tensor (split-FP16 and FP64 layouts,
  * all levels) and the group's slot count (cells plus bracket padding) */
 int gd_plan_schedule_stats(const gd_plan* plan, int group, long long* frags_mixed, long long* frags_fp64,
@@ -167,6 +169,43 @@ int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, doubl
 int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_steps, long long* violations);
 
 /*
+ * Reverse mode (the adjoint of gd_rk_step), FP64 whatever the plan's precision.
+ *
+ * gd_rk_forward -- gd_rk_step (same steps, limiter placement and results) that also
+ *   records what the reverse pass needs, launch by launch (no graph):
+ *     states : device, (1 + 3 n_steps) states of n_values doubles: [0] the limited
+ *              start state, then per step n the limited stage outputs y1, y2 and
+ *              g_{n+1} at [3n+1], [3n+2], [3n+3];
+ *     gammas : device, (1 + 3 n_steps) arrays of n_bins doubles (n_bins = sum over
+ *              groups of cells * bins, cell-major per group): the factor the limiter
+ *              applied to each bin when it wrote the state of the same index.
+ *   g is overwritten with the final state, as gd_rk_step does.
+ * gd_adjoint -- the vector-Jacobian product of the whole gd_rk_forward call:
+ *     lam      : device, state layout; in: dLoss/dg(final), out: dLoss/dg(input)
+ *                (the caller's state before the start limiter);
+ *     dkscale  : device [n_cells] or NULL: dLoss/dkscale (written);
+ *     dvfrag   : device [n_cells] or NULL: dLoss/dv_frag through the blend weight of
+ *                Eq. (level blend), 0 outside the level table (written);
+ *   states, gammas, kscale, dt and n_steps as given to gd_rk_forward.  The steps run
+ *   backwards through the stage combinations of Eq. RK3, the limiter of Eq. gamma
+ *   (envelope theorem at the minimiser of the bin polynomial; a flattened bin passes
+ *   nothing to its higher coefficients) and the collision operator: with the raw
+ *   flux vector Y_o = sum_{p<=q} Tf[o][p][q] g_p g_q (Sec. 3.3), a cotangent nu on Y
+ *   gives dg_p = sum_{q>=p} M_p[q] g_q + sum_{q<=p} M_q[p] g_q, M_p[q] = sum_o nu_o
+ *   Tf[o][p][q], computed on the FP64 MFMA from a transposed copy of the tensor.
+ *   The first call on a plan allocates the reverse-mode workspace (synchronous).
+ * gd_collision_vjp -- one right-hand-side product: grad += (dL/dg)^T mu at state g,
+ *   dkscale/dvfrag (device [n_cells] or NULL) written with d(mu . L)/dkscale and
+ *   d(mu . L)/dv_frag.  mu, grad: device, state layout (mu read only).
+ */
+int gd_rk_forward(gd_plan* plan, double* g, const double* kscale, double dt, int n_steps, double* states,
+                  double* gammas, long long* violations);
+int gd_adjoint(gd_plan* plan, const double* states, const double* gammas, const double* kscale, double dt,
+               int n_steps, double* lam, double* dkscale, double* dvfrag);
+int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, double* mu, double* grad,
+                     double* dkscale, double* dvfrag);
+
+/*
  * Batching of the contraction (uneven batches of several groups in one launch).
  * Every contraction is ONE launch over all groups of the plan: a list of work items
  * (group, threshold level, a range of output row blocks, a chunk of 4 or 8 tiles of
@@ -174,15 +213,19 @@ int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_
  * are likewise one launch over all groups.
  *
  * gd_plan_set_variant -- choose the contraction variant: waves (4 or 8) per
- *   workgroup, each wave one tile of cells (32 split-FP16, 16 FP64), and rows =
- *   row blocks per work item (0 = all of the group's row blocks).  Every variant
- *   gives bit-identical results.  Rebuilds the item list (synchronous).
- * gd_plan_variant -- the current variant, the number of work items of one
- *   contraction launch and the MFMA flops one launch executes (every stored
- *   fragment, all products, for every tile of an item); any pointer may be NULL.
+ *   workgroup, each wave one tile of cells (32 split-FP16, 16 FP64); rows = row
+ *   blocks per work item (0 = all of the group's row blocks); xcd = 1 orders the
+ *   items in 8 contiguous cost-balanced ranges, one per XCD (workgroup b runs on
+ *   XCD b % 8), so that the workgroups sharing an L2 stream the fragments of few
+ *   iteration lists; xcd = 0 orders all items largest first.  Every variant gives
+ *   bit-identical results.  Rebuilds the item list (synchronous).
+ * gd_plan_variant -- the current variant, the number of workgroups of one
+ *   contraction launch (items plus padding) and the MFMA flops one launch executes
+ *   (every stored fragment, all products, for every tile of an item); any pointer
+ *   may be NULL.
  * gd_plan_autotune -- time every variant on state g (device, state layout, read
  *   only; kscale as in gd_rk_step) and keep the fastest.  cache_path (or NULL)
- *   names a text file of "key waves rows" lines: a plan of the same shape (precision,
+ *   names a text file of "key waves rows xcd" lines: a plan of the same shape (precision,
  *   bins, order, levels, cells and brackets of every group) takes its stored
  *   choice without timing; a newly timed choice is appended.  Synchronous.
  * gd_plan_use_graph -- (default on) gd_rk_step captures one RK step (three
@@ -191,10 +234,10 @@ int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_
  *   when g, kscale, dt or the variant change.  Off: the launches are issued one by
  *   one.  Timing (gd_plan_timing) also issues them one by one.
  */
-int gd_plan_set_variant(gd_plan* plan, int waves, int rows);
-int gd_plan_variant(const gd_plan* plan, int* waves, int* rows, int* n_items, double* exec_flops);
+int gd_plan_set_variant(gd_plan* plan, int waves, int rows, int xcd);
+int gd_plan_variant(const gd_plan* plan, int* waves, int* rows, int* xcd, int* n_items, double* exec_flops);
 int gd_plan_autotune(gd_plan* plan, const double* g, const double* kscale, const char* cache_path, int* waves,
-                     int* rows);
+                     int* rows, int* xcd);
 int gd_plan_use_graph(gd_plan* plan, int enable);
 
 /*
@@ -209,15 +252,17 @@ int gd_projection_points(const gd_tensor* t, double* host_x);
 int gd_project(const gd_tensor* t, int n_cells, const double* samples, double* coef, void* stream);
 
 /*
- * gd_plan_timing / gd_plan_contraction_time -- measurement support.  While timing
- * is enabled the plan records a HIP event pair on its stream around every
- * contraction launch.  gd_plan_contraction_time synchronises the stream, returns
- * the summed event time (ms) and the number of launches since timing was enabled
- * or last read, and resets the count.  Enabling timing adds two event records per
- * launch and nothing else.
+ * gd_plan_timing / gd_plan_contraction_time / gd_plan_stage_time -- measurement
+ * support.  While timing is enabled the plan records a HIP event pair on its stream
+ * around every contraction launch and every stage-kernel launch (limiter, flux
+ * assembly, RK combination and state split), and issues the RK step launch by
+ * launch instead of as a graph.  The _time calls synchronise the stream, return the
+ * summed event time (ms) and the number of launches of that kernel since timing was
+ * enabled or last read, and reset that count.
  */
 int gd_plan_timing(gd_plan* plan, int enable);
 int gd_plan_contraction_time(gd_plan* plan, double* total_ms, int* launches);
+int gd_plan_stage_time(gd_plan* plan, double* total_ms, int* launches);
 
 const char* gd_last_error(void);
 

@@ -1,0 +1,408 @@
+// Reverse mode of the SSP-RK3 collision step (the adjoint): the vector-Jacobian
+// product of the raw flux vector, the scaling limiter and the stage combinations,
+// all in FP64.
+//
+// With Y_o(g) = sum_{p<=q} Tf[o][p][q] g_p g_q (Sec. 3.3) and a cotangent nu on Y,
+//     G_p = d(nu . Y)/dg_p = sum_{q>=p} M_p[q] g_q + sum_{q<=p} M_q[p] g_q,
+//     M_p[q] = sum_o nu_o Tf[o][p][q]                       (q >= p).
+// The contraction computes the tiles M_p[q-block] (rows q, K = o, cells as columns)
+// on the FP64 MFMA and reduces each tile twice: over its rows against g_q (the
+// first sum, a partial per q block) and into per-row accumulators weighted by g_p
+// (the second sum).  By Euler's theorem for the quadratic form,
+// nu . Y = (1/2) g . G, which gives the derivative with respect to the per-cell
+// kernel scale without another contraction; the level-difference part of a
+// blended operator gives the derivative with respect to the blend weight,
+// sum_p g_p sum_q M^diff_p[q] g_q.
+#include <algorithm>
+
+#include "contract_common.h"
+
+namespace gd {
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------- VJP contraction
+template <int KS>
+struct AdjSeg {
+    const double* A;         // first fragment of the segment in LDS, + lane
+    const double* b;         // [4 KS] nu of the lane's cell
+    doublex4* Z;
+    template <int LO>
+    __device__ __forceinline__ void run()
+    {
+        doublex4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int ks = LO; ks < KS; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                z = __builtin_amdgcn_mfma_f64_16x16x4f64(A[((ks - LO) * 4 + j) * 64], b[ks * 4 + j], z, 0, 0, 0);
+        *Z = z;
+    }
+};
+
+template <int W>
+struct AdjItem {
+    const GD_CONST GroupDev* gp;
+    const double* gplan;
+    int r, ob0, ob1, tile0;
+    uint4* buf0;
+    uint4* buf1;
+
+    template <int KS>
+    __device__ __forceinline__ void item()
+    {
+        constexpr int SEG = kSegMax;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const GD_GLOBAL uint4* frag = gptr(gp->afrag);
+        const GD_CONST IterDesc* iters = cptr(gp->aiters);
+        const GD_GLOBAL int* perm = gptr(gp->perm);
+        const GD_GLOBAL double* theta = gptr(gp->theta);
+        const int P = gp->P, n_slots = gp->n_slots, NQB = gp->NQB;
+        const int tile = tile0 + wave;
+        const int col = lane & 15, rsub = lane >> 4;
+        const int slot = tile * 16 + col;
+        int cell = -1;
+        if (tile < gp->tiles16 && slot < n_slots) cell = perm ? perm[slot] : slot;
+        const int ccl = cell >= 0 ? cell : 0;
+        const double th = (cell >= 0 && theta) ? theta[slot] : 0.0;
+        const GD_GLOBAL double* gcell = gptr(gplan) + gp->val0 + (size_t)ccl * P;
+        // B operand: the cotangent nu of the lane's cell, K = output row o
+        double b[4 * KS];
+        {
+            const GD_GLOBAL double* nu = gptr(gp->nu) + (size_t)(cell >= 0 ? slot : 0) * (KS * 16);
+#pragma unroll
+            for (int k4 = 0; k4 < 4 * KS; ++k4) b[k4] = (cell >= 0) ? nu[k4 * 4 + rsub] : 0.0;
+        }
+        GD_GLOBAL double* G1p = gptr(gp->G1p);
+        doublex4 G2;
+        double yq[4];
+        double dth;
+
+        auto prefetch_w = [&](const IterDesc& d, double (&gw)[SEG]) {
+#pragma unroll
+            for (int s = 0; s < SEG; ++s) gw[s] = gcell[(s < d.nseg) ? d.p[s] : 0];
+        };
+
+        auto body = [&](const IterDesc& d, const IterDesc& dn, const double (&gw)[SEG], double (&gwn)[SEG],
+                        const uint4* rd, uint4* wr, int qb) {
+            dma_frags<W>(frag + (size_t)dn.frag * 128, wr, dn.nfrag, wave, lane);
+            prefetch_w(dn, gwn);
+            const double* rdd = reinterpret_cast<const double*>(rd);
+            const double pw = d.delta ? th : 1.0;
+            int f = 0;
+#pragma unroll
+            for (int s = 0; s < SEG; ++s) {
+                if (s >= d.nseg) break;
+                doublex4 z = {0.0, 0.0, 0.0, 0.0};
+                AdjSeg<KS> seg{rdd + f * 256 + lane, b, &z};
+                pick_lo<KS, 0>(d.lo[s], seg);
+                f += KS - d.lo[s];
+                const double w = (cell >= 0) ? gw[s] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) G2[q] = fma(pw * w, z[q], G2[q]);
+                double t = yq[0] * z[0] + yq[1] * z[1] + yq[2] * z[2] + yq[3] * z[3];
+                t += __shfl_xor(t, 16);
+                t += __shfl_xor(t, 32);
+                if (rsub == 0 && cell >= 0)
+                    G1p[(((size_t)d.delta * NQB + qb) * n_slots + slot) * P + d.p[s]] = pw * t;
+                if (d.delta) dth = fma(w, t, dth);
+            }
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        };
+
+        for (int qb = ob0; qb < ob1; ++qb) {
+            const int list = r * NQB + qb;
+            const GD_CONST IterDesc* its = iters + cptr(gp->alist_off)[list];
+            const int n_it = cptr(gp->alist_cnt)[list];
+            G2 = doublex4{0.0, 0.0, 0.0, 0.0};
+            dth = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int qq = qb * 16 + 4 * q + rsub;
+                yq[q] = (cell >= 0 && qq < P) ? gcell[qq] : 0.0;
+            }
+            IterDesc dA = its[0], dB = its[1];
+            double gw0[SEG], gw1[SEG];
+            dma_frags<W>(frag + (size_t)dA.frag * 128, buf0, dA.nfrag, wave, lane);
+            prefetch_w(dA, gw0);
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            for (int i = 0; i < n_it; i += 2) {
+                const IterDesc dC = its[i + 2];
+                body(dA, dB, gw0, gw1, buf0, buf1, qb);
+                if (i + 1 >= n_it) break;
+                const IterDesc dD = its[i + 3];
+                body(dB, dC, gw1, gw0, buf1, buf0, qb);
+                dA = dC;
+                dB = dD;
+            }
+            if (cell >= 0) {
+                GD_GLOBAL double* g2 = gptr(gp->G2) + (size_t)slot * P;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int qq = qb * 16 + 4 * q + rsub;
+                    if (qq < P) g2[qq] = G2[q];
+                }
+                if (rsub == 0) gptr(gp->Dth)[(size_t)qb * n_slots + slot] = dth;
+            }
+        }
+    }
+};
+
+template <int KSMAX, int W>
+__global__ __launch_bounds__(64 * W) void k_adjoint_fp64(ContractArgs a)
+{
+    __shared__ uint4 buf0[kFragBudget * 128];
+    __shared__ uint4 buf1[kFragBudget * 128];
+    const int4 it = cptr(a.items)[blockIdx.x];
+    if (it.x < 0) return;
+    AdjItem<W> f{cptr(a.groups) + it.x, a.g, it.y, it.z & 0xffff, it.z >> 16, it.w, buf0, buf1};
+    dispatch_ks<KSMAX>(f.gp->KSO, f);
+}
+
+template <int KSMAX, int W>
+static int launch_adj(const ContractArgs& a, hipStream_t s)
+{
+    if (a.n_items == 0) return GD_OK;
+    hipLaunchKernelGGL((k_adjoint_fp64<KSMAX, W>), dim3(a.n_items), dim3(64 * W), 0, s, a);
+    HIP_TRY(hipGetLastError());
+    return GD_OK;
+}
+
+int launch_adjoint_fp64(const ContractArgs& a, int ksomax, hipStream_t s)
+{
+    if (ksomax <= 6) return launch_adj<6, 8>(a, s);
+    if (ksomax <= 12) return launch_adj<12, 8>(a, s);
+    return fail(GD_EUNSUPPORTED, "too many output rows for the adjoint contraction");
+}
+
+// ---------------------------------------------------------------------------- per-bin pieces
+__device__ __forceinline__ double leg(int i, double x)
+{
+    switch (i) {
+    case 0: return 1.0;
+    case 1: return x;
+    case 2: return 1.5 * x * x - 0.5;
+    default: return 2.5 * x * x * x - 1.5 * x;
+    }
+}
+
+// Location of the minimum over [-1,1] of sum_i c_i P_i (k <= 3): end points and the
+// real roots of the derivative inside (-1,1).
+__device__ double poly_argmin(int k, const double* c)
+{
+    auto val = [&](double x) {
+        double v = 0.0;
+        for (int i = 0; i <= k; ++i) v += c[i] * leg(i, x);
+        return v;
+    };
+    double xb = -1.0, mb = val(-1.0);
+    if (val(1.0) < mb) { xb = 1.0; mb = val(1.0); }
+    if (k < 2) return xb;
+    const double A = (k >= 3) ? 7.5 * c[3] : 0.0;
+    const double B = 3.0 * c[2];
+    const double C = c[1] - ((k >= 3) ? 1.5 * c[3] : 0.0);
+    double r[2];
+    int nr = 0;
+    if (A != 0.0) {
+        const double d = B * B - 4.0 * A * C;
+        if (d >= 0.0) {
+            const double sq = sqrt(d);
+            const double qq = -0.5 * (B + copysign(sq, B));
+            if (qq != 0.0) { r[nr++] = qq / A; r[nr++] = C / qq; }
+            else r[nr++] = 0.0;
+        }
+    } else if (B != 0.0) {
+        r[nr++] = -C / B;
+    }
+    for (int t = 0; t < nr; ++t)
+        if (r[t] > -1.0 && r[t] < 1.0 && val(r[t]) < mb) { xb = r[t]; mb = val(r[t]); }
+    return xb;
+}
+
+__device__ __forceinline__ int find_group_bins(const GD_CONST GroupDev* groups, int n_groups, long long b)
+{
+    int gi = 0;
+    while (gi + 1 < n_groups && b >= groups[gi + 1].gam0) ++gi;
+    return gi;
+}
+
+// lam <- J_limiter^T lam for every bin, from the limited state y and the factor
+// gamma the forward limiter applied (y_i = gamma z_i for i >= 1, y_0 = z_0):
+//   gamma = 1: identity;  gamma = 0 (flattened bin): the higher coefficients get 0;
+//   else, with q = sum_{i>=1} z_i P_i(x*) at the minimiser x* (so gamma = -z_0/q and,
+//   by the envelope theorem, dq/dz_i = P_i(x*)) and S = sum_{i>=1} lam_i z_i:
+//   mu_0 = lam_0 - S/q,   mu_j = gamma lam_j + S z_0 P_j(x*) / q^2.
+__global__ __launch_bounds__(256) void k_adj_limit(AdjStageArgs a)
+{
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.n_bins) return;
+    const GD_CONST GroupDev* groups = cptr(a.groups);
+    const GD_CONST GroupDev* G = groups + find_group_bins(groups, a.n_groups, b);
+    const int N = G->N, k = G->k, K1 = k + 1, P = G->P;
+    const long long lb = b - G->gam0;
+    const int c = (int)(lb / N), j = (int)(lb - (long long)c * N);
+    const size_t base = G->val0 + (size_t)c * P + j * K1;
+    const double gam = a.gamma[b];
+    GD_GLOBAL double* lam = gptr(a.lam) + base;
+    if (gam == 1.0 || k == 0) return;
+    if (gam == 0.0) {
+        for (int i = 1; i <= k; ++i) lam[i] = 0.0;
+        return;
+    }
+    const GD_GLOBAL double* y = gptr(a.y) + base;
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    z[0] = y[0];
+    for (int i = 1; i <= k; ++i) z[i] = y[i] / gam;
+    const double xs = poly_argmin(k, z);
+    double q = 0.0, S = 0.0;
+    for (int i = 1; i <= k; ++i) {
+        q += z[i] * leg(i, xs);
+        S += lam[i] * z[i];
+    }
+    if (!(q < 0.0)) return;   // cannot happen for 0 < gamma < 1
+    const double l0 = lam[0] - S / q;
+    for (int i = 1; i <= k; ++i) lam[i] = gam * lam[i] + S * z[0] * leg(i, xs) / (q * q);
+    lam[0] = l0;
+}
+
+// From mu (the cotangent of a stage's pre-limiter value z = a g_n + b (y + dt L(y))):
+//   acc (=|+=) a mu, prev (=|+=) b mu, and nu = A^T (b dt mu) in slot order, where A is
+// the assembly of Eq. evo: L_{j,i} = (2i+1)/h_j (V_{j,i} - F_{j+1} + (-1)^i F_j).
+// One workgroup per tile of 32 slots, one thread per (slot, bin).
+__global__ __launch_bounds__(kAdjThreads) void k_adj_nu(AdjStageArgs a)
+{
+    const GD_CONST GroupDev* groups = cptr(a.groups);
+    int gi = 0;
+    while (gi + 1 < a.n_groups && (int)blockIdx.x >= groups[gi + 1].tile_off) ++gi;
+    const GD_CONST GroupDev* G = groups + gi;
+    const int tile = (int)blockIdx.x - G->tile_off;
+    const int N = G->N, k = G->k, K1 = k + 1, P = G->P, n_out = G->n_out, nus = G->KSO * 16;
+    const bool conservative = G->conservative != 0;
+    const GD_CONST double* h = cptr(G->h);
+    const GD_GLOBAL int* perm = gptr(G->perm);
+    const GD_GLOBAL double* mu = gptr(a.mu) + G->val0;
+    GD_GLOBAL double* acc = a.acc ? gptr(a.acc) + G->val0 : nullptr;
+    GD_GLOBAL double* prev = gptr(a.prev) + G->val0;
+    GD_GLOBAL double* nu = gptr(G->nu);
+    const int vbase = (N - 1) + (conservative ? 0 : 1);
+    for (int t = threadIdx.x; t < 32 * N; t += blockDim.x) {
+        const int sl = t / N, j = t - sl * N;
+        const int s = tile * 32 + sl;
+        if (s >= G->n_slots) continue;
+        const int c = perm ? perm[s] : s;
+        GD_GLOBAL double* nrow = nu + (size_t)s * nus;
+        if (c < 0) {
+            for (int o = j; o < nus; o += N) nrow[o] = 0.0;
+            continue;
+        }
+        const size_t base = (size_t)c * P + j * K1;
+        double rho[4], rhol[4];
+        for (int i = 0; i < K1; ++i) {
+            const double m = mu[base + i];
+            rho[i] = a.bdt * m;
+            if (acc) acc[base + i] = a.acc_add ? acc[base + i] + a.a * m : a.a * m;
+            prev[base + i] = a.prev_add ? prev[base + i] + a.b * m : a.b * m;
+        }
+        const double hj = h[j];
+        // V_{j,i}
+        for (int i = 1; i < K1; ++i) nrow[vbase + j * k + i - 1] = rho[i] * (2.0 * i + 1.0) / hj;
+        // F_j (interior interface j >= 1): from bin j (as F_j) and bin j-1 (as F_{j+1})
+        if (j >= 1) {
+            const double hl = h[j - 1];
+            const size_t bl = (size_t)c * P + (j - 1) * K1;
+            double v = 0.0;
+            for (int i = 0; i < K1; ++i) {
+                rhol[i] = a.bdt * mu[bl + i];
+                v += ((i & 1) ? -1.0 : 1.0) * rho[i] * (2.0 * i + 1.0) / hj - rhol[i] * (2.0 * i + 1.0) / hl;
+            }
+            nrow[j - 1] = v;
+        }
+        if (j == N - 1 && !conservative) {
+            double v = 0.0;
+            for (int i = 0; i < K1; ++i) v -= rho[i] * (2.0 * i + 1.0) / hj;
+            nrow[N - 1] = v;
+        }
+        if (j == 0)
+            for (int o = n_out; o < nus; ++o) nrow[o] = 0.0;
+    }
+}
+
+// prev += s G with G_p = G2_p + sum over q blocks of the first-sum partials (both
+// parts); dkscale += (1/2) y . G; dvfrag += s (sum of the blend partials) dtheta/dv.
+__global__ __launch_bounds__(kAdjThreads) void k_adj_combine(AdjStageArgs a)
+{
+    __shared__ double red[32];
+    const GD_CONST GroupDev* groups = cptr(a.groups);
+    int gi = 0;
+    while (gi + 1 < a.n_groups && (int)blockIdx.x >= groups[gi + 1].tile_off) ++gi;
+    const GD_CONST GroupDev* G = groups + gi;
+    const int tile = (int)blockIdx.x - G->tile_off;
+    const int P = G->P, NQB = G->NQB, n_slots = G->n_slots;
+    const bool blend = G->R > 1;
+    const GD_GLOBAL int* perm = gptr(G->perm);
+    const GD_GLOBAL double* y = gptr(a.y) + G->val0;
+    GD_GLOBAL double* prev = gptr(a.prev) + G->val0;
+    const GD_GLOBAL double* G2 = gptr(G->G2);
+    const GD_GLOBAL double* G1p = gptr(G->G1p);
+    if (threadIdx.x < 32) red[threadIdx.x] = 0.0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < 32 * P; t += blockDim.x) {
+        const int sl = t / P, p = t - sl * P;
+        const int s = tile * 32 + sl;
+        if (s >= n_slots) continue;
+        const int c = perm ? perm[s] : s;
+        if (c < 0) continue;
+        double g = G2[(size_t)s * P + p];
+        for (int qb = p / 16; qb < NQB; ++qb) {
+            g += G1p[((size_t)qb * n_slots + s) * P + p];
+            if (blend) g += G1p[(((size_t)NQB + qb) * n_slots + s) * P + p];
+        }
+        const double sc = a.kscale ? a.kscale[G->cell0 + c] : 1.0;
+        prev[(size_t)c * P + p] += sc * g;
+        atomicAdd(&red[sl], 0.5 * y[(size_t)c * P + p] * g);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        const int s = tile * 32 + threadIdx.x;
+        if (s < n_slots) {
+            const int c = perm ? perm[s] : s;
+            if (c >= 0) {
+                if (a.dkscale) a.dkscale[G->cell0 + c] += red[threadIdx.x];
+                if (a.dvfrag && blend) {
+                    double d = 0.0;
+                    for (int qb = 0; qb < NQB; ++qb) d += G->Dth[(size_t)qb * n_slots + s];
+                    const double sc = a.kscale ? a.kscale[G->cell0 + c] : 1.0;
+                    a.dvfrag[G->cell0 + c] += sc * d * G->dthdv[s];
+                }
+            }
+        }
+    }
+}
+
+int launch_adj_limit(const AdjStageArgs& a, hipStream_t s)
+{
+    if (a.n_bins == 0) return GD_OK;
+    hipLaunchKernelGGL(k_adj_limit, dim3((unsigned)((a.n_bins + 255) / 256)), dim3(256), 0, s, a);
+    HIP_TRY(hipGetLastError());
+    return GD_OK;
+}
+
+int launch_adj_nu(const AdjStageArgs& a, hipStream_t s)
+{
+    if (a.n_tiles == 0) return GD_OK;
+    hipLaunchKernelGGL(k_adj_nu, dim3(a.n_tiles), dim3(kAdjThreads), 0, s, a);
+    HIP_TRY(hipGetLastError());
+    return GD_OK;
+}
+
+int launch_adj_combine(const AdjStageArgs& a, hipStream_t s)
+{
+    if (a.n_tiles == 0) return GD_OK;
+    hipLaunchKernelGGL(k_adj_combine, dim3(a.n_tiles), dim3(kAdjThreads), 0, s, a);
+    HIP_TRY(hipGetLastError());
+    return GD_OK;
+}
+
+} // namespace gd

@@ -61,6 +61,9 @@ struct gd_tensor {
     const double* colscale = nullptr;   // [P]
     const double* rowscale = nullptr;   // [NOB*32]
     Schedule mixed, f64;
+    Schedule adj;              // FP64 transposed layout of the vector-Jacobian product
+    bool adj_packed = false;
+    int KSO = 0;               // K steps of 16 output rows o (adjoint contraction)
 };
 
 // folded tensor of level r: Tf[o][p][q] = T[o][p][q] + T[o][q][p] (p < q), T[o][p][p]
@@ -187,6 +190,95 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterD
             iters.push_back(sentinel);
             iters.push_back(sentinel);
         }
+}
+
+// Schedule of the vector-Jacobian product G_p = sum_o nu_o dY_o/dg_p (FP64).  With
+// M_p[q] = sum_o nu_o Tf[o][p][q] (q >= p), G_p = sum_q M_p[q] g_q + sum_q' M_q'[p] g_q'.
+// One list per (level r, block of 16 q); within it, for both parts and for EVERY
+// p < end of the block (also p without a stored fragment, whose chain is empty, so
+// that every partial output is written), a segment over the K steps of o
+// (16 rows of o each, lo..KSO-1).  Fragment: 16 rows q x 16 o as four 4-column
+// sub-steps, lane l, sub-step j: Tf[o = 16ks + 4j + l/16][p][q = 16qb + l%16] (q >= p).
+static int pack_adjoint(gd_tensor* t)
+{
+    if (t->adj_packed) return GD_OK;
+    const int P = t->P, NO = t->n_out, R = t->R;
+    const int NQB = cdiv(P, 16), KSO = cdiv(NO, 16);
+    t->KSO = KSO;
+    std::vector<IterDesc> iters;
+    std::vector<int> off, cnt;
+    std::vector<double> frag;
+    Schedule& S = t->adj;
+    int nfrag = 0;
+    for (int r = 0; r < R; ++r)
+        for (int qb = 0; qb < NQB; ++qb) {
+            off.push_back(int(iters.size()));
+            const int nf0 = nfrag;
+            const int pend = std::min(P, qb * 16 + 16);
+            for (int delta = 0; delta <= (r + 1 < R ? 1 : 0); ++delta) {
+                struct Seg { int p, lo; };
+                std::vector<Seg> segs;
+                for (int p = 0; p < pend; ++p) {
+                    int lo = KSO;
+                    for (int ks = 0; ks < KSO && lo == KSO; ++ks) {
+                        bool nz = false;
+                        for (int o = ks * 16; o < std::min(NO, ks * 16 + 16) && !nz; ++o)
+                            for (int q = std::max(p, qb * 16); q < pend; ++q)
+                                if (part(t, r, delta, o, p, q) != 0.0) { nz = true; break; }
+                        if (nz) lo = ks;
+                    }
+                    segs.push_back({p, lo});
+                }
+                size_t s0 = 0;
+                while (s0 < segs.size()) {
+                    IterDesc d{};
+                    d.ob = qb;
+                    d.delta = delta;
+                    d.frag = nfrag;
+                    while (s0 < segs.size() && d.nseg < kSegMax &&
+                           (nfrag - d.frag) + (KSO - segs[s0].lo) <= kFragBudget) {
+                        const int j = d.nseg++;
+                        d.p[j] = segs[s0].p;
+                        d.lo[j] = segs[s0].lo;
+                        d.hi[j] = KSO - 1;
+                        for (int ks = d.lo[j]; ks < KSO; ++ks) {
+                            const size_t f = frag.size() / 256;
+                            frag.resize(frag.size() + 256, 0.0);
+                            for (int jj = 0; jj < 4; ++jj)
+                                for (int l = 0; l < 64; ++l) {
+                                    const int q = qb * 16 + (l & 15), o = ks * 16 + 4 * jj + (l >> 4);
+                                    if (o < NO && q < P && q >= d.p[j])
+                                        frag[f * 256 + jj * 64 + l] = part(t, r, delta, o, d.p[j], q);
+                                }
+                            ++nfrag;
+                        }
+                        ++s0;
+                    }
+                    d.nfrag = nfrag - d.frag;
+                    iters.push_back(d);
+                }
+            }
+            cnt.push_back(int(iters.size()) - off.back());
+            S.list_cost.push_back((nfrag - nf0) + kIterCost * cnt.back());
+            S.list_frags.push_back(nfrag - nf0);
+            IterDesc sentinel{};
+            sentinel.ob = -1;
+            sentinel.frag = nfrag;
+            iters.push_back(sentinel);
+            iters.push_back(sentinel);
+        }
+    int rc;
+    const double* dfrag = nullptr;
+    if ((rc = upload(t->bufs, frag, &dfrag, &t->bytes))) return rc;
+    S.frag = dfrag;
+    S.frags = (long long)(frag.size() / 256);
+    S.iters_total = (long long)iters.size();
+    S.NOB = NQB;
+    if ((rc = upload(t->bufs, iters, &S.iters, &t->bytes))) return rc;
+    if ((rc = upload(t->bufs, off, &S.list_off, &t->bytes))) return rc;
+    if ((rc = upload(t->bufs, cnt, &S.list_cnt, &t->bytes))) return rc;
+    t->adj_packed = true;
+    return GD_OK;
 }
 
 static int pack_tensor(gd_tensor* t)
@@ -393,6 +485,7 @@ struct Bracket {
 };
 
 struct Group {
+    std::vector<double> h_dthdv;   // d theta / d v_frag per slot (blended groups)
     const gd_tensor* t = nullptr;
     int C = 0;
     long long cell0 = 0, val0 = 0, raw0 = 0;
@@ -427,9 +520,10 @@ struct gd_plan {
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;              // private stream the step graph is captured on
     long long n_cells = 0, n_values = 0, n_raw = 0;
-    int ksmax = 1, tiles32 = 0;
+    int ksmax = 1, tiles32 = 0, max_bins = 1;
     GroupDev* groups_dev = nullptr;
-    int waves = 4, rows = 1;                // contraction variant: waves per workgroup, row blocks per item
+    int waves = 4, rows = 1, xcd = 1;       // contraction variant: waves per workgroup, row blocks per item,
+                                            // items grouped by XCD
     int4* items = nullptr;
     int n_items = 0;
     size_t items_cap = 0;
@@ -439,8 +533,15 @@ struct gd_plan {
     double* y1 = nullptr;
     double* y2 = nullptr;
     unsigned long long* viol = nullptr;
+    long long n_bins = 0;                   // sum over groups of cells * bins
+    std::vector<GroupDev> gdev;             // host copy of groups_dev
+    // reverse mode, set up by the first adjoint call
+    bool adj_ready = false;
+    int4* adj_items = nullptr;
+    int n_adj_items = 0, ksomax = 1;
+    double* adj_buf[2] = {nullptr, nullptr};
     bool timing = false;
-    KernelTimer timer;
+    KernelTimer timer, stimer;              // contraction and stage launches
     std::vector<void*> allocs;
     void drop_graph()
     {
@@ -451,11 +552,13 @@ struct gd_plan {
     {
         drop_graph();
         if (cap) (void)hipStreamDestroy(cap);
-        for (auto& e : timer.ev) {
-            (void)hipEventDestroy(e.first);
-            (void)hipEventDestroy(e.second);
-        }
+        for (KernelTimer* T : {&timer, &stimer})
+            for (auto& e : T->ev) {
+                (void)hipEventDestroy(e.first);
+                (void)hipEventDestroy(e.second);
+            }
         if (items) (void)hipFree(items);
+        if (adj_items) (void)hipFree(adj_items);
         for (void* p : allocs) (void)hipFree(p);
     }
 };
@@ -483,56 +586,98 @@ static int dcopy(gd_plan* pl, T** p, const std::vector<T>& v)
 // contraction workgroup (at most 8 tiles of 32 slots) reads one level
 static constexpr int kSlotGranule = 256;
 
-// Work items of the contraction for the plan's variant, largest first: the hardware
-// hands workgroups out in launch order, so the expensive items start first and the
-// small ones fill the tail.  Items of one list are adjacent, so that the workgroups
-// running at one time share the list's fragments in L2.
-static int build_items(gd_plan* pl)
+// Work items of the contraction for the plan's variant.  The hardware hands
+// workgroup b to XCD b % 8, and each XCD has its own L2.  With xcd ordering on, the
+// items, in list order (group, level, row block, tile chunk), are cut into 8
+// contiguous ranges of equal cost, one per XCD, so that an XCD streams the
+// fragments of few lists at a time; within a range (or over all items with xcd
+// ordering off) the items run largest first, so that the small ones fill the tail.
+// Ranges of unequal length are padded with empty items (group -1).
+// Item list of one contraction over every group of the plan: the lists of schedule
+// `which` (0: the plan's forward precision, 1: the FP64 vector-Jacobian product),
+// workgroups of W waves over tiles of ts slots.
+static void make_items(const gd_plan* pl, int which, int W, int rows, int xcd, std::vector<int4>& h, double* flops)
 {
-    const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
-    const int ts = mixed ? 32 : 16, W = pl->waves;
+    const bool mixed = which == 0 && pl->prec == GD_PREC_MIXED_F16X3;
+    const int ts = mixed ? 32 : 16;
     struct It {
         long long cost;
         int4 v;
         long long frags;
     };
     std::vector<It> v;
+    long long total = 0;
     for (size_t gi = 0; gi < pl->groups.size(); ++gi) {
         const Group& G = pl->groups[gi];
         if (G.C == 0) continue;
-        const Schedule& S = mixed ? G.t->mixed : G.t->f64;
+        const Schedule& S = which == 1 ? G.t->adj : (mixed ? G.t->mixed : G.t->f64);
         const int NOB = S.NOB;
-        const int rows = pl->rows <= 0 ? NOB : std::min(NOB, pl->rows);
+        const int nr = rows <= 0 ? NOB : std::min(NOB, rows);
         for (const Bracket& b : G.brackets) {
             const int t0 = b.s0 / ts, t1 = cdiv(b.s0 + b.n, ts);
-            for (int tile = t0; tile < t1; tile += W)
-                for (int ob = 0; ob < NOB; ob += rows) {
-                    const int ob1 = std::min(NOB, ob + rows);
-                    long long c = 4, f = 0;
-                    for (int o = ob; o < ob1; ++o) {
-                        c += S.list_cost[size_t(b.r) * NOB + o];
-                        f += S.list_frags[size_t(b.r) * NOB + o];
-                    }
-                    v.push_back({c, int4{int(gi), b.r, ob | (ob1 << 16), tile}, f});
+            for (int ob = 0; ob < NOB; ob += nr) {
+                const int ob1 = std::min(NOB, ob + nr);
+                long long c = 4, f = 0;
+                for (int o = ob; o < ob1; ++o) {
+                    c += S.list_cost[size_t(b.r) * NOB + o];
+                    f += S.list_frags[size_t(b.r) * NOB + o];
                 }
+                for (int tile = t0; tile < t1; tile += W) {
+                    v.push_back({c, int4{int(gi), b.r, ob | (ob1 << 16), tile}, f});
+                    total += c;
+                }
+            }
         }
     }
-    std::stable_sort(v.begin(), v.end(), [](const It& x, const It& y) { return x.cost > y.cost; });
-    std::vector<int4> h(v.size());
+    auto by_cost = [](const It& x, const It& y) { return x.cost > y.cost; };
+    h.clear();
+    if (xcd && !v.empty()) {
+        std::vector<std::vector<It>> B(8);
+        long long pre = 0;
+        for (const It& it : v) {
+            const int x = std::min<long long>(7, (2 * pre + it.cost) * 8 / std::max<long long>(1, 2 * total));
+            B[x].push_back(it);
+            pre += it.cost;
+        }
+        size_t M = 0;
+        for (auto& b : B) {
+            std::stable_sort(b.begin(), b.end(), by_cost);
+            M = std::max(M, b.size());
+        }
+        h.assign(8 * M, int4{-1, 0, 0, 0});
+        for (int x = 0; x < 8; ++x)
+            for (size_t i = 0; i < B[x].size(); ++i) h[i * 8 + x] = B[x][i].v;
+    } else {
+        std::stable_sort(v.begin(), v.end(), by_cost);
+        for (const It& it : v) h.push_back(it.v);
+    }
     double fl = 0.0;
-    for (size_t i = 0; i < v.size(); ++i) {
-        h[i] = v[i].v;
+    for (const It& it : v)
         // split path: 3 products of 32x32x16 per fragment and tile; FP64: 4 of 16x16x4
-        fl += double(v[i].frags) * W * (mixed ? 3.0 * 2 * 32 * 32 * 16 : 4.0 * 2 * 16 * 16 * 4);
+        fl += double(it.frags) * W * (mixed ? 3.0 * 2 * 32 * 32 * 16 : 4.0 * 2 * 16 * 16 * 4);
+    if (flops) *flops = fl;
+}
+
+static int upload_items(const std::vector<int4>& h, int4** dev, size_t* cap)
+{
+    if (h.size() > *cap) {
+        if (*dev) HIP_TRY(hipFree(*dev));
+        *dev = nullptr;
+        *cap = 0;
+        HIP_TRY(hipMalloc(dev, h.size() * sizeof(int4)));
+        *cap = h.size();
     }
-    if (h.size() > pl->items_cap) {
-        if (pl->items) HIP_TRY(hipFree(pl->items));
-        pl->items = nullptr;
-        pl->items_cap = 0;
-        HIP_TRY(hipMalloc(&pl->items, h.size() * sizeof(int4)));
-        pl->items_cap = h.size();
-    }
-    if (!h.empty()) HIP_TRY(hipMemcpy(pl->items, h.data(), h.size() * sizeof(int4), hipMemcpyHostToDevice));
+    if (!h.empty()) HIP_TRY(hipMemcpy(*dev, h.data(), h.size() * sizeof(int4), hipMemcpyHostToDevice));
+    return GD_OK;
+}
+
+static int build_items(gd_plan* pl)
+{
+    std::vector<int4> h;
+    double fl = 0.0;
+    make_items(pl, 0, pl->waves, pl->rows, pl->xcd, h, &fl);
+    int rc = upload_items(h, &pl->items, &pl->items_cap);
+    if (rc) return rc;
     pl->n_items = int(h.size());
     pl->exec_flops = fl;
     pl->drop_graph();
@@ -563,6 +708,7 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
         pl->n_values += (long long)G.C * G.t->P;
         pl->n_raw += (long long)G.C * G.t->n_out;
         pl->ksmax = std::max(pl->ksmax, G.t->KS);
+        pl->max_bins = std::max(pl->max_bins, G.t->N);
         pl->groups.push_back(std::move(G));
     }
     if (pl->n_cells > (1ll << 30)) return fail(GD_EINVAL, "too many cells");
@@ -574,12 +720,15 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
             // theta = (v - levels[r]) / (levels[r+1] - levels[r]) clamped to [0,1]
             const std::vector<double>& lv = t->spec.levels;
             std::vector<std::vector<std::pair<int, double>>> br(t->R - 1);
+            std::vector<double> dth(G.C);
             for (int c = 0; c < G.C; ++c) {
                 const double v = vfrag ? vfrag[G.cell0 + c] : lv[0];
                 if (!std::isfinite(v)) return fail(GD_EINVAL, "non-finite fragmentation threshold");
                 int r = 0;
                 while (r < t->R - 2 && v >= lv[r + 1]) ++r;
                 double th = (v - lv[r]) / (lv[r + 1] - lv[r]);
+                // inside the table theta moves with v; outside it is clamped
+                dth[c] = (v >= lv[r] && v <= lv[r + 1]) ? 1.0 / (lv[r + 1] - lv[r]) : 0.0;
                 th = std::min(1.0, std::max(0.0, th));
                 br[r].push_back({c, th});
             }
@@ -591,10 +740,12 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
                 for (auto& ct : br[r]) {
                     perm.push_back(ct.first);
                     theta.push_back(ct.second);
+                    G.h_dthdv.push_back(dth[ct.first]);
                 }
                 while (perm.size() % kSlotGranule) {
                     perm.push_back(-1);
                     theta.push_back(0.0);
+                    G.h_dthdv.push_back(0.0);
                 }
             }
             G.n_slots = int(perm.size());
@@ -651,8 +802,12 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
         d.tiles16 = G.tiles16;
         d.tile_off = G.tile_off;
         d.conservative = t->spec.conservative;
+        d.R = t->R;
+        d.gam0 = pl->n_bins;
+        pl->n_bins += (long long)G.C * t->N;
         gdev.push_back(d);
     }
+    pl->gdev = gdev;
     if ((rc = dcopy(pl.get(), &pl->groups_dev, gdev))) return rc;
     if ((rc = dalloc(pl.get(), &pl->y1, pl->n_values))) return rc;
     if ((rc = dalloc(pl.get(), &pl->y2, pl->n_values))) return rc;
@@ -672,23 +827,32 @@ extern "C" int gd_plan_sizes(const gd_plan* pl, long long* n_cells, long long* n
     return GD_OK;
 }
 
+extern "C" int gd_plan_bins(const gd_plan* pl, long long* n_bins)
+{
+    if (!pl || !n_bins) return fail(GD_EINVAL, "null argument");
+    *n_bins = pl->n_bins;
+    return GD_OK;
+}
+
 extern "C" void gd_plan_destroy(gd_plan* pl) { delete pl; }
 
-extern "C" int gd_plan_set_variant(gd_plan* pl, int waves, int rows)
+extern "C" int gd_plan_set_variant(gd_plan* pl, int waves, int rows, int xcd)
 {
     if (!pl) return fail(GD_EINVAL, "null plan");
     if (waves != 4 && waves != 8) return fail(GD_EINVAL, "waves must be 4 or 8");
     if (rows < 0) return fail(GD_EINVAL, "rows must be >= 0");
     pl->waves = waves;
     pl->rows = rows;
+    pl->xcd = xcd ? 1 : 0;
     return build_items(pl);
 }
 
-extern "C" int gd_plan_variant(const gd_plan* pl, int* waves, int* rows, int* n_items, double* exec_flops)
+extern "C" int gd_plan_variant(const gd_plan* pl, int* waves, int* rows, int* xcd, int* n_items, double* exec_flops)
 {
     if (!pl) return fail(GD_EINVAL, "null plan");
     if (waves) *waves = pl->waves;
     if (rows) *rows = pl->rows;
+    if (xcd) *xcd = pl->xcd;
     if (n_items) *n_items = pl->n_items;
     if (exec_flops) *exec_flops = pl->exec_flops;
     return GD_OK;
@@ -702,13 +866,32 @@ extern "C" int gd_plan_use_graph(gd_plan* pl, int enable)
     return GD_OK;
 }
 
-static int stage(const gd_plan* pl, hipStream_t s, int mode, int limit, int split, const double* kscale,
-                 const double* gn, const double* gs, double* out, double dt, double* raw)
+// event pair around the next launch on s while timing is on (*end receives the end event)
+static int timer_begin(gd_plan* pl, KernelTimer& T, hipStream_t s, hipEvent_t* end)
+{
+    *end = nullptr;
+    if (!pl->timing) return GD_OK;
+    if (T.used == T.ev.size()) {
+        hipEvent_t e0, e1;
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        T.ev.push_back({e0, e1});
+    }
+    HIP_TRY(hipEventRecord(T.ev[T.used].first, s));
+    *end = T.ev[T.used].second;
+    ++T.used;
+    return GD_OK;
+}
+
+static int stage(gd_plan* pl, hipStream_t s, int mode, int limit, int split, const double* kscale,
+                 const double* gn, const double* gs, double* out, double dt, double* raw, double* gamma = nullptr)
 {
     StageArgs a{};
+    a.gamma = gamma;
     a.groups = pl->groups_dev;
     a.n_groups = int(pl->groups.size());
     a.n_tiles = pl->tiles32;
+    a.max_bins = pl->max_bins;
     a.mode = mode;
     a.limit = limit;
     a.split = split;
@@ -719,28 +902,23 @@ static int stage(const gd_plan* pl, hipStream_t s, int mode, int limit, int spli
     a.raw = raw;
     a.viol = pl->viol;
     a.dt = dt;
-    return launch_stage(a, s);
+    hipEvent_t ev_end;
+    int rc = timer_begin(pl, pl->stimer, s, &ev_end);
+    if (rc) return rc;
+    if ((rc = launch_stage(a, s))) return rc;
+    if (ev_end) HIP_TRY(hipEventRecord(ev_end, s));
+    return GD_OK;
 }
 
 // one contraction launch over every group on stage state gs (the split path reads
 // the fragments the previous stage kernel wrote from gs)
 static int contract(gd_plan* pl, hipStream_t s, const double* gs)
 {
-    hipEvent_t ev_end = nullptr;
-    if (pl->timing) {
-        KernelTimer& T = pl->timer;
-        if (T.used == T.ev.size()) {
-            hipEvent_t e0, e1;
-            HIP_TRY(hipEventCreate(&e0));
-            HIP_TRY(hipEventCreate(&e1));
-            T.ev.push_back({e0, e1});
-        }
-        HIP_TRY(hipEventRecord(T.ev[T.used].first, s));
-        ev_end = T.ev[T.used].second;
-        ++T.used;
-    }
+    hipEvent_t ev_end;
+    int rc = timer_begin(pl, pl->timer, s, &ev_end);
+    if (rc) return rc;
     ContractArgs a{pl->groups_dev, pl->items, gs, pl->n_items};
-    int rc = (pl->prec == GD_PREC_MIXED_F16X3) ? launch_contract_mixed(a, pl->ksmax, pl->waves, s)
+    rc = (pl->prec == GD_PREC_MIXED_F16X3) ? launch_contract_mixed(a, pl->ksmax, pl->waves, s)
                                                : launch_contract_fp64(a, pl->ksmax, pl->waves, s);
     if (rc) return rc;
     if (ev_end) HIP_TRY(hipEventRecord(ev_end, s));
@@ -824,6 +1002,184 @@ extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double d
     return GD_OK;
 }
 
+// ---------------------------------------------------------------------------- reverse mode
+// Buffers, transposed schedules and work items of the vector-Jacobian product.
+static int prepare_adjoint(gd_plan* pl)
+{
+    if (pl->adj_ready) return GD_OK;
+    int rc;
+    for (size_t gi = 0; gi < pl->groups.size(); ++gi) {
+        Group& G = pl->groups[gi];
+        gd_tensor* t = const_cast<gd_tensor*>(G.t);
+        if ((rc = pack_adjoint(t))) return rc;
+        GroupDev& d = pl->gdev[gi];
+        d.afrag = static_cast<const uint4*>(t->adj.frag);
+        d.aiters = t->adj.iters;
+        d.alist_off = t->adj.list_off;
+        d.alist_cnt = t->adj.list_cnt;
+        d.KSO = t->KSO;
+        d.NQB = t->adj.NOB;
+        pl->ksomax = std::max(pl->ksomax, t->KSO);
+        const size_t ns = size_t(std::max(1, G.n_slots));
+        double *nu, *g2, *g1, *dt_, *dv;
+        if ((rc = dalloc(pl, &nu, ns * t->KSO * 16))) return rc;
+        if ((rc = dalloc(pl, &g2, ns * t->P))) return rc;
+        if ((rc = dalloc(pl, &g1, size_t(t->R > 1 ? 2 : 1) * d.NQB * ns * t->P))) return rc;
+        if ((rc = dalloc(pl, &dt_, size_t(d.NQB) * ns))) return rc;
+        std::vector<double> dthdv = G.h_dthdv;
+        dthdv.resize(ns, 0.0);
+        if ((rc = dcopy(pl, &dv, dthdv))) return rc;
+        d.nu = nu;
+        d.G2 = g2;
+        d.G1p = g1;
+        d.Dth = dt_;
+        d.dthdv = dv;
+    }
+    HIP_TRY(hipMemcpy(pl->groups_dev, pl->gdev.data(), pl->gdev.size() * sizeof(GroupDev), hipMemcpyHostToDevice));
+    for (double*& b : pl->adj_buf)
+        if ((rc = dalloc(pl, &b, pl->n_values))) return rc;
+    std::vector<int4> h;
+    make_items(pl, 1, 8, 1, 1, h, nullptr);
+    size_t cap = 0;
+    if ((rc = upload_items(h, &pl->adj_items, &cap))) return rc;
+    pl->n_adj_items = int(h.size());
+    pl->adj_ready = true;
+    return GD_OK;
+}
+
+extern "C" int gd_rk_forward(gd_plan* pl, double* g, const double* kscale, double dt, int n_steps, double* states,
+                             double* gammas, long long* violations)
+{
+    if (!pl || !g || !states || !gammas || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!std::isfinite(dt)) return fail(GD_EINVAL, "dt must be finite");
+    int rc;
+    hipStream_t s = pl->stream;
+    const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
+    const size_t V = size_t(pl->n_values), B = size_t(pl->n_bins);
+    auto S = [&](long long i) { return states + i * V; };
+    auto Gm = [&](long long i) { return gammas + i * B; };
+    if ((rc = launch_fill_u64(pl->viol, 1, s))) return rc;
+    if ((rc = stage(pl, s, -1, 1, split, kscale, nullptr, g, S(0), dt, nullptr, Gm(0)))) return rc;
+    for (int n = 0; n < n_steps; ++n) {
+        double* gn = S(3ll * n);
+        if ((rc = contract(pl, s, gn))) return rc;
+        if ((rc = stage(pl, s, 1, 1, split, kscale, gn, gn, S(3ll * n + 1), dt, nullptr, Gm(3ll * n + 1)))) return rc;
+        if ((rc = contract(pl, s, S(3ll * n + 1)))) return rc;
+        if ((rc = stage(pl, s, 2, 1, split, kscale, gn, S(3ll * n + 1), S(3ll * n + 2), dt, nullptr, Gm(3ll * n + 2))))
+            return rc;
+        if ((rc = contract(pl, s, S(3ll * n + 2)))) return rc;
+        if ((rc = stage(pl, s, 3, 1, split, kscale, gn, S(3ll * n + 2), S(3ll * n + 3), dt, nullptr, Gm(3ll * n + 3))))
+            return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(g, S(3ll * n_steps), V * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (violations) {
+        unsigned long long v = 0;
+        HIP_TRY(hipMemcpyAsync(&v, pl->viol, sizeof(v), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        *violations = (long long)v;
+    }
+    return GD_OK;
+}
+
+static AdjStageArgs adj_args(const gd_plan* pl)
+{
+    AdjStageArgs a{};
+    a.groups = pl->groups_dev;
+    a.n_groups = int(pl->groups.size());
+    a.n_tiles = pl->tiles32;
+    a.n_bins = pl->n_bins;
+    return a;
+}
+
+// cotangent of a stage's pre-limiter value -> contributions to the cotangents of g_n
+// (acc) and of the stage input y (prev), through L at y
+static int adj_stage(gd_plan* pl, hipStream_t s, const double* kscale, double* mu, double* acc, int acc_add, double a,
+                     double* prev, int prev_add, double b, double bdt, const double* y, double* dks, double* dvf)
+{
+    int rc;
+    AdjStageArgs A = adj_args(pl);
+    A.mu = mu;
+    A.acc = acc;
+    A.acc_add = acc_add;
+    A.a = a;
+    A.prev = prev;
+    A.prev_add = prev_add;
+    A.b = b;
+    A.bdt = bdt;
+    if ((rc = launch_adj_nu(A, s))) return rc;
+    ContractArgs c{pl->groups_dev, pl->adj_items, y, pl->n_adj_items};
+    if ((rc = launch_adjoint_fp64(c, pl->ksomax, s))) return rc;
+    AdjStageArgs C = adj_args(pl);
+    C.y = y;
+    C.prev = prev;
+    C.kscale = kscale;
+    C.dkscale = dks;
+    C.dvfrag = dvf;
+    return launch_adj_combine(C, s);
+}
+
+static int adj_limit(gd_plan* pl, hipStream_t s, double* lam, const double* y, const double* gamma)
+{
+    AdjStageArgs A = adj_args(pl);
+    A.lam = lam;
+    A.y = y;
+    A.gamma = gamma;
+    return launch_adj_limit(A, s);
+}
+
+extern "C" int gd_adjoint(gd_plan* pl, const double* states, const double* gammas, const double* kscale, double dt,
+                          int n_steps, double* lam, double* dkscale, double* dvfrag)
+{
+    if (!pl || !states || !gammas || !lam || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    int rc;
+    if ((rc = prepare_adjoint(pl))) return rc;
+    hipStream_t s = pl->stream;
+    const size_t V = size_t(pl->n_values), B = size_t(pl->n_bins);
+    auto S = [&](long long i) { return states + i * V; };
+    auto Gm = [&](long long i) { return gammas + i * B; };
+    if (dkscale && (rc = launch_fill_f64(dkscale, pl->n_cells, 0.0, s))) return rc;
+    if (dvfrag && (rc = launch_fill_f64(dvfrag, pl->n_cells, 0.0, s))) return rc;
+    // three cotangent buffers rotate: the caller's lam and two of the plan
+    double* buf[3] = {lam, pl->adj_buf[0], pl->adj_buf[1]};
+    int cur = 0;
+    for (int n = n_steps - 1; n >= 0; --n) {
+        const double* gn = S(3ll * n);
+        const double* y1 = S(3ll * n + 1);
+        const double* y2 = S(3ll * n + 2);
+        const double* g1 = S(3ll * n + 3);
+        double* X = buf[cur];
+        double* Acc = buf[(cur + 1) % 3];
+        double* Y = buf[(cur + 2) % 3];
+        // stage 3: g1 = Lim(1/3 gn + 2/3 (y2 + dt L(y2)))
+        if ((rc = adj_limit(pl, s, X, g1, Gm(3ll * n + 3)))) return rc;
+        if ((rc = adj_stage(pl, s, kscale, X, Acc, 0, 1.0 / 3.0, Y, 0, 2.0 / 3.0, 2.0 / 3.0 * dt, y2, dkscale, dvfrag))) return rc;
+        // stage 2: y2 = Lim(3/4 gn + 1/4 (y1 + dt L(y1))); the cotangent of y2 is in Y
+        if ((rc = adj_limit(pl, s, Y, y2, Gm(3ll * n + 2)))) return rc;
+        if ((rc = adj_stage(pl, s, kscale, Y, Acc, 1, 0.75, X, 0, 0.25, 0.25 * dt, y1, dkscale, dvfrag))) return rc;
+        // stage 1: y1 = Lim(gn + dt L(gn)); the cotangent of y1 is in X, that of gn gathers in Acc
+        if ((rc = adj_limit(pl, s, X, y1, Gm(3ll * n + 1)))) return rc;
+        if ((rc = adj_stage(pl, s, kscale, X, nullptr, 0, 0.0, Acc, 1, 1.0, dt, gn, dkscale, dvfrag))) return rc;
+        cur = (cur + 1) % 3;
+    }
+    // the limiter applied to the caller's state before the first step
+    if ((rc = adj_limit(pl, s, buf[cur], S(0), Gm(0)))) return rc;
+    if (cur != 0) HIP_TRY(hipMemcpyAsync(lam, buf[cur], V * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return GD_OK;
+}
+
+// single right-hand-side vector-Jacobian product (test and composition support):
+// grad += J_L(g)^T mu, dkscale += d(mu . L)/ds, dvfrag += d(mu . L)/dv
+extern "C" int gd_collision_vjp(gd_plan* pl, const double* g, const double* kscale, double* mu, double* grad,
+                                double* dkscale, double* dvfrag)
+{
+    if (!pl || !g || !mu || !grad) return fail(GD_EINVAL, "null argument");
+    int rc;
+    if ((rc = prepare_adjoint(pl))) return rc;
+    if (dkscale && (rc = launch_fill_f64(dkscale, pl->n_cells, 0.0, pl->stream))) return rc;
+    if (dvfrag && (rc = launch_fill_f64(dvfrag, pl->n_cells, 0.0, pl->stream))) return rc;
+    return adj_stage(pl, pl->stream, kscale, mu, nullptr, 0, 0.0, grad, 1, 0.0, 1.0, g, dkscale, dvfrag);
+}
+
 // ---------------------------------------------------------------------------- autotuner
 // Times every contraction variant (4 or 8 waves per workgroup; 1, 2 or all row
 // blocks per work item) on the given state and keeps the fastest.  With a cache
@@ -840,7 +1196,7 @@ static std::string tune_key(const gd_plan* pl)
 }
 
 extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* kscale, const char* cache_path,
-                                int* waves, int* rows)
+                                int* waves, int* rows, int* xcd)
 {
     if (!pl || !g) return fail(GD_EINVAL, "null argument");
     const std::string key = tune_key(pl);
@@ -848,20 +1204,22 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "r")) {
             char line[4096];
-            int bw = 0, br = -1;
+            int bw = 0, br = -1, bx = 0;
             while (std::fgets(line, sizeof line, f)) {
                 char k[4000];
-                int w, r;
-                if (std::sscanf(line, "%3999s %d %d", k, &w, &r) == 3 && key == k) {
+                int w, r, x;
+                if (std::sscanf(line, "%3999s %d %d %d", k, &w, &r, &x) == 4 && key == k) {
                     bw = w;
                     br = r;
+                    bx = x;
                 }
             }
             std::fclose(f);
             if ((bw == 4 || bw == 8) && br >= 0) {
-                if ((rc = gd_plan_set_variant(pl, bw, br))) return rc;
+                if ((rc = gd_plan_set_variant(pl, bw, br, bx))) return rc;
                 if (waves) *waves = bw;
                 if (rows) *rows = br;
+                if (xcd) *xcd = bx;
                 return GD_OK;
             }
         }
@@ -872,20 +1230,24 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
     int nob = 1;
     for (const Group& G : pl->groups)
         nob = std::max(nob, pl->prec == GD_PREC_MIXED_F16X3 ? G.t->NOB : G.t->NOB16);
-    std::vector<std::pair<int, int>> cand;
-    for (int w : {4, 8})
-        for (int r : {1, 2, 0})
-            if (r == 0 || r < nob) cand.push_back({w, r});
+    struct Cand {
+        int w, r, x;
+    };
+    std::vector<Cand> cand;
+    for (int x : {1, 0})
+        for (int w : {4, 8})
+            for (int r : {1, 2, 0})
+                if (r == 0 || r < nob) cand.push_back({w, r, x});
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const bool timing = pl->timing;
     pl->timing = false;
     float best = 1e30f;
-    int bw = 4, br = 1;
+    int bw = 4, br = 1, bx = 1;
     rc = GD_OK;
     for (auto& c : cand) {
-        if ((rc = gd_plan_set_variant(pl, c.first, c.second))) break;
+        if ((rc = gd_plan_set_variant(pl, c.w, c.r, c.x))) break;
         if ((rc = contract(pl, s, g))) break;
         if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(GD_EHIP, "event record"); break; }
         for (int i = 0; i < 3 && !rc; ++i) rc = contract(pl, s, g);
@@ -898,22 +1260,24 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
         (void)hipEventElapsedTime(&ms, e0, e1);
         if (ms < best) {
             best = ms;
-            bw = c.first;
-            br = c.second;
+            bw = c.w;
+            br = c.r;
+            bx = c.x;
         }
     }
     pl->timing = timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    if ((rc = gd_plan_set_variant(pl, bw, br))) return rc;
+    if ((rc = gd_plan_set_variant(pl, bw, br, bx))) return rc;
     if (cache_path)
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d\n", key.c_str(), bw, br);
+            std::fprintf(f, "%s %d %d %d\n", key.c_str(), bw, br, bx);
             std::fclose(f);
         }
     if (waves) *waves = bw;
     if (rows) *rows = br;
+    if (xcd) *xcd = bx;
     return GD_OK;
 }
 
@@ -972,23 +1336,36 @@ extern "C" int gd_plan_timing(gd_plan* pl, int enable)
     if (!pl) return fail(GD_EINVAL, "null plan");
     pl->timing = enable != 0;
     pl->timer.used = 0;
+    pl->stimer.used = 0;
+    return GD_OK;
+}
+
+static int read_timer(gd_plan* pl, KernelTimer& T, double* total_ms, int* launches)
+{
+    if (!total_ms || !launches) return fail(GD_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(pl->stream));
+    double tot = 0.0;
+    for (size_t i = 0; i < T.used; ++i) {
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, T.ev[i].first, T.ev[i].second));
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int)T.used;
+    T.used = 0;
     return GD_OK;
 }
 
 extern "C" int gd_plan_contraction_time(gd_plan* pl, double* total_ms, int* launches)
 {
-    if (!pl || !total_ms || !launches) return fail(GD_EINVAL, "null argument");
-    HIP_TRY(hipStreamSynchronize(pl->stream));
-    double tot = 0.0;
-    for (size_t i = 0; i < pl->timer.used; ++i) {
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, pl->timer.ev[i].first, pl->timer.ev[i].second));
-        tot += ms;
-    }
-    *total_ms = tot;
-    *launches = (int)pl->timer.used;
-    pl->timer.used = 0;
-    return GD_OK;
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    return read_timer(pl, pl->timer, total_ms, launches);
+}
+
+extern "C" int gd_plan_stage_time(gd_plan* pl, double* total_ms, int* launches)
+{
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    return read_timer(pl, pl->stimer, total_ms, launches);
 }
 
 extern "C" int gd_plan_schedule_stats(const gd_plan* pl, int group, long long* frags_mixed, long long* frags_fp64,

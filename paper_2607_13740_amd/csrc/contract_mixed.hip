@@ -144,6 +144,7 @@ __global__ __launch_bounds__(64 * W) void k_contract_mixed(ContractArgs a)
     __shared__ uint4 buf0[kFragBudget * 128];
     __shared__ uint4 buf1[kFragBudget * 128];
     const int4 it = cptr(a.items)[blockIdx.x];
+    if (it.x < 0) return;   // padding of an XCD's range
     MixedItem<W> f{cptr(a.groups) + it.x, it.y, it.z & 0xffff, it.z >> 16, it.w, buf0, buf1};
     dispatch_ks<KSMAX>(f.gp->KS, f);
 }

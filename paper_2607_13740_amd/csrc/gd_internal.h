@@ -114,6 +114,19 @@ struct GroupDev {
     int n_slots, tiles32, tiles16;
     int tile_off;              // first 32-slot tile of the group in the stage launch
     int conservative;
+    int R;                     // threshold levels of the tensor
+    long long gam0;            // first bin of the group in per-bin arrays (cells * N per group)
+    // reverse mode (allocated by the first adjoint call)
+    const uint4* afrag;        // FP64 transposed fragments of the vector-Jacobian product
+    const IterDesc* aiters;
+    const int* alist_off;      // [R * NQB]
+    const int* alist_cnt;
+    int KSO, NQB;              // K steps of 16 rows o; blocks of 16 coefficients q
+    double* nu;                // [n_slots][KSO*16] cotangent of the raw flux vector
+    double* G2;                // [n_slots][P] second-sum output
+    double* G1p;               // [parts][NQB][n_slots][P] first-sum partials
+    double* Dth;               // [NQB][n_slots] blend-weight partials
+    const double* dthdv;       // [n_slots] d theta / d v_frag of the slot's cell
 };
 
 // One contraction workgroup: {group, level, ob0 | ob1 << 16, first tile}.  The
@@ -135,9 +148,11 @@ struct ContractArgs {
 //     new state for the next contraction.
 // State pointers are plan-wide; every group adds its own offsets.
 struct StageArgs {
+    double* gamma;             // optional limiter factors [bins] (cell order per group)
     const GroupDev* groups;
     int n_groups;
     int n_tiles;               // 32-slot tiles over all groups
+    int max_bins;              // largest N over the groups (sets the workgroup size)
     int mode;                  // -1 none, 0: out = L, 1..3: RK stage into out
     int limit, split;
     const double* kscale;      // [cells] or nullptr
@@ -149,6 +164,29 @@ struct StageArgs {
     double dt;
 };
 
+// Kernels of the reverse step (see adjoint.hip).
+constexpr int kAdjThreads = 1024;
+struct AdjStageArgs {
+    const GroupDev* groups;
+    int n_groups;
+    int n_tiles;               // 32-slot tiles over all groups
+    long long n_bins;          // bins over all groups
+    const double* gamma;       // k_adj_limit: limiter factors of the stage
+    const double* y;           // k_adj_limit: limited state; k_adj_combine: linearisation state
+    double* lam;               // k_adj_limit: cotangent, in place
+    const double* mu;          // k_adj_nu: cotangent of the stage's pre-limiter value
+    double* acc;               // k_adj_nu: acc (=|+=) a mu (or nullptr)
+    int acc_add;
+    double a;
+    double* prev;              // k_adj_nu: prev (=|+=) b mu; k_adj_combine: prev += s G
+    int prev_add;
+    double b;
+    double bdt;                // b dt
+    const double* kscale;
+    double* dkscale;           // k_adj_combine outputs (+=), [cells] or nullptr
+    double* dvfrag;
+};
+
 // ------------------------------------------------------------------ launchers
 int launch_stage(const StageArgs& a, hipStream_t s);
 int launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
@@ -156,5 +194,10 @@ int launch_project(const double* samples, const double* wP, double* coef, int C,
 // ksmax: largest KS of the plan; waves: 4 or 8 per workgroup
 int launch_contract_mixed(const ContractArgs& a, int ksmax, int waves, hipStream_t s);
 int launch_contract_fp64(const ContractArgs& a, int ksmax, int waves, hipStream_t s);
+int launch_adjoint_fp64(const ContractArgs& a, int ksomax, hipStream_t s);
+int launch_adj_limit(const AdjStageArgs& a, hipStream_t s);
+int launch_adj_nu(const AdjStageArgs& a, hipStream_t s);
+int launch_adj_combine(const AdjStageArgs& a, hipStream_t s);
+int launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 
 } // namespace gd

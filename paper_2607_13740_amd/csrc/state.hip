@@ -3,6 +3,8 @@
 // scaling limiter (Sec. 3.2, Eqs. recon/gamma), the split of the scaled state into
 // FP16 halves for the next contraction, and the projection of initial profiles
 // (Eq. init).
+#include <algorithm>
+
 #include "gd_internal.h"
 
 namespace gd {
@@ -49,10 +51,9 @@ __device__ double poly_min(int k, const double* c)
 // Limiter of one bin in registers: g^i <- gamma g^i (i >= 1) with
 // gamma = min(1, avg / (avg - min)); a non-positive average flattens the bin and a
 // negative one is reported.
-__device__ __forceinline__ int limit_bin(int k, double* c)
+__device__ __forceinline__ int limit_bin(int k, double* c, double& gamma)
 {
     const double avg = c[0];
-    double gamma;
     int viol = 0;
     if (avg <= 0.0) {
         gamma = 0.0;
@@ -71,6 +72,12 @@ __global__ void k_fill_u64(unsigned long long* p, int n)
     if (i < n) p[i] = 0ull;
 }
 
+__global__ void k_fill_f64(double* p, long long n, double v)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // g_j^i = (2i+1)/2 sum_a w_a g0(x_a) P_i(s_a); wP holds (2i+1)/2 w_a P_i(s_a).
 __global__ __launch_bounds__(256) void k_project(const double* samples, const double* wP, double* coef,
                                                  int C, int N, int k)
@@ -87,14 +94,18 @@ __global__ __launch_bounds__(256) void k_project(const double* samples, const do
 }
 
 // ---------------------------------------------------------------------------
-// Fused stage kernel (see StageArgs), 256 threads per tile of 32 slots of one group.
+// Fused stage kernel (see StageArgs), one workgroup per tile of 32 slots of one group,
+// with one thread per (slot, bin) task where the workgroup size allows (phase 1 is
+// a chain of dependent loads: slot -> cell -> state and raw vector).
 // With the split on, phase 1 stages the scaled new state h_j g_q colscale_q of the
 // tile in LDS (rows padded to P+1 doubles against bank conflicts) and collects the
 // largest binary exponent of every slot, so that the FP16 fragments and FP32 weights
 // are written coalesced in phase 2.
 constexpr int kStageMaxP = 192;
 
-__global__ __launch_bounds__(256) void k_stage(StageArgs a)
+constexpr int kStageMaxThreads = 1024;
+
+__global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
 {
     __shared__ double st[32 * (kStageMaxP + 1)];
     __shared__ int smax[32];
@@ -123,7 +134,8 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
 
     // ---- phase 1: one task per (slot, bin)
     int viol = 0;
-    for (int t = tid; t < 32 * N; t += 256) {
+    const int nthr = blockDim.x;
+    for (int t = tid; t < 32 * N; t += nthr) {
         const int sl = t / N, j = t - sl * N;
         const int s = tile * 32 + sl;
         const int c = (s < n_slots) ? (perm ? perm[s] : s) : -1;
@@ -161,9 +173,13 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
                     }
                 }
             }
-            if (a.limit) viol += limit_bin(k, v);
+            if (a.limit) {
+                double gam;
+                viol += limit_bin(k, v, gam);
+                if (a.gamma) a.gamma[G->gam0 + (size_t)c * N + j] = gam;
+            }
             if (a.mode >= 0 || a.limit) {
-                GD_GLOBAL double* o = (a.mode >= 0) ? out : const_cast<GD_GLOBAL double*>(gs);
+                GD_GLOBAL double* o = (a.mode >= 0 || out) ? out : const_cast<GD_GLOBAL double*>(gs);
                 for (int i = 0; i < K1; ++i) o[base + i] = v[i];
             }
         }
@@ -196,7 +212,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
     __syncthreads();
     const int KS = G->KS;
     GD_GLOBAL uint4* mfrag = gptr(G->mfrag);
-    for (int t = tid; t < KS * 64; t += 256) {
+    for (int t = tid; t < KS * 64; t += nthr) {
         const int ks = t >> 6, lane = t & 63, sl = lane & 31, hh = lane >> 5;
         half8_t hi, lo;
         for (int jj = 0; jj < 8; ++jj) {
@@ -212,7 +228,7 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a)
         mfrag[base + 64] = __builtin_bit_cast(uint4, lo);
     }
     GD_GLOBAL float* mt = gptr(G->mt);
-    for (int t = tid; t < P * 32; t += 256) {
+    for (int t = tid; t < P * 32; t += nthr) {
         const int q = t >> 5, sl = t & 31;
         mt[((size_t)tile * P + q) * 32 + sl] = (float)ldexp(st[sl * LD + q], -smax[sl]);
     }
@@ -230,6 +246,14 @@ int launch_stage(const StageArgs& a, hipStream_t s)
 int launch_fill_u64(unsigned long long* p, int n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_fill_u64, dim3(cdiv(n, 64)), dim3(64), 0, s, p, n);
+    HIP_TRY(hipGetLastError());
+    return GD_OK;
+}
+
+int launch_fill_f64(double* p, long long n, double v, hipStream_t s)
+{
+    if (n <= 0) return GD_OK;
+    hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
     HIP_TRY(hipGetLastError());
     return GD_OK;
 }

@@ -86,13 +86,19 @@ def lib():
             "gd_projection_points": ([_VP, _DP], ctypes.c_int),
             "gd_project": ([_VP, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
             "gd_plan_timing": ([_VP, ctypes.c_int], ctypes.c_int),
-            "gd_plan_set_variant": ([_VP, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+            "gd_plan_set_variant": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
             "gd_plan_variant": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                 ctypes.POINTER(ctypes.c_int), _DP], ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _DP], ctypes.c_int),
             "gd_plan_autotune": ([_VP, _VP, _VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
-                                  ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_plan_use_graph": ([_VP, ctypes.c_int], ctypes.c_int),
+            "gd_plan_bins": ([_VP, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+            "gd_rk_forward": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP,
+                               ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+            "gd_adjoint": ([_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
+            "gd_collision_vjp": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
             "gd_plan_contraction_time": ([_VP, _DP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+            "gd_plan_stage_time": ([_VP, _DP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_last_error": ([], ctypes.c_char_p),
         }
         for name, (args, res) in sig.items():
@@ -217,6 +223,9 @@ class Plan:
         _check(lib().gd_plan_sizes(self.h, ctypes.byref(nc), ctypes.byref(nv)))
         self.n_cells, self.n_values = nc.value, nv.value
         self.n_raw = sum(c * t.n_out for t, c in zip(self.tensors, self.cells))
+        nb = ctypes.c_longlong()
+        _check(lib().gd_plan_bins(self.h, ctypes.byref(nb)))
+        self.n_bins = nb.value
 
     def schedule_stats(self, group=0):
         fm, ff, ns = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
@@ -245,24 +254,66 @@ class Plan:
     def timing(self, enable=True):
         _check(lib().gd_plan_timing(self.h, int(bool(enable))))
 
-    def set_variant(self, waves=4, rows=1):
-        """Contraction variant: waves per workgroup (4 or 8), row blocks per item (0 = all)."""
-        _check(lib().gd_plan_set_variant(self.h, int(waves), int(rows)))
+    def rk_forward(self, g, dt, n_steps, kscale=None, count_violations=False):
+        """gd_rk_step on g in place, recording checkpoints; returns (states, gammas[, violations])."""
+        import torch
+        _dev64(g, self.n_values, "g")
+        _dev64(kscale, self.n_cells, "kscale")
+        st = torch.empty((1 + 3 * n_steps) * self.n_values, dtype=torch.float64, device=g.device)
+        gm = torch.empty((1 + 3 * n_steps) * self.n_bins, dtype=torch.float64, device=g.device)
+        v = ctypes.c_longlong(0)
+        _check(lib().gd_rk_forward(self.h, _ptr(g), _ptr(kscale), float(dt), int(n_steps), _ptr(st), _ptr(gm),
+                                   ctypes.byref(v) if count_violations else None))
+        return (st, gm, v.value) if count_violations else (st, gm)
+
+    def adjoint(self, states, gammas, dt, n_steps, lam, kscale=None, want_kscale=True, want_vfrag=True):
+        """lam (dLoss/dg_final) -> dLoss/dg_input in place; returns (dkscale, dvfrag)."""
+        import torch
+        _dev64(lam, self.n_values, "lam")
+        _dev64(kscale, self.n_cells, "kscale")
+        _dev64(states, (1 + 3 * n_steps) * self.n_values, "states")
+        _dev64(gammas, (1 + 3 * n_steps) * self.n_bins, "gammas")
+        dks = torch.empty(self.n_cells, dtype=torch.float64, device=lam.device) if want_kscale else None
+        dvf = torch.empty(self.n_cells, dtype=torch.float64, device=lam.device) if want_vfrag else None
+        _check(lib().gd_adjoint(self.h, _ptr(states), _ptr(gammas), _ptr(kscale), float(dt), int(n_steps),
+                                _ptr(lam), _ptr(dks), _ptr(dvf)))
+        return dks, dvf
+
+    def collision_vjp(self, g, mu, kscale=None, grad=None):
+        """grad += (dL/dg)^T mu; returns (grad, dkscale, dvfrag)."""
+        import torch
+        _dev64(g, self.n_values, "g")
+        _dev64(mu, self.n_values, "mu")
+        _dev64(kscale, self.n_cells, "kscale")
+        if grad is None:
+            grad = torch.zeros_like(g)
+        _dev64(grad, self.n_values, "grad")
+        dks = torch.empty(self.n_cells, dtype=torch.float64, device=g.device)
+        dvf = torch.empty(self.n_cells, dtype=torch.float64, device=g.device)
+        _check(lib().gd_collision_vjp(self.h, _ptr(g), _ptr(kscale), _ptr(mu), _ptr(grad), _ptr(dks), _ptr(dvf)))
+        return grad, dks, dvf
+
+    def set_variant(self, waves=4, rows=1, xcd=1):
+        """Contraction variant: waves per workgroup (4 or 8), row blocks per item (0 = all),
+        items grouped by XCD (1) or in one largest-first order (0)."""
+        _check(lib().gd_plan_set_variant(self.h, int(waves), int(rows), int(xcd)))
 
     def variant(self):
-        w, r, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        w, r, x, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         f = ctypes.c_double()
-        _check(lib().gd_plan_variant(self.h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(n), ctypes.byref(f)))
-        return {"waves": w.value, "rows": r.value, "n_items": n.value, "exec_flops": f.value}
+        _check(lib().gd_plan_variant(self.h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(x), ctypes.byref(n),
+                                     ctypes.byref(f)))
+        return {"waves": w.value, "rows": r.value, "xcd": x.value, "n_items": n.value, "exec_flops": f.value}
 
     def autotune(self, g, kscale=None, cache_path=None):
         """Time every contraction variant on state g and keep the fastest."""
         _dev64(g, self.n_values, "g")
         _dev64(kscale, self.n_cells, "kscale")
-        w, r = ctypes.c_int(), ctypes.c_int()
+        w, r, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         cp = cache_path.encode() if cache_path else None
-        _check(lib().gd_plan_autotune(self.h, _ptr(g), _ptr(kscale), cp, ctypes.byref(w), ctypes.byref(r)))
-        return {"waves": w.value, "rows": r.value}
+        _check(lib().gd_plan_autotune(self.h, _ptr(g), _ptr(kscale), cp, ctypes.byref(w), ctypes.byref(r),
+                                      ctypes.byref(x)))
+        return {"waves": w.value, "rows": r.value, "xcd": x.value}
 
     def use_graph(self, enable=True):
         _check(lib().gd_plan_use_graph(self.h, int(bool(enable))))
@@ -274,8 +325,58 @@ class Plan:
         _check(lib().gd_plan_contraction_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
 
+    def stage_time(self):
+        """(total ms, launches) of the stage kernels since timing was enabled."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(lib().gd_plan_stage_time(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h is not None and _lib is not None:
             _lib.gd_plan_destroy(h)
             self.h = None
+
+
+_RKSOLVE = None
+
+
+def _rksolve_class():
+    global _RKSOLVE
+    if _RKSOLVE is None:
+        import torch
+
+        class RKSolve(torch.autograd.Function):
+            """n_steps of SSP-RK3 with the limiter (gd_rk_forward) whose backward is the
+            library's adjoint (gd_adjoint): gradients for the initial state, the per-cell
+            kernel scale and the per-cell fragmentation threshold.  The threshold tensor
+            only carries the gradient: its values must be the ones the plan was built
+            with (the plan fixes the threshold brackets)."""
+
+            @staticmethod
+            def forward(ctx, g0, kscale, vfrag, plan, dt, n_steps):
+                g = g0.detach().clone().contiguous()
+                ks = None if kscale is None else kscale.detach().contiguous()
+                states, gammas = plan.rk_forward(g, dt, n_steps, kscale=ks)
+                ctx.plan, ctx.dt, ctx.n_steps = plan, dt, n_steps
+                ctx.ks = ks
+                ctx.save_for_backward(states, gammas)
+                return g
+
+            @staticmethod
+            def backward(ctx, grad):
+                states, gammas = ctx.saved_tensors
+                lam = grad.detach().to(torch.float64).clone().contiguous()
+                dks, dvf = ctx.plan.adjoint(states, gammas, ctx.dt, ctx.n_steps, lam, kscale=ctx.ks,
+                                            want_kscale=ctx.needs_input_grad[1],
+                                            want_vfrag=ctx.needs_input_grad[2])
+                return lam, dks, dvf, None, None, None
+
+        _RKSOLVE = RKSolve
+    return _RKSOLVE
+
+
+def rk_solve(plan, g0, dt, n_steps, kscale=None, vfrag=None):
+    """Differentiable n_steps of SSP-RK3 on the plan (see RKSolve)."""
+    return _rksolve_class().apply(g0, kscale, vfrag, plan, dt, n_steps)

@@ -1,0 +1,160 @@
+"""GPU tests of the reverse mode: the FP64 adjoint of the collision step against
+central finite differences of the oracle (FP64, CPU).
+
+The right-hand side is quadratic in the state and linear in the kernel scale and
+(inside a threshold bracket) in the blend weight, so central differences of the
+oracle's L are exact up to rounding there; through RK steps and the limiter they
+are accurate to O(h^2).  Bar: 1e-7 relative for the FP64 adjoint.  Directions are
+seeded; the limiter is active in the start state (noisy higher coefficients), and
+the step stays inside the region where the oracle reports no violation.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2607_13740_amd import gracedg as G  # noqa: E402
+from paper_2607_13740_amd import workloads as W  # noqa: E402
+
+DEV = "cuda:0"
+LV = W.VFRAG_LEVELS
+
+
+def _case(O, N=8, k=2, C=12, seed=3, conservative=True, levels=LV, kernel="ballistic", noise=0.3):
+    t = G.Tensor(N, k, 1e-4, 1e8, kernel=kernel, frag="powerlaw", levels=levels, conservative=conservative)
+    cfg = O.Config(N=N, k=k, xmin=1e-4, xmax=1e8, kernel=kernel, frag="powerlaw", conservative=conservative,
+                   levels=levels if len(levels) > 1 else (), vfrag=levels[0])
+    rng = np.random.default_rng(seed)
+    g = np.stack([O.project(cfg, lambda x, mu=mu: W.lognormal_density(x, mu, 1.0, 1.0))
+                  for mu in rng.uniform(np.log(30.0), np.log(3000.0), C)])
+    g = g.reshape(C, N, k + 1)
+    g[:, :, 1:] += noise * rng.standard_normal((C, N, k)) * np.abs(g[:, :, :1])
+    g = g.reshape(C, -1)
+    ks = np.exp(0.5 * rng.standard_normal(C))
+    vf = rng.uniform(0.32, 0.98, C) if len(levels) > 1 else None
+    return t, cfg, g, ks, vf, rng
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device=DEV)
+
+
+@pytest.mark.parametrize("conservative", [True, False])
+def test_collision_vjp_matches_oracle_differences(oracle, conservative):
+    O = oracle
+    t, cfg, g, ks, vf, rng = _case(O, conservative=conservative)
+    C, P = g.shape
+    plan = G.Plan(t, C, precision="fp64", vfrag=vf)
+    mu = rng.standard_normal((C, P))
+    grad, dks, dvf = plan.collision_vjp(_dev(g).view(-1), _dev(mu).view(-1), kscale=_dev(ks))
+    grad, dks, dvf = grad.cpu().numpy().reshape(C, P), dks.cpu().numpy(), dvf.cpu().numpy()
+
+    def f(gg, kk=ks, vv=vf):
+        return (O.rhs(cfg, gg, kscale=kk, vfrag=vv)[1] * mu).sum(axis=1)
+
+    for _ in range(3):
+        d = rng.standard_normal((C, P)) * np.abs(g).max(axis=1, keepdims=True)
+        h = 1e-3
+        fd = (f(g + h * d) - f(g - h * d)) / (2 * h)
+        ad = (grad * d).sum(axis=1)
+        assert np.max(np.abs(ad - fd) / np.maximum(np.abs(fd), 1e-300)) <= 1e-7, (ad, fd)
+    # kernel scale: mu . L is linear in s
+    fd = (f(g, ks * (1 + 1e-3)) - f(g, ks * (1 - 1e-3))) / (2e-3 * ks)
+    assert np.max(np.abs(dks - fd) / np.abs(fd)) <= 1e-7
+    # threshold: linear in the blend weight inside a bracket
+    hv = 1e-4
+    assert np.min(np.abs(vf[:, None] - np.array(LV)[None, :])) > 2 * hv
+    fd = (f(g, ks, vf + hv) - f(g, ks, vf - hv)) / (2 * hv)
+    scale = np.abs(fd).max()
+    assert np.max(np.abs(dvf - fd)) <= 1e-7 * scale, (dvf, fd)
+
+
+def _loss_oracle(O, cfg, g0, ks, vf, dt, n, w):
+    gf, v = O.rk(cfg, g0, dt, n, kscale=ks, vfrag=vf)
+    assert v == 0
+    return (gf * w).sum(axis=1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk_adjoint_matches_oracle_differences(oracle, prec):
+    """Loss = sum_c w_c . g_c(final) after 3 limited SSP-RK3 steps; gradients with
+    respect to the initial state (directional), kernel scales and thresholds."""
+    O = oracle
+    t, cfg, g, ks, vf, rng = _case(O, C=10, seed=5)
+    C, P = g.shape
+    # a step well inside the oracle's violation-free range for these states (3e-5
+    # already produces a negative bin average)
+    dt, n = 1e-5, 3
+    w = rng.standard_normal((C, P))
+    plan = G.Plan(t, C, precision=prec, vfrag=vf)
+    gd = _dev(g).view(-1)
+    st, gm, v = plan.rk_forward(gd, dt, n, kscale=_dev(ks), count_violations=True)
+    assert v == 0
+    # the limiter was active on the start state (the adjoint passes through it)
+    assert (gm[:plan.n_bins].cpu().numpy() < 1.0).sum() > 0
+    lam = _dev(w).view(-1).clone()
+    dks, dvf = plan.adjoint(st, gm, dt, n, lam, kscale=_dev(ks))
+    lam, dks, dvf = lam.cpu().numpy().reshape(C, P), dks.cpu().numpy(), dvf.cpu().numpy()
+    tol = 1e-7 if prec == "fp64" else 1e-5
+    for _ in range(2):
+        # relative perturbation of every coefficient (d_p = g_p zeta_p), so that bins
+        # holding almost no mass stay where they are
+        d = rng.standard_normal((C, P)) * g
+        h = 1e-6
+        fd = (_loss_oracle(O, cfg, g + h * d, ks, vf, dt, n, w) - _loss_oracle(O, cfg, g - h * d, ks, vf, dt, n, w)) / (2 * h)
+        ad = (lam * d).sum(axis=1)
+        assert np.max(np.abs(ad - fd) / np.abs(fd)) <= tol, (ad, fd)
+    # steps small enough for O(h^2) to vanish at this bar (1e-3 is not), large enough
+    # for rounding of the loss
+    hk = 1e-5
+    fd = (_loss_oracle(O, cfg, g, ks * (1 + hk), vf, dt, n, w) - _loss_oracle(O, cfg, g, ks * (1 - hk), vf, dt, n, w)) / (2 * hk * ks)
+    assert np.max(np.abs(dks - fd)) <= tol * np.abs(fd).max(), (dks, fd)
+    hv = 1e-5
+    assert np.min(np.abs(vf[:, None] - np.array(LV)[None, :])) > 2 * hv
+    fd = (_loss_oracle(O, cfg, g, ks, vf + hv, dt, n, w) - _loss_oracle(O, cfg, g, ks, vf - hv, dt, n, w)) / (2 * hv)
+    assert np.max(np.abs(dvf - fd)) <= tol * np.abs(fd).max(), (dvf, fd)
+
+
+def test_mass_gradient(oracle):
+    """Total mass is conserved by every stage and untouched by the limiter, so for
+    Loss = sum_j h_j g_j^0(final) the gradient is h_j on the averages, zero on the
+    higher coefficients, and zero for the kernel scales and thresholds."""
+    O = oracle
+    t, cfg, g, ks, vf, rng = _case(O, C=16, seed=8)
+    C, P = g.shape
+    plan = G.Plan(t, C, precision="fp64", vfrag=vf)
+    gd = _dev(g).view(-1)
+    dt, n = 1e-5, 4
+    st, gm = plan.rk_forward(gd, dt, n, kscale=_dev(ks))
+    h = np.diff(O.edges(cfg))
+    w = np.zeros((C, cfg.N, cfg.k + 1))
+    w[:, :, 0] = h
+    lam = _dev(w).view(-1).clone()
+    dks, dvf = plan.adjoint(st, gm, dt, n, lam, kscale=_dev(ks))
+    lam = lam.cpu().numpy().reshape(C, cfg.N, cfg.k + 1)
+    assert np.max(np.abs(lam[:, :, 0] - h) / h) <= 1e-10
+    assert np.max(np.abs(lam[:, :, 1:])) <= 1e-10 * h.max()
+    # scale of the individual terms: |lam| times the size of one stage's mass flux
+    ref = np.abs(O.rhs(cfg, g, kscale=ks, vfrag=vf)[1].reshape(C, cfg.N, -1)[:, :, 0] * h).sum(axis=1) * dt * n
+    assert np.all(np.abs(dks.cpu().numpy()) <= 1e-10 * ref / ks)
+    assert np.all(np.abs(dvf.cpu().numpy()) <= 1e-9 * ref * 10)
+
+
+def test_autograd_function(oracle):
+    """torch.autograd through RKSolve gives the adjoint's gradients."""
+    O = oracle
+    t, cfg, g, ks, vf, rng = _case(O, C=6, seed=11)
+    C, P = g.shape
+    plan = G.Plan(t, C, precision="fp64", vfrag=vf)
+    g0 = _dev(g).view(-1).requires_grad_(True)
+    kst = _dev(ks).requires_grad_(True)
+    vft = _dev(vf).requires_grad_(True)
+    w = _dev(rng.standard_normal((C, P))).view(-1)
+    out = G.rk_solve(plan, g0, 2e-6, 2, kscale=kst, vfrag=vft)
+    loss = (out * w).sum()
+    gg, gk, gv = torch.autograd.grad(loss, (g0, kst, vft))
+    st, gm = plan.rk_forward(_dev(g).view(-1), 2e-6, 2, kscale=_dev(ks))
+    lam = w.clone()
+    dks, dvf = plan.adjoint(st, gm, 2e-6, 2, lam, kscale=_dev(ks))
+    assert torch.equal(gg, lam) and torch.equal(gk, dks) and torch.equal(gv, dvf)

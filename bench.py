@@ -144,6 +144,88 @@ def cpu_baseline(w, params, seconds):
                       f"Gauss-Legendre sums in C (gcc -O2, OpenMP across cells), {dt:.1f} s"}
 
 
+def moment_weights(t, pmax=3, R=32):
+    """W[p][j*(k+1)+i] = integral over bin j of x^(p-1) P_i(xi(x)) dx, so that the
+    moment M_p of a cell is W[p] . g (Gauss-Legendre with R points per bin)."""
+    import numpy as np
+    e = t.edges()
+    s, wq = np.polynomial.legendre.leggauss(R)
+    K1 = t.order + 1
+    W = np.zeros((pmax + 1, t.bins * K1))
+    for j in range(t.bins):
+        a, b = e[j], e[j + 1]
+        x = 0.5 * (a + b) + 0.5 * (b - a) * s
+        for i in range(K1):
+            Pi = np.polynomial.legendre.legval(s, [0] * i + [1])
+            for p in range(pmax + 1):
+                W[p, j * K1 + i] = 0.5 * (b - a) * np.sum(wq * x ** (p - 1) * Pi)
+    return W
+
+
+def adjoint_bench(steps_fraction=1.0):
+    """Reverse-mode cost on the adjoint workload: the checkpointed forward (gd_rk_forward)
+    and the adjoint (gd_adjoint) of its n_steps, seeded with the gradient of the
+    moment loss sum_c sum_p ((M_p - M*_p)/M*_p)^2, p = 0..3, where M* are the moments
+    of the unperturbed FP64 run times exp(0.1 eps), eps ~ N(0,1) (seeded)."""
+    import numpy as np
+    import torch
+    from paper_2607_13740_amd import gracedg as G
+    from paper_2607_13740_amd import workloads as W
+
+    dev = "cuda:0"
+    w = W.WORKLOADS["c5_adjoint"]
+    n = max(1, int(w.n_steps * steps_fraction))
+    tensors, counts, g0, ks, vf, _, _ = build_inputs(w, dev)
+    t = tensors[0]
+    C = w.cells
+    Wm = torch.tensor(moment_weights(t), device=dev)              # [4, P]
+    out = {"workload": f"c5_adjoint: {C} cells, {w.bins} bins, order {w.order} (P={w.P}), {n} steps of dt={w.dt:g}, "
+                       "per-cell kernel scale and v_frag, moment loss p=0..3"}
+    ref = g0.clone()
+    G.Plan(tensors, counts, precision="fp64", vfrag=vf).rk_step(ref, w.dt, n, kscale=ks)
+    Mref = ref.view(C, -1) @ Wm.T
+    rng = np.random.default_rng(w.seed)
+    Mstar = Mref * torch.tensor(np.exp(0.1 * rng.standard_normal((C, 4))), device=dev)
+    for prec in ("mixed", "fp64"):
+        plan = G.Plan(tensors, counts, precision=prec, vfrag=vf)
+        g = g0.clone()
+        plan.rk_step(g, w.dt, 2, kscale=ks)          # warm-up (graph capture, kernels)
+        g = g0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.rk_step(g, w.dt, n, kscale=ks)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t0
+        g = g0.clone()
+        st, gm = plan.rk_forward(g, w.dt, 2, kscale=ks)
+        lam = torch.zeros_like(g)
+        plan.adjoint(st, gm, w.dt, 2, lam, kscale=ks)  # warm-up (reverse-mode workspace)
+        del st, gm
+        g = g0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, gm = plan.rk_forward(g, w.dt, n, kscale=ks)
+        torch.cuda.synchronize()
+        t_fwd = time.perf_counter() - t0
+        M = g.view(C, -1) @ Wm.T
+        loss = float((((M - Mstar) / Mstar) ** 2).sum())
+        lam = ((2.0 * (M - Mstar) / Mstar ** 2) @ Wm).reshape(-1).contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dks, dvf = plan.adjoint(st, gm, w.dt, n, lam, kscale=ks)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        out[prec] = {"forward_ms_per_step": t_plain * 1e3 / n, "checkpointed_forward_ms_per_step": t_fwd * 1e3 / n,
+                     "adjoint_ms_per_step": t_adj * 1e3 / n, "adjoint_over_forward": t_adj / t_plain,
+                     "adjoint_over_checkpointed_forward": t_adj / t_fwd, "loss": loss,
+                     "grad_norm": float(lam.norm()), "dkscale_norm": float(dks.norm()),
+                     "dvfrag_norm": float(dvf.norm())}
+        print(f"# adjoint {prec}: forward {t_plain * 1e3 / n:.3f} ms/step (checkpointed {t_fwd * 1e3 / n:.3f}), "
+              f"adjoint {t_adj * 1e3 / n:.3f} ms/step, ratio {t_adj / t_plain:.2f}", file=sys.stderr, flush=True)
+        del st, gm
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +235,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (cells shard with no "
@@ -258,6 +341,8 @@ def main():
                            "variant": f["variant"],
                            "peak_tflops": PEAK_F64_TFLOPS, "mass_drift": f["mass_drift"]}
         out["speedup_mixed_vs_fp64"] = cell_evals / f_evals
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_bench()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, params, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -57,7 +57,7 @@ struct AdjItem {
         const GD_CONST IterDesc* iters = cptr(gp->aiters);
         const GD_GLOBAL int* perm = gptr(gp->perm);
         const GD_GLOBAL double* theta = gptr(gp->theta);
-        const int P = gp->P, n_slots = gp->n_slots, NQB = gp->NQB;
+        const int P = gp->P, n_slots = gp->n_slots, NQB = gp->NQB, NPS = gp->NPS;
         const int tile = tile0 + wave;
         const int col = lane & 15, rsub = lane >> 4;
         const int slot = tile * 16 + col;
@@ -111,8 +111,9 @@ struct AdjItem {
             __syncthreads();
         };
 
-        for (int qb = ob0; qb < ob1; ++qb) {
-            const int list = r * NQB + qb;
+        for (int ob = ob0; ob < ob1; ++ob) {
+            const int qb = ob / NPS, ps = ob - qb * NPS;
+            const int list = r * NQB * NPS + ob;
             const GD_CONST IterDesc* its = iters + cptr(gp->alist_off)[list];
             const int n_it = cptr(gp->alist_cnt)[list];
             G2 = doublex4{0.0, 0.0, 0.0, 0.0};
@@ -138,13 +139,13 @@ struct AdjItem {
                 dB = dD;
             }
             if (cell >= 0) {
-                GD_GLOBAL double* g2 = gptr(gp->G2) + (size_t)slot * P;
+                GD_GLOBAL double* g2 = gptr(gp->G2) + ((size_t)ps * n_slots + slot) * P;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int qq = qb * 16 + 4 * q + rsub;
                     if (qq < P) g2[qq] = G2[q];
                 }
-                if (rsub == 0) gptr(gp->Dth)[(size_t)qb * n_slots + slot] = dth;
+                if (rsub == 0) gptr(gp->Dth)[((size_t)ps * NQB + qb) * n_slots + slot] = dth;
             }
         }
     }
@@ -172,12 +173,14 @@ static int launch_adj(const ContractArgs& a, hipStream_t s)
 
 int launch_adjoint_fp64(const ContractArgs& a, int ksomax, hipStream_t s)
 {
-    if (ksomax <= 6) return launch_adj<6, 8>(a, s);
-    if (ksomax <= 12) return launch_adj<12, 8>(a, s);
+    if (ksomax <= 6) return launch_adj<6, kAdjWaves>(a, s);
+    if (ksomax <= 12) return launch_adj<12, kAdjWaves>(a, s);
     return fail(GD_EUNSUPPORTED, "too many output rows for the adjoint contraction");
 }
 
 // ---------------------------------------------------------------------------- per-bin pieces
+__device__ __forceinline__ int cdiv_dev(int a, int b) { return (a + b - 1) / b; }
+
 __device__ __forceinline__ double leg(int i, double x)
 {
     switch (i) {
@@ -234,6 +237,8 @@ __device__ __forceinline__ int find_group_bins(const GD_CONST GroupDev* groups, 
 //   else, with q = sum_{i>=1} z_i P_i(x*) at the minimiser x* (so gamma = -z_0/q and,
 //   by the envelope theorem, dq/dz_i = P_i(x*)) and S = sum_{i>=1} lam_i z_i:
 //   mu_0 = lam_0 - S/q,   mu_j = gamma lam_j + S z_0 P_j(x*) / q^2.
+// Both are evaluated on u = z / z_0 (scale free: q/z_0 = sum u_i P_i(x*) <= -1), so
+// that bins holding 1e-250 of the mass do not underflow q^2.
 __global__ __launch_bounds__(256) void k_adj_limit(AdjStageArgs a)
 {
     const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -252,18 +257,17 @@ __global__ __launch_bounds__(256) void k_adj_limit(AdjStageArgs a)
         return;
     }
     const GD_GLOBAL double* y = gptr(a.y) + base;
-    double z[4] = {0.0, 0.0, 0.0, 0.0};
-    z[0] = y[0];
-    for (int i = 1; i <= k; ++i) z[i] = y[i] / gam;
-    const double xs = poly_argmin(k, z);
-    double q = 0.0, S = 0.0;
+    double u[4] = {1.0, 0.0, 0.0, 0.0};
+    for (int i = 1; i <= k; ++i) u[i] = (y[i] / gam) / y[0];
+    const double xs = poly_argmin(k, u);
+    double qt = 0.0, St = 0.0;
     for (int i = 1; i <= k; ++i) {
-        q += z[i] * leg(i, xs);
-        S += lam[i] * z[i];
+        qt += u[i] * leg(i, xs);
+        St += lam[i] * u[i];
     }
-    if (!(q < 0.0)) return;   // cannot happen for 0 < gamma < 1
-    const double l0 = lam[0] - S / q;
-    for (int i = 1; i <= k; ++i) lam[i] = gam * lam[i] + S * z[0] * leg(i, xs) / (q * q);
+    if (!(qt < 0.0)) return;   // cannot happen for 0 < gamma < 1
+    const double l0 = lam[0] - St / qt;
+    for (int i = 1; i <= k; ++i) lam[i] = gam * lam[i] + St * leg(i, xs) / (qt * qt);
     lam[0] = l0;
 }
 
@@ -339,7 +343,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_combine(AdjStageArgs a)
     while (gi + 1 < a.n_groups && (int)blockIdx.x >= groups[gi + 1].tile_off) ++gi;
     const GD_CONST GroupDev* G = groups + gi;
     const int tile = (int)blockIdx.x - G->tile_off;
-    const int P = G->P, NQB = G->NQB, n_slots = G->n_slots;
+    const int P = G->P, NQB = G->NQB, NPS = G->NPS, n_slots = G->n_slots;
     const bool blend = G->R > 1;
     const GD_GLOBAL int* perm = gptr(G->perm);
     const GD_GLOBAL double* y = gptr(a.y) + G->val0;
@@ -354,7 +358,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_combine(AdjStageArgs a)
         if (s >= n_slots) continue;
         const int c = perm ? perm[s] : s;
         if (c < 0) continue;
-        double g = G2[(size_t)s * P + p];
+        // second-sum partials: the p ranges present in the block of q = p
+        const int qbp = p / 16, npr = cdiv_dev(min(P, qbp * 16 + 16), kAdjPs);
+        double g = 0.0;
+        for (int ps = 0; ps < npr; ++ps) g += G2[((size_t)ps * n_slots + s) * P + p];
         for (int qb = p / 16; qb < NQB; ++qb) {
             g += G1p[((size_t)qb * n_slots + s) * P + p];
             if (blend) g += G1p[(((size_t)NQB + qb) * n_slots + s) * P + p];
@@ -372,7 +379,10 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_combine(AdjStageArgs a)
                 if (a.dkscale) a.dkscale[G->cell0 + c] += red[threadIdx.x];
                 if (a.dvfrag && blend) {
                     double d = 0.0;
-                    for (int qb = 0; qb < NQB; ++qb) d += G->Dth[(size_t)qb * n_slots + s];
+                    for (int qb = 0; qb < NQB; ++qb) {
+                        const int npr = cdiv_dev(min(P, qb * 16 + 16), kAdjPs);
+                        for (int ps = 0; ps < npr; ++ps) d += G->Dth[((size_t)ps * NQB + qb) * n_slots + s];
+                    }
                     const double sc = a.kscale ? a.kscale[G->cell0 + c] : 1.0;
                     a.dvfrag[G->cell0 + c] += sc * d * G->dthdv[s];
                 }

@@ -64,6 +64,7 @@ struct gd_tensor {
     Schedule adj;              // FP64 transposed layout of the vector-Jacobian product
     bool adj_packed = false;
     int KSO = 0;               // K steps of 16 output rows o (adjoint contraction)
+    int NPS = 0;               // ranges of p per q block (adjoint contraction)
 };
 
 // folded tensor of level r: Tf[o][p][q] = T[o][p][q] + T[o][q][p] (p < q), T[o][p][p]
@@ -194,31 +195,35 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterD
 
 // Schedule of the vector-Jacobian product G_p = sum_o nu_o dY_o/dg_p (FP64).  With
 // M_p[q] = sum_o nu_o Tf[o][p][q] (q >= p), G_p = sum_q M_p[q] g_q + sum_q' M_q'[p] g_q'.
-// One list per (level r, block of 16 q); within it, for both parts and for EVERY
-// p < end of the block (also p without a stored fragment, whose chain is empty, so
-// that every partial output is written), a segment over the K steps of o
-// (16 rows of o each, lo..KSO-1).  Fragment: 16 rows q x 16 o as four 4-column
+// One list per (level r, block qb of 16 q, range ps of kAdjPs values of p); within
+// it, for both parts and for EVERY p of the range below the end of the block (also
+// p without a stored fragment, whose chain is empty, so that every partial output
+// is written), a segment over the K steps of o (16 rows of o each, lo..KSO-1).
+// Lists are numbered (r * NQB + qb) * NPS + ps; a (qb, ps) with no p is empty.  Fragment: 16 rows q x 16 o as four 4-column
 // sub-steps, lane l, sub-step j: Tf[o = 16ks + 4j + l/16][p][q = 16qb + l%16] (q >= p).
 static int pack_adjoint(gd_tensor* t)
 {
     if (t->adj_packed) return GD_OK;
     const int P = t->P, NO = t->n_out, R = t->R;
-    const int NQB = cdiv(P, 16), KSO = cdiv(NO, 16);
+    const int NQB = cdiv(P, 16), KSO = cdiv(NO, 16), NPS = cdiv(P, kAdjPs);
     t->KSO = KSO;
+    t->NPS = NPS;
     std::vector<IterDesc> iters;
     std::vector<int> off, cnt;
     std::vector<double> frag;
     Schedule& S = t->adj;
     int nfrag = 0;
     for (int r = 0; r < R; ++r)
-        for (int qb = 0; qb < NQB; ++qb) {
+        for (int qb = 0; qb < NQB; ++qb)
+        for (int ps = 0; ps < NPS; ++ps) {
             off.push_back(int(iters.size()));
             const int nf0 = nfrag;
             const int pend = std::min(P, qb * 16 + 16);
-            for (int delta = 0; delta <= (r + 1 < R ? 1 : 0); ++delta) {
+            const int p0 = ps * kAdjPs, p1 = std::min(pend, p0 + kAdjPs);
+            for (int delta = 0; delta <= (r + 1 < R ? 1 : 0) && p0 < p1; ++delta) {
                 struct Seg { int p, lo; };
                 std::vector<Seg> segs;
-                for (int p = 0; p < pend; ++p) {
+                for (int p = p0; p < p1; ++p) {
                     int lo = KSO;
                     for (int ks = 0; ks < KSO && lo == KSO; ++ks) {
                         bool nz = false;
@@ -273,7 +278,8 @@ static int pack_adjoint(gd_tensor* t)
     S.frag = dfrag;
     S.frags = (long long)(frag.size() / 256);
     S.iters_total = (long long)iters.size();
-    S.NOB = NQB;
+    S.NOB = NQB * NPS;
+    S.list_n = cnt;
     if ((rc = upload(t->bufs, iters, &S.iters, &t->bytes))) return rc;
     if ((rc = upload(t->bufs, off, &S.list_off, &t->bytes))) return rc;
     if ((rc = upload(t->bufs, cnt, &S.list_cnt, &t->bytes))) return rc;
@@ -617,6 +623,7 @@ static void make_items(const gd_plan* pl, int which, int W, int rows, int xcd, s
             const int t0 = b.s0 / ts, t1 = cdiv(b.s0 + b.n, ts);
             for (int ob = 0; ob < NOB; ob += nr) {
                 const int ob1 = std::min(NOB, ob + nr);
+                if (!S.list_n.empty() && S.list_n[size_t(b.r) * NOB + ob] == 0) continue;   // empty list
                 long long c = 4, f = 0;
                 for (int o = ob; o < ob1; ++o) {
                     c += S.list_cost[size_t(b.r) * NOB + o];
@@ -1018,14 +1025,15 @@ static int prepare_adjoint(gd_plan* pl)
         d.alist_off = t->adj.list_off;
         d.alist_cnt = t->adj.list_cnt;
         d.KSO = t->KSO;
-        d.NQB = t->adj.NOB;
+        d.NQB = cdiv(t->P, 16);
+        d.NPS = t->NPS;
         pl->ksomax = std::max(pl->ksomax, t->KSO);
         const size_t ns = size_t(std::max(1, G.n_slots));
         double *nu, *g2, *g1, *dt_, *dv;
         if ((rc = dalloc(pl, &nu, ns * t->KSO * 16))) return rc;
-        if ((rc = dalloc(pl, &g2, ns * t->P))) return rc;
+        if ((rc = dalloc(pl, &g2, size_t(t->NPS) * ns * t->P))) return rc;
         if ((rc = dalloc(pl, &g1, size_t(t->R > 1 ? 2 : 1) * d.NQB * ns * t->P))) return rc;
-        if ((rc = dalloc(pl, &dt_, size_t(d.NQB) * ns))) return rc;
+        if ((rc = dalloc(pl, &dt_, size_t(d.NQB) * t->NPS * ns))) return rc;
         std::vector<double> dthdv = G.h_dthdv;
         dthdv.resize(ns, 0.0);
         if ((rc = dcopy(pl, &dv, dthdv))) return rc;
@@ -1039,7 +1047,7 @@ static int prepare_adjoint(gd_plan* pl)
     for (double*& b : pl->adj_buf)
         if ((rc = dalloc(pl, &b, pl->n_values))) return rc;
     std::vector<int4> h;
-    make_items(pl, 1, 8, 1, 1, h, nullptr);
+    make_items(pl, 1, kAdjWaves, 1, 1, h, nullptr);
     size_t cap = 0;
     if ((rc = upload_items(h, &pl->adj_items, &cap))) return rc;
     pl->n_adj_items = int(h.size());

@@ -83,6 +83,7 @@ struct Schedule {
     const float* scale = nullptr;         // split path: stage-2 factors
     std::vector<long long> list_cost;     // host: fragments + iterations of every list
     std::vector<long long> list_frags;    // host: fragments of every list
+    std::vector<int> list_n;              // host: iterations of every list (adjoint: 0 = empty list)
     int NOB = 0;                          // row blocks
     long long frags = 0;                  // stored fragments (all levels)
     long long iters_total = 0;
@@ -121,11 +122,11 @@ struct GroupDev {
     const IterDesc* aiters;
     const int* alist_off;      // [R * NQB]
     const int* alist_cnt;
-    int KSO, NQB;              // K steps of 16 rows o; blocks of 16 coefficients q
+    int KSO, NQB, NPS;         // K steps of 16 rows o; blocks of 16 coefficients q; ranges of p
     double* nu;                // [n_slots][KSO*16] cotangent of the raw flux vector
-    double* G2;                // [n_slots][P] second-sum output
+    double* G2;                // [NPS][n_slots][P] second-sum partials (one per p range)
     double* G1p;               // [parts][NQB][n_slots][P] first-sum partials
-    double* Dth;               // [NQB][n_slots] blend-weight partials
+    double* Dth;               // [NPS][NQB][n_slots] blend-weight partials
     const double* dthdv;       // [n_slots] d theta / d v_frag of the slot's cell
 };
 
@@ -166,6 +167,8 @@ struct StageArgs {
 
 // Kernels of the reverse step (see adjoint.hip).
 constexpr int kAdjThreads = 1024;
+constexpr int kAdjPs = 32;     // values of p per list of the vector-Jacobian product
+constexpr int kAdjWaves = 4;   // waves per workgroup of the vector-Jacobian product
 struct AdjStageArgs {
     const GroupDev* groups;
     int n_groups;

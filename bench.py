@@ -144,6 +144,21 @@ def cpu_baseline(w, params, seconds):
                       f"Gauss-Legendre sums in C (gcc -O2, OpenMP across cells), {dt:.1f} s"}
 
 
+def measured_traffic():
+    """HBM bytes of one split-FP16 contraction launch from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE measurement, scaled by the copy-kernel factors; None when the
+    kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_contract_mixed_c3_batched_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec["source_files"]:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+
+
 def moment_weights(t, pmax=3, R=32):
     """W[p][j*(k+1)+i] = integral over bin j of x^(p-1) P_i(xi(x)) dx, so that the
     moment M_p of a cell is W[p] . g (Gauss-Legendre with R points per bin)."""
@@ -236,6 +251,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--variant", default=None,
+                    help="waves,rows,xcd of the contraction instead of the autotuner's choice (e.g. 8,1,1)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (cells shard with no "
@@ -259,7 +276,12 @@ def main():
     for prec in (("mixed",) if args.no_fp64 else ("mixed", "fp64")):
         plan = G.Plan(tensors, counts, precision=prec, vfrag=vf)
         g = g0.clone()
-        tune = plan.autotune(g, kscale=ks)
+        if args.variant:
+            wv, rv, xv = (int(x) for x in args.variant.split(","))
+            plan.set_variant(wv, rv, xv)
+            tune = {"waves": wv, "rows": rv, "xcd": xv, "fixed": True}
+        else:
+            tune = plan.autotune(g, kscale=ks)
         ms, kms, launches, sms = time_steps(plan, g, w, ks, args.steps, args.warmup)
         res[prec] = {"ms_per_step": ms, "kernel_ms": kms, "launches": launches, "plan": plan, "stage_ms": sms,
                      "variant": plan.variant(), "tune": tune}
@@ -321,7 +343,8 @@ def main():
                                 "FP64 state/limiter/RK",
                    "contraction_variant": mixed["variant"], "step": "one captured HIP graph per RK step"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_F16_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_F16_TFLOPS,
+                     "traffic": measured_traffic() if w.name == "c3_batched" else None,
                      "kernel": "k_contract_mixed", "kernel_ms": mixed["kernel_ms"],
                      "algorithmic_flops_per_launch": flops_launch,
                      "flops_per_cell_eval": flops_launch / C,

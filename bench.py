@@ -252,7 +252,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--variant", default=None,
-                    help="waves,rows,xcd of the contraction instead of the autotuner's choice (e.g. 8,1,1)")
+                    help="waves,rows,xcd[,tiles_per_wave] of the contraction instead of the autotuner's choice")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (cells shard with no "
@@ -277,9 +277,10 @@ def main():
         plan = G.Plan(tensors, counts, precision=prec, vfrag=vf)
         g = g0.clone()
         if args.variant:
-            wv, rv, xv = (int(x) for x in args.variant.split(","))
-            plan.set_variant(wv, rv, xv)
-            tune = {"waves": wv, "rows": rv, "xcd": xv, "fixed": True}
+            vv = [int(x) for x in args.variant.split(",")] + [1]
+            tp = vv[3] if prec == "mixed" else 1
+            plan.set_variant(vv[0], vv[1], vv[2], tp)
+            tune = {"waves": vv[0], "rows": vv[1], "xcd": vv[2], "tiles_per_wave": tp, "fixed": True}
         else:
             tune = plan.autotune(g, kscale=ks)
         ms, kms, launches, sms = time_steps(plan, g, w, ks, args.steps, args.warmup)

@@ -213,19 +213,21 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, doubl
  * are likewise one launch over all groups.
  *
  * gd_plan_set_variant -- choose the contraction variant: waves (4 or 8) per
- *   workgroup, each wave one tile of cells (32 split-FP16, 16 FP64); rows = row
- *   blocks per work item (0 = all of the group's row blocks); xcd = 1 orders the
- *   items in 8 contiguous cost-balanced ranges, one per XCD (workgroup b runs on
- *   XCD b % 8), so that the workgroups sharing an L2 stream the fragments of few
- *   iteration lists; xcd = 0 orders all items largest first.  Every variant gives
- *   bit-identical results.  Rebuilds the item list (synchronous).
+ *   workgroup; tiles_per_wave (1, or 2 for split-FP16 plans with 4 waves and
+ *   P <= 96: one A fragment read feeds two independent MFMA chains), a tile being
+ *   32 cells (split FP16) or 16 cells (FP64); rows = row blocks per work item (0 =
+ *   all of the group's row blocks); xcd = 1 orders the items in 8 contiguous
+ *   cost-balanced ranges, one per XCD (workgroup b runs on XCD b % 8), so that the
+ *   workgroups sharing an L2 stream the fragments of few iteration lists; xcd = 0
+ *   orders all items largest first.  Every variant gives bit-identical results.
+ *   Rebuilds the item list (synchronous).
  * gd_plan_variant -- the current variant, the number of workgroups of one
  *   contraction launch (items plus padding) and the MFMA flops one launch executes
  *   (every stored fragment, all products, for every tile of an item); any pointer
  *   may be NULL.
  * gd_plan_autotune -- time every variant on state g (device, state layout, read
  *   only; kscale as in gd_rk_step) and keep the fastest.  cache_path (or NULL)
- *   names a text file of "key waves rows xcd" lines: a plan of the same shape (precision,
+ *   names a text file of "key waves tiles_per_wave rows xcd" lines: a plan of the same shape (precision,
  *   bins, order, levels, cells and brackets of every group) takes its stored
  *   choice without timing; a newly timed choice is appended.  Synchronous.
  * gd_plan_use_graph -- (default on) gd_rk_step captures one RK step (three
@@ -234,10 +236,11 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, doubl
  *   when g, kscale, dt or the variant change.  Off: the launches are issued one by
  *   one.  Timing (gd_plan_timing) also issues them one by one.
  */
-int gd_plan_set_variant(gd_plan* plan, int waves, int rows, int xcd);
-int gd_plan_variant(const gd_plan* plan, int* waves, int* rows, int* xcd, int* n_items, double* exec_flops);
+int gd_plan_set_variant(gd_plan* plan, int waves, int tiles_per_wave, int rows, int xcd);
+int gd_plan_variant(const gd_plan* plan, int* waves, int* tiles_per_wave, int* rows, int* xcd, int* n_items,
+                    double* exec_flops);
 int gd_plan_autotune(gd_plan* plan, const double* g, const double* kscale, const char* cache_path, int* waves,
-                     int* rows, int* xcd);
+                     int* tiles_per_wave, int* rows, int* xcd);
 int gd_plan_use_graph(gd_plan* plan, int enable);
 
 /*

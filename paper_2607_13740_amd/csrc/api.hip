@@ -62,6 +62,11 @@ struct gd_tensor {
     const double* rowscale = nullptr;   // [NOB*32]
     Schedule mixed, f64;
     Schedule adj;              // FP64 transposed layout of the vector-Jacobian product
+    // Rows of the forward schedules are ordered bin by bin (F_j with V_{j,1..k}), so that
+    // a row block covers neighbouring masses and its nonzero (p, q) blocks are few:
+    // rowperm[position] = row o, ypos[o] = position of row o in the raw buffers.
+    std::vector<int> rowperm;
+    const int* ypos = nullptr;
     bool adj_packed = false;
     int KSO = 0;               // K steps of 16 output rows o (adjoint contraction)
     int NPS = 0;               // ranges of p per q block (adjoint contraction)
@@ -145,7 +150,7 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterD
                             bool nz = false;
                             for (int o = ob * RB; o < std::min(NO, ob * RB + RB) && !nz; ++o)
                                 for (int q = std::max(p, ks * KW); q < std::min(P, ks * KW + KW); ++q)
-                                    if (part(t, r, delta, o, p, q) != 0.0) { nz = true; break; }
+                                    if (part(t, r, delta, t->rowperm[o], p, q) != 0.0) { nz = true; break; }
                             if (nz) lo = ks;
                         }
                         if (lo >= 0) segs.push_back({p, lo});
@@ -301,12 +306,25 @@ static int pack_tensor(gd_tensor* t)
     for (int j = 0; j < t->N; ++j) h[j] = t->host.edges[j + 1] - t->host.edges[j];
     if ((rc = upload(t->bufs, h, &t->h, &t->bytes))) return rc;
 
+    {
+        const int N = t->N, k = t->k, vbase = (N - 1) + (t->spec.conservative ? 0 : 1);
+        t->rowperm.clear();
+        for (int j = 0; j < N; ++j) {
+            if (j >= 1) t->rowperm.push_back(j - 1);
+            for (int i = 1; i <= k; ++i) t->rowperm.push_back(vbase + j * k + i - 1);
+        }
+        if (!t->spec.conservative) t->rowperm.push_back(N - 1);
+        std::vector<int> ypos(NO);
+        for (int q = 0; q < NO; ++q) ypos[t->rowperm[q]] = q;
+        if ((rc = upload(t->bufs, ypos, &t->ypos, &t->bytes))) return rc;
+    }
+
     // ---------------- scaling of the split path.  U = Tf / (h_l h_m).
     // rowscale_o = 2^ceil(log2 max |U[o]|) over all levels; colscale_q = 2^ceil(log2 of
     // the largest |U[.][.][q]| / rowscale) over all levels.  T is divided by both and the
     // state multiplied by colscale, so that columns whose entries are large (small
     // colliding masses) do not meet the FP16 absolute floor of small state values.
-    auto U = [&](int r, int delta, int o, int p, int q) { return part(t, r, delta, o, p, q) / (h[p / K1] * h[q / K1]); };
+    auto U = [&](int r, int delta, int o, int p, int q) { return part(t, r, delta, t->rowperm[o], p, q) / (h[p / K1] * h[q / K1]); };
     std::vector<double> rs(size_t(t->NOB) * 32, 1.0), colmax(P, 0.0);
     for (int o = 0; o < NO; ++o) {
         double mx = 0.0;
@@ -390,7 +408,7 @@ static int pack_tensor(gd_tensor* t)
             for (int j = 0; j < 4; ++j)
                 for (int l = 0; l < 64; ++l) {
                     const int o = ob * 16 + (l & 15), q = ks * 16 + 4 * j + (l >> 4);
-                    if (o < NO && q < P && q >= p) frag[f * 256 + j * 64 + l] = part(t, r, delta, o, p, q);
+                    if (o < NO && q < P && q >= p) frag[f * 256 + j * 64 + l] = part(t, r, delta, t->rowperm[o], p, q);
                 }
         };
         build_schedule(t, 16, 16, iters, off, cnt, t->f64.list_cost, t->f64.list_frags, emit, blockscale);
@@ -526,10 +544,10 @@ struct gd_plan {
     hipStream_t stream = nullptr;
     hipStream_t cap = nullptr;              // private stream the step graph is captured on
     long long n_cells = 0, n_values = 0, n_raw = 0;
-    int ksmax = 1, tiles32 = 0, max_bins = 1;
+    int ksmax = 1, tiles32 = 0, max_p = 1;
     GroupDev* groups_dev = nullptr;
-    int waves = 4, rows = 1, xcd = 1;       // contraction variant: waves per workgroup, row blocks per item,
-                                            // items grouped by XCD
+    int waves = 4, tpw = 1, rows = 1, xcd = 1;   // contraction variant: waves per workgroup, tiles per wave,
+                                                 // row blocks per item, items grouped by XCD
     int4* items = nullptr;
     int n_items = 0;
     size_t items_cap = 0;
@@ -601,7 +619,7 @@ static constexpr int kSlotGranule = 256;
 // Ranges of unequal length are padded with empty items (group -1).
 // Item list of one contraction over every group of the plan: the lists of schedule
 // `which` (0: the plan's forward precision, 1: the FP64 vector-Jacobian product),
-// workgroups of W waves over tiles of ts slots.
+// workgroups over W consecutive tiles of ts slots.
 static void make_items(const gd_plan* pl, int which, int W, int rows, int xcd, std::vector<int4>& h, double* flops)
 {
     const bool mixed = which == 0 && pl->prec == GD_PREC_MIXED_F16X3;
@@ -682,7 +700,7 @@ static int build_items(gd_plan* pl)
 {
     std::vector<int4> h;
     double fl = 0.0;
-    make_items(pl, 0, pl->waves, pl->rows, pl->xcd, h, &fl);
+    make_items(pl, 0, pl->waves * pl->tpw, pl->rows, pl->xcd, h, &fl);
     int rc = upload_items(h, &pl->items, &pl->items_cap);
     if (rc) return rc;
     pl->n_items = int(h.size());
@@ -715,7 +733,7 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
         pl->n_values += (long long)G.C * G.t->P;
         pl->n_raw += (long long)G.C * G.t->n_out;
         pl->ksmax = std::max(pl->ksmax, G.t->KS);
-        pl->max_bins = std::max(pl->max_bins, G.t->N);
+        pl->max_p = std::max(pl->max_p, G.t->P);
         pl->groups.push_back(std::move(G));
     }
     if (pl->n_cells > (1ll << 30)) return fail(GD_EINVAL, "too many cells");
@@ -787,6 +805,7 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
         d.h = t->h;
         d.colscale = t->colscale;
         d.rowscale = t->rowscale;
+        d.ypos = t->ypos;
         d.perm = G.perm;
         d.theta = G.theta;
         d.mfrag = G.mfrag;
@@ -843,21 +862,27 @@ extern "C" int gd_plan_bins(const gd_plan* pl, long long* n_bins)
 
 extern "C" void gd_plan_destroy(gd_plan* pl) { delete pl; }
 
-extern "C" int gd_plan_set_variant(gd_plan* pl, int waves, int rows, int xcd)
+extern "C" int gd_plan_set_variant(gd_plan* pl, int waves, int tiles_per_wave, int rows, int xcd)
 {
     if (!pl) return fail(GD_EINVAL, "null plan");
     if (waves != 4 && waves != 8) return fail(GD_EINVAL, "waves must be 4 or 8");
+    if (tiles_per_wave != 1 && tiles_per_wave != 2) return fail(GD_EINVAL, "tiles_per_wave must be 1 or 2");
+    if (tiles_per_wave == 2 && (pl->prec != GD_PREC_MIXED_F16X3 || waves != 4 || pl->ksmax > 6))
+        return fail(GD_EINVAL, "two tiles per wave: split precision, 4 waves, P <= 96");
     if (rows < 0) return fail(GD_EINVAL, "rows must be >= 0");
     pl->waves = waves;
+    pl->tpw = tiles_per_wave;
     pl->rows = rows;
     pl->xcd = xcd ? 1 : 0;
     return build_items(pl);
 }
 
-extern "C" int gd_plan_variant(const gd_plan* pl, int* waves, int* rows, int* xcd, int* n_items, double* exec_flops)
+extern "C" int gd_plan_variant(const gd_plan* pl, int* waves, int* tiles_per_wave, int* rows, int* xcd, int* n_items,
+                               double* exec_flops)
 {
     if (!pl) return fail(GD_EINVAL, "null plan");
     if (waves) *waves = pl->waves;
+    if (tiles_per_wave) *tiles_per_wave = pl->tpw;
     if (rows) *rows = pl->rows;
     if (xcd) *xcd = pl->xcd;
     if (n_items) *n_items = pl->n_items;
@@ -898,7 +923,7 @@ static int stage(gd_plan* pl, hipStream_t s, int mode, int limit, int split, con
     a.groups = pl->groups_dev;
     a.n_groups = int(pl->groups.size());
     a.n_tiles = pl->tiles32;
-    a.max_bins = pl->max_bins;
+    a.max_p = pl->max_p;
     a.mode = mode;
     a.limit = limit;
     a.split = split;
@@ -925,7 +950,7 @@ static int contract(gd_plan* pl, hipStream_t s, const double* gs)
     int rc = timer_begin(pl, pl->timer, s, &ev_end);
     if (rc) return rc;
     ContractArgs a{pl->groups_dev, pl->items, gs, pl->n_items};
-    rc = (pl->prec == GD_PREC_MIXED_F16X3) ? launch_contract_mixed(a, pl->ksmax, pl->waves, s)
+    rc = (pl->prec == GD_PREC_MIXED_F16X3) ? launch_contract_mixed(a, pl->ksmax, pl->waves, pl->tpw, s)
                                                : launch_contract_fp64(a, pl->ksmax, pl->waves, s);
     if (rc) return rc;
     if (ev_end) HIP_TRY(hipEventRecord(ev_end, s));
@@ -1204,7 +1229,7 @@ static std::string tune_key(const gd_plan* pl)
 }
 
 extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* kscale, const char* cache_path,
-                                int* waves, int* rows, int* xcd)
+                                int* waves, int* tiles_per_wave, int* rows, int* xcd)
 {
     if (!pl || !g) return fail(GD_EINVAL, "null argument");
     const std::string key = tune_key(pl);
@@ -1212,20 +1237,22 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "r")) {
             char line[4096];
-            int bw = 0, br = -1, bx = 0;
+            int bw = 0, bt = 1, br = -1, bx = 0;
             while (std::fgets(line, sizeof line, f)) {
                 char k[4000];
-                int w, r, x;
-                if (std::sscanf(line, "%3999s %d %d %d", k, &w, &r, &x) == 4 && key == k) {
+                int w, tt, r, x;
+                if (std::sscanf(line, "%3999s %d %d %d %d", k, &w, &tt, &r, &x) == 5 && key == k) {
                     bw = w;
+                    bt = tt;
                     br = r;
                     bx = x;
                 }
             }
             std::fclose(f);
             if ((bw == 4 || bw == 8) && br >= 0) {
-                if ((rc = gd_plan_set_variant(pl, bw, br, bx))) return rc;
+                if ((rc = gd_plan_set_variant(pl, bw, bt, br, bx))) return rc;
                 if (waves) *waves = bw;
+                if (tiles_per_wave) *tiles_per_wave = bt;
                 if (rows) *rows = br;
                 if (xcd) *xcd = bx;
                 return GD_OK;
@@ -1239,23 +1266,24 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
     for (const Group& G : pl->groups)
         nob = std::max(nob, pl->prec == GD_PREC_MIXED_F16X3 ? G.t->NOB : G.t->NOB16);
     struct Cand {
-        int w, r, x;
+        int w, t, r, x;
     };
     std::vector<Cand> cand;
+    const bool two = pl->prec == GD_PREC_MIXED_F16X3 && pl->ksmax <= 6;
     for (int x : {1, 0})
-        for (int w : {4, 8})
+        for (int wt : {41, 81, 42})
             for (int r : {1, 2, 0})
-                if (r == 0 || r < nob) cand.push_back({w, r, x});
+                if ((r == 0 || r < nob) && (wt != 42 || two)) cand.push_back({wt / 10, wt % 10, r, x});
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     const bool timing = pl->timing;
     pl->timing = false;
     float best = 1e30f;
-    int bw = 4, br = 1, bx = 1;
+    int bw = 4, bt = 1, br = 1, bx = 1;
     rc = GD_OK;
     for (auto& c : cand) {
-        if ((rc = gd_plan_set_variant(pl, c.w, c.r, c.x))) break;
+        if ((rc = gd_plan_set_variant(pl, c.w, c.t, c.r, c.x))) break;
         if ((rc = contract(pl, s, g))) break;
         if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(GD_EHIP, "event record"); break; }
         for (int i = 0; i < 3 && !rc; ++i) rc = contract(pl, s, g);
@@ -1269,6 +1297,7 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
         if (ms < best) {
             best = ms;
             bw = c.w;
+            bt = c.t;
             br = c.r;
             bx = c.x;
         }
@@ -1277,13 +1306,14 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    if ((rc = gd_plan_set_variant(pl, bw, br, bx))) return rc;
+    if ((rc = gd_plan_set_variant(pl, bw, bt, br, bx))) return rc;
     if (cache_path)
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %d\n", key.c_str(), bw, br, bx);
+            std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), bw, bt, br, bx);
             std::fclose(f);
         }
     if (waves) *waves = bw;
+    if (tiles_per_wave) *tiles_per_wave = bt;
     if (rows) *rows = br;
     if (xcd) *xcd = bx;
     return GD_OK;

@@ -100,7 +100,8 @@ struct GroupDev {
     const float* scale;
     const double* h;           // [N] bin widths
     const double* colscale;    // [P]   split path column factors
-    const double* rowscale;    // [NOB*32] split path row factors
+    const double* rowscale;    // [NOB*32] split path row factors (by position)
+    const int* ypos;           // [n_out] position of raw-vector row o in Y and rowscale
     const int* perm;           // [n_slots] slot -> cell of the group (-1: padding); nullptr: identity
     const double* theta;       // [n_slots] blend weight; nullptr: 0
     uint4* mfrag;              // split path B operands [tiles32][KS][hi|lo][64 lanes]
@@ -153,7 +154,7 @@ struct StageArgs {
     const GroupDev* groups;
     int n_groups;
     int n_tiles;               // 32-slot tiles over all groups
-    int max_bins;              // largest N over the groups (sets the workgroup size)
+    int max_p;                 // largest P over the groups (sets the LDS size)
     int mode;                  // -1 none, 0: out = L, 1..3: RK stage into out
     int limit, split;
     const double* kscale;      // [cells] or nullptr
@@ -195,7 +196,7 @@ int launch_stage(const StageArgs& a, hipStream_t s);
 int launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
 int launch_project(const double* samples, const double* wP, double* coef, int C, int N, int k, hipStream_t s);
 // ksmax: largest KS of the plan; waves: 4 or 8 per workgroup
-int launch_contract_mixed(const ContractArgs& a, int ksmax, int waves, hipStream_t s);
+int launch_contract_mixed(const ContractArgs& a, int ksmax, int waves, int tpw, hipStream_t s);
 int launch_contract_fp64(const ContractArgs& a, int ksmax, int waves, hipStream_t s);
 int launch_adjoint_fp64(const ContractArgs& a, int ksomax, hipStream_t s);
 int launch_adj_limit(const AdjStageArgs& a, hipStream_t s);

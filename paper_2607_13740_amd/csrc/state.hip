@@ -95,19 +95,22 @@ __global__ __launch_bounds__(256) void k_project(const double* samples, const do
 
 // ---------------------------------------------------------------------------
 // Fused stage kernel (see StageArgs), one workgroup per tile of 32 slots of one group,
-// with one thread per (slot, bin) task where the workgroup size allows (phase 1 is
-// a chain of dependent loads: slot -> cell -> state and raw vector).
+// with one thread per (slot, bin) task where the workgroup size allows.  The per-slot
+// values (cell, exponent, kernel scale) are fetched once into LDS, and the
+// coefficients of a bin move as 16-byte vectors when order + 1 is even.
 // With the split on, phase 1 stages the scaled new state h_j g_q colscale_q of the
-// tile in LDS (rows padded to P+1 doubles against bank conflicts) and collects the
-// largest binary exponent of every slot, so that the FP16 fragments and FP32 weights
-// are written coalesced in phase 2.
+// tile in LDS (FP64: its range exceeds FP32 before the per-slot power of two is
+// known; rows padded to P+1 against bank conflicts) and collects the largest binary
+// exponent of every slot, so that the FP16 fragments and FP32 weights are written
+// coalesced in phase 2.  Small workgroups with LDS sized to the plan's largest P keep
+// most tiles of a launch resident at once.
 constexpr int kStageMaxP = 192;
+constexpr int kStageThreads = 256;
 
-constexpr int kStageMaxThreads = 1024;
-
-__global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
+template <int PMAX>
+__global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
 {
-    __shared__ double st[32 * (kStageMaxP + 1)];
+    __shared__ double st[32 * (PMAX + 1)];
     __shared__ int smax[32];
     const GD_CONST GroupDev* groups = cptr(a.groups);
     int gi = 0;
@@ -120,6 +123,7 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
     const GD_CONST double* h = cptr(G->h);
     const GD_GLOBAL double* cs = gptr(G->colscale);
     const GD_CONST double* rowscale = cptr(G->rowscale);
+    const GD_CONST int* ypos = cptr(G->ypos);
     const GD_GLOBAL int* perm = gptr(G->perm);
     const GD_GLOBAL float* Yf = gptr(G->Yf);
     const GD_GLOBAL double* Yd = gptr(G->Yd);
@@ -129,8 +133,22 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
     const GD_GLOBAL double* gs = gptr(a.gs) + G->val0;
     GD_GLOBAL double* out = a.out ? gptr(a.out) + G->val0 : nullptr;
     GD_GLOBAL double* raw = a.raw ? gptr(a.raw) + G->raw0 : nullptr;
-    if (a.split && tid < 32) smax[tid] = INT_MIN;
-    if (a.split) __syncthreads();
+    __shared__ int scell[32];
+    __shared__ double sfac[32];
+    if (tid < 32) {
+        const int s = tile * 32 + tid;
+        const int c = (s < n_slots) ? (perm ? perm[s] : s) : -1;
+        scell[tid] = c;
+        double fac = (c >= 0 && kscale) ? kscale[c] : 1.0;
+        if (c >= 0 && a.mode >= 0 && Yf) fac = ldexp(fac, 2 * eslot[s]);
+        sfac[tid] = fac;
+        if (a.split) smax[tid] = INT_MIN;
+    }
+    __syncthreads();
+
+    // 16-byte moves need an even order + 1 and 16-byte aligned bin starts
+    auto al16 = [](const void* p) { return p == nullptr || ((uintptr_t)p & 15) == 0; };
+    const bool vec = (K1 & 1) == 0 && al16(gs) && al16(gn) && al16(out);
 
     // ---- phase 1: one task per (slot, bin)
     int viol = 0;
@@ -138,18 +156,31 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
     for (int t = tid; t < 32 * N; t += nthr) {
         const int sl = t / N, j = t - sl * N;
         const int s = tile * 32 + sl;
-        const int c = (s < n_slots) ? (perm ? perm[s] : s) : -1;
+        const int c = scell[sl];
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         if (c >= 0) {
             const size_t base = (size_t)c * P + j * K1;
+            // bin coefficients, as 16-byte vectors when K1 is even (base is then even)
+            auto load = [&](const GD_GLOBAL double* src, double (&x)[4]) {
+                if (vec) {
+                    const GD_GLOBAL double2* s2 = reinterpret_cast<const GD_GLOBAL double2*>(src + base);
+                    for (int i2 = 0; i2 < K1 / 2; ++i2) {
+                        const double2 d2 = s2[i2];
+                        x[2 * i2] = d2.x;
+                        x[2 * i2 + 1] = d2.y;
+                    }
+                } else {
+                    for (int i = 0; i < K1; ++i) x[i] = src[base + i];
+                }
+            };
             if (a.mode < 0) {
-                for (int i = 0; i < K1; ++i) v[i] = gs[base + i];
+                load(gs, v);
             } else {
-                double fac = kscale ? kscale[c] : 1.0;
-                if (Yf) fac = ldexp(fac, 2 * eslot[s]);
+                const double fac = sfac[sl];
                 auto row = [&](int o) -> double {
-                    if (Yf) return (double)Yf[(size_t)s * ystride + o] * rowscale[o] * fac;
-                    return Yd[(size_t)s * ystride + o] * fac;
+                    const int q = ypos[o];
+                    if (Yf) return (double)Yf[(size_t)s * ystride + q] * rowscale[q] * fac;
+                    return Yd[(size_t)s * ystride + q] * fac;
                 };
                 const double Fl = (j == 0) ? 0.0 : row(j - 1);
                 const double Fr = (j + 1 < N) ? row(j) : (conservative ? 0.0 : row(N - 1));
@@ -160,6 +191,9 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
                     if (j >= 1) rw[j - 1] = Fl;
                     if (j == N - 1 && !conservative) rw[N - 1] = Fr;
                 }
+                double xs[4] = {0.0, 0.0, 0.0, 0.0}, xn[4] = {0.0, 0.0, 0.0, 0.0};
+                if (a.mode >= 1) load(gs, xs);
+                if (a.mode >= 2) load(gn, xn);
                 for (int i = 0; i < K1; ++i) {
                     const double V = (i == 0) ? 0.0 : row(vbase + j * k + i - 1);
                     if (raw && i > 0) raw[(size_t)c * n_out + vbase + j * k + i - 1] = V;
@@ -167,9 +201,9 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
                     const double L = (2.0 * i + 1.0) / hj * (V - Fr + sgn * Fl);
                     switch (a.mode) {
                     case 0: v[i] = L; break;
-                    case 1: v[i] = gs[base + i] + a.dt * L; break;
-                    case 2: v[i] = 0.75 * gn[base + i] + 0.25 * (gs[base + i] + a.dt * L); break;
-                    default: v[i] = gn[base + i] / 3.0 + 2.0 / 3.0 * (gs[base + i] + a.dt * L); break;
+                    case 1: v[i] = xs[i] + a.dt * L; break;
+                    case 2: v[i] = 0.75 * xn[i] + 0.25 * (xs[i] + a.dt * L); break;
+                    default: v[i] = xn[i] / 3.0 + 2.0 / 3.0 * (xs[i] + a.dt * L); break;
                     }
                 }
             }
@@ -180,7 +214,12 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
             }
             if (a.mode >= 0 || a.limit) {
                 GD_GLOBAL double* o = (a.mode >= 0 || out) ? out : const_cast<GD_GLOBAL double*>(gs);
-                for (int i = 0; i < K1; ++i) o[base + i] = v[i];
+                if (vec) {
+                    GD_GLOBAL double2* o2 = reinterpret_cast<GD_GLOBAL double2*>(o + base);
+                    for (int i2 = 0; i2 < K1 / 2; ++i2) o2[i2] = make_double2(v[2 * i2], v[2 * i2 + 1]);
+                } else {
+                    for (int i = 0; i < K1; ++i) o[base + i] = v[i];
+                }
             }
         }
         if (a.split) {
@@ -237,7 +276,10 @@ __global__ __launch_bounds__(kStageMaxThreads) void k_stage(StageArgs a)
 int launch_stage(const StageArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return GD_OK;
-    hipLaunchKernelGGL(k_stage, dim3(a.n_tiles), dim3(256), 0, s, a);
+    if (a.max_p > kStageMaxP) return fail(GD_EUNSUPPORTED, "P too large for the stage kernel");
+    // LDS sized to the plan's largest P (more resident workgroups for small P)
+    if (a.max_p <= 96) hipLaunchKernelGGL(k_stage<96>, dim3(a.n_tiles), dim3(kStageThreads), 0, s, a);
+    else hipLaunchKernelGGL(k_stage<kStageMaxP>, dim3(a.n_tiles), dim3(kStageThreads), 0, s, a);
     HIP_TRY(hipGetLastError());
     return GD_OK;
 }

@@ -86,11 +86,9 @@ def lib():
             "gd_projection_points": ([_VP, _DP], ctypes.c_int),
             "gd_project": ([_VP, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
             "gd_plan_timing": ([_VP, ctypes.c_int], ctypes.c_int),
-            "gd_plan_set_variant": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
-            "gd_plan_variant": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                 ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int), _DP], ctypes.c_int),
-            "gd_plan_autotune": ([_VP, _VP, _VP, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int),
-                                  ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+            "gd_plan_set_variant": ([_VP, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+            "gd_plan_variant": ([_VP] + [ctypes.POINTER(ctypes.c_int)] * 5 + [_DP], ctypes.c_int),
+            "gd_plan_autotune": ([_VP, _VP, _VP, ctypes.c_char_p] + [ctypes.POINTER(ctypes.c_int)] * 4, ctypes.c_int),
             "gd_plan_use_graph": ([_VP, ctypes.c_int], ctypes.c_int),
             "gd_plan_bins": ([_VP, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_rk_forward": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP,
@@ -293,27 +291,28 @@ class Plan:
         _check(lib().gd_collision_vjp(self.h, _ptr(g), _ptr(kscale), _ptr(mu), _ptr(grad), _ptr(dks), _ptr(dvf)))
         return grad, dks, dvf
 
-    def set_variant(self, waves=4, rows=1, xcd=1):
-        """Contraction variant: waves per workgroup (4 or 8), row blocks per item (0 = all),
-        items grouped by XCD (1) or in one largest-first order (0)."""
-        _check(lib().gd_plan_set_variant(self.h, int(waves), int(rows), int(xcd)))
+    def set_variant(self, waves=4, rows=1, xcd=1, tiles_per_wave=1):
+        """Contraction variant: waves per workgroup (4 or 8), tiles per wave (1 or 2), row
+        blocks per item (0 = all), items grouped by XCD (1) or in one largest-first order (0)."""
+        _check(lib().gd_plan_set_variant(self.h, int(waves), int(tiles_per_wave), int(rows), int(xcd)))
 
     def variant(self):
-        w, r, x, n = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        w, t, r, x, n = (ctypes.c_int() for _ in range(5))
         f = ctypes.c_double()
-        _check(lib().gd_plan_variant(self.h, ctypes.byref(w), ctypes.byref(r), ctypes.byref(x), ctypes.byref(n),
-                                     ctypes.byref(f)))
-        return {"waves": w.value, "rows": r.value, "xcd": x.value, "n_items": n.value, "exec_flops": f.value}
+        _check(lib().gd_plan_variant(self.h, ctypes.byref(w), ctypes.byref(t), ctypes.byref(r), ctypes.byref(x),
+                                     ctypes.byref(n), ctypes.byref(f)))
+        return {"waves": w.value, "tiles_per_wave": t.value, "rows": r.value, "xcd": x.value, "n_items": n.value,
+                "exec_flops": f.value}
 
     def autotune(self, g, kscale=None, cache_path=None):
         """Time every contraction variant on state g and keep the fastest."""
         _dev64(g, self.n_values, "g")
         _dev64(kscale, self.n_cells, "kscale")
-        w, r, x = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        w, t, r, x = (ctypes.c_int() for _ in range(4))
         cp = cache_path.encode() if cache_path else None
-        _check(lib().gd_plan_autotune(self.h, _ptr(g), _ptr(kscale), cp, ctypes.byref(w), ctypes.byref(r),
-                                      ctypes.byref(x)))
-        return {"waves": w.value, "rows": r.value, "xcd": x.value}
+        _check(lib().gd_plan_autotune(self.h, _ptr(g), _ptr(kscale), cp, ctypes.byref(w), ctypes.byref(t),
+                                      ctypes.byref(r), ctypes.byref(x)))
+        return {"waves": w.value, "tiles_per_wave": t.value, "rows": r.value, "xcd": x.value}
 
     def use_graph(self, enable=True):
         _check(lib().gd_plan_use_graph(self.h, int(bool(enable))))

@@ -19,7 +19,9 @@ from paper_2607_13740_amd import gracedg as G  # noqa: E402
 from paper_2607_13740_amd import workloads as W  # noqa: E402
 
 DEV = "cuda:0"
-VARIANTS = [(4, 1, 1), (4, 2, 1), (4, 0, 1), (8, 1, 1), (8, 2, 1), (8, 0, 1), (4, 1, 0), (8, 2, 0)]
+# (waves, rows, xcd, tiles per wave)
+VARIANTS = [(4, 1, 1, 1), (4, 2, 1, 1), (4, 0, 1, 1), (8, 1, 1, 1), (8, 2, 1, 1), (8, 0, 1, 1), (4, 1, 0, 1),
+            (8, 2, 0, 1), (4, 1, 1, 2), (4, 0, 0, 2)]
 
 
 def _eps(Yg, Yo):
@@ -62,11 +64,14 @@ def test_variants_are_bit_identical(oracle, prec):
     gd = torch.tensor(g, device=DEV).view(-1)
     ksd = torch.tensor(ks, device=DEV)
     ref = None
-    for w, r, x in VARIANTS:
-        print(f"variant {prec} waves={w} rows={r} xcd={x}", flush=True)
-        plan.set_variant(w, r, x)
+    for w, r, x, tpw in VARIANTS:
+        if tpw == 2 and prec == "fp64":
+            continue
+        print(f"variant {prec} waves={w} rows={r} xcd={x} tiles/wave={tpw}", flush=True)
+        plan.set_variant(w, r, x, tpw)
         v = plan.variant()
-        assert v["waves"] == w and v["rows"] == r and v["xcd"] == x and v["n_items"] > 0
+        assert v["waves"] == w and v["rows"] == r and v["xcd"] == x and v["tiles_per_wave"] == tpw
+        assert v["n_items"] > 0
         raw = _raw(plan, gd, ksd)
         if ref is None:
             ref = raw.clone()
@@ -75,7 +80,7 @@ def test_variants_are_bit_identical(oracle, prec):
             tol = 1e-12 if prec == "fp64" else 1e-6
             assert _eps(raw.view(C, -1)[idx].cpu().numpy(), Yo).max() <= tol
         else:
-            assert torch.equal(raw, ref), (w, r, x)
+            assert torch.equal(raw, ref), (w, r, x, tpw)
 
 
 def _uneven(O, counts, kernel="additive"):
@@ -114,8 +119,10 @@ def test_uneven_batch_matches_oracle(oracle, prec):
         off += n * cfg.n_out
         assert _eps(Yg, Yo).max() <= tol, (cfg.N, cfg.k, _eps(Yg, Yo).max())
     assert off == raw.size
-    for w, r, x in VARIANTS[1:]:
-        plan.set_variant(w, r, x)
+    for w, r, x, tpw in VARIANTS[1:]:
+        if tpw == 2:
+            continue       # P up to 192 here: two tiles per wave serve P <= 96 only
+        plan.set_variant(w, r, x, tpw)
         assert np.array_equal(_raw(plan, torch.tensor(g, device=DEV)).cpu().numpy(), raw), (w, r, x)
 
 
@@ -159,7 +166,8 @@ def test_autotune_keeps_results_and_uses_cache(oracle, tmp_path):
     ref = _raw(plan, gd, ksd)
     cache = str(tmp_path / "tune.txt")
     choice = plan.autotune(gd, kscale=ksd, cache_path=cache)
-    assert (choice["waves"], choice["rows"]) in [(w, r) for w, r, _ in VARIANTS] and choice["xcd"] in (0, 1)
+    assert (choice["waves"], choice["rows"]) in [(w, r) for w, r, _, _ in VARIANTS] and choice["xcd"] in (0, 1)
+    assert choice["tiles_per_wave"] in (1, 2)
     assert torch.equal(_raw(plan, gd, ksd), ref)
     lines = open(cache).read().splitlines()
     assert len(lines) == 1 and lines[0].startswith("mixed;12x3r8c600")
@@ -168,7 +176,8 @@ def test_autotune_keeps_results_and_uses_cache(oracle, tmp_path):
     assert p2.autotune(gd, kscale=ksd, cache_path=cache) == choice
     assert open(cache).read().splitlines() == lines
     v = p2.variant()
-    assert (v["waves"], v["rows"], v["xcd"]) == (choice["waves"], choice["rows"], choice["xcd"])
+    assert (v["waves"], v["rows"], v["xcd"], v["tiles_per_wave"]) == (choice["waves"], choice["rows"], choice["xcd"],
+                                                                       choice["tiles_per_wave"])
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])

@@ -62,11 +62,12 @@ struct gd_tensor {
     const double* rowscale = nullptr;   // [NOB*32]
     Schedule mixed, f64;
     Schedule adj;              // FP64 transposed layout of the vector-Jacobian product
-    // Rows of the forward schedules are ordered bin by bin (F_j with V_{j,1..k}), so that
-    // a row block covers neighbouring masses and its nonzero (p, q) blocks are few:
-    // rowperm[position] = row o, ypos[o] = position of row o in the raw buffers.
+    // Rows of the forward schedules are ordered bin by bin (V_{0,1..k}, then F_j with
+    // V_{j,1..k} for j = 1..N-1, then F_N if non-conservative), so that a row block
+    // covers neighbouring masses and its nonzero (p, q) blocks are few: F_j sits at
+    // position j(k+1)-1 and V_{j,i} at j(k+1)+i-1 of the raw buffers (the stage kernel
+    // reads them there).  rowperm[position] = row o.
     std::vector<int> rowperm;
-    const int* ypos = nullptr;
     bool adj_packed = false;
     int KSO = 0;               // K steps of 16 output rows o (adjoint contraction)
     int NPS = 0;               // ranges of p per q block (adjoint contraction)
@@ -314,9 +315,6 @@ static int pack_tensor(gd_tensor* t)
             for (int i = 1; i <= k; ++i) t->rowperm.push_back(vbase + j * k + i - 1);
         }
         if (!t->spec.conservative) t->rowperm.push_back(N - 1);
-        std::vector<int> ypos(NO);
-        for (int q = 0; q < NO; ++q) ypos[t->rowperm[q]] = q;
-        if ((rc = upload(t->bufs, ypos, &t->ypos, &t->bytes))) return rc;
     }
 
     // ---------------- scaling of the split path.  U = Tf / (h_l h_m).
@@ -805,7 +803,6 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
         d.h = t->h;
         d.colscale = t->colscale;
         d.rowscale = t->rowscale;
-        d.ypos = t->ypos;
         d.perm = G.perm;
         d.theta = G.theta;
         d.mfrag = G.mfrag;

@@ -100,15 +100,14 @@ struct GroupDev {
     const float* scale;
     const double* h;           // [N] bin widths
     const double* colscale;    // [P]   split path column factors
-    const double* rowscale;    // [NOB*32] split path row factors (by position)
-    const int* ypos;           // [n_out] position of raw-vector row o in Y and rowscale
+    const double* rowscale;    // [NOB*32] split path row factors (by position in Y)
     const int* perm;           // [n_slots] slot -> cell of the group (-1: padding); nullptr: identity
     const double* theta;       // [n_slots] blend weight; nullptr: 0
     uint4* mfrag;              // split path B operands [tiles32][KS][hi|lo][64 lanes]
     float* mt;                 // split path stage-2 weights [tiles32][P][32]
     int* eslot;                // split path per-slot exponent [n_slots]
-    float* Yf;                 // split path raw vector [n_slots][ystride]
-    double* Yd;                // FP64 raw vector [n_slots][ystride]
+    float* Yf;                 // split path raw vector [n_slots][ystride], rows bin by bin
+    double* Yd;                // FP64 raw vector [n_slots][ystride], rows bin by bin
     long long val0;            // first state value of the group in the plan-wide arrays
     long long raw0;            // first raw-vector value of the group
     int cell0;                 // first cell of the group

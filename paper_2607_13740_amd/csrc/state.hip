@@ -123,7 +123,6 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
     const GD_CONST double* h = cptr(G->h);
     const GD_GLOBAL double* cs = gptr(G->colscale);
     const GD_CONST double* rowscale = cptr(G->rowscale);
-    const GD_CONST int* ypos = cptr(G->ypos);
     const GD_GLOBAL int* perm = gptr(G->perm);
     const GD_GLOBAL float* Yf = gptr(G->Yf);
     const GD_GLOBAL double* Yd = gptr(G->Yd);
@@ -177,13 +176,14 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                 load(gs, v);
             } else {
                 const double fac = sfac[sl];
-                auto row = [&](int o) -> double {
-                    const int q = ypos[o];
+                // raw rows are stored bin by bin: F_j at position j(k+1)-1, V_{j,i} at
+                // j(k+1)+i-1, F_{j+1} (and F_N of the non-conservative flux) at (j+1)(k+1)-1
+                auto pos = [&](int q) -> double {
                     if (Yf) return (double)Yf[(size_t)s * ystride + q] * rowscale[q] * fac;
                     return Yd[(size_t)s * ystride + q] * fac;
                 };
-                const double Fl = (j == 0) ? 0.0 : row(j - 1);
-                const double Fr = (j + 1 < N) ? row(j) : (conservative ? 0.0 : row(N - 1));
+                const double Fl = (j == 0) ? 0.0 : pos(j * K1 - 1);
+                const double Fr = (j + 1 < N || !conservative) ? pos((j + 1) * K1 - 1) : 0.0;
                 const int vbase = (N - 1) + (conservative ? 0 : 1);
                 const double hj = h[j];
                 if (raw) {
@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                 if (a.mode >= 1) load(gs, xs);
                 if (a.mode >= 2) load(gn, xn);
                 for (int i = 0; i < K1; ++i) {
-                    const double V = (i == 0) ? 0.0 : row(vbase + j * k + i - 1);
+                    const double V = (i == 0) ? 0.0 : pos(j * K1 + i - 1);
                     if (raw && i > 0) raw[(size_t)c * n_out + vbase + j * k + i - 1] = V;
                     const double sgn = (i & 1) ? -1.0 : 1.0;
                     const double L = (2.0 * i + 1.0) / hj * (V - Fr + sgn * Fl);
@@ -249,15 +249,21 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
         if (s < n_slots) eslot[s] = e;
     }
     __syncthreads();
+    // each lane splits 8 consecutive coefficients of one slot: hi/lo halves into the
+    // B-operand fragment, the FP32 value into the weights [tile][q][32 slots]
     const int KS = G->KS;
     GD_GLOBAL uint4* mfrag = gptr(G->mfrag);
+    GD_GLOBAL float* mt = gptr(G->mt) + (size_t)tile * P * 32;
     for (int t = tid; t < KS * 64; t += nthr) {
         const int ks = t >> 6, lane = t & 63, sl = lane & 31, hh = lane >> 5;
         half8_t hi, lo;
         for (int jj = 0; jj < 8; ++jj) {
             const int q = ks * 16 + hh * 8 + jj;
             float m = 0.0f;
-            if (q < P) m = (float)ldexp(st[sl * LD + q], -smax[sl]);
+            if (q < P) {
+                m = (float)ldexp(st[sl * LD + q], -smax[sl]);
+                mt[(size_t)q * 32 + sl] = m;
+            }
             const _Float16 mh = (_Float16)m;
             hi[jj] = mh;
             lo[jj] = (_Float16)(m - (float)mh);
@@ -265,11 +271,6 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
         const size_t base = ((size_t)(tile * KS + ks) * 2) * 64 + lane;
         mfrag[base] = __builtin_bit_cast(uint4, hi);
         mfrag[base + 64] = __builtin_bit_cast(uint4, lo);
-    }
-    GD_GLOBAL float* mt = gptr(G->mt);
-    for (int t = tid; t < P * 32; t += nthr) {
-        const int q = t >> 5, sl = t & 31;
-        mt[((size_t)tile * P + q) * 32 + sl] = (float)ldexp(st[sl * LD + q], -smax[sl]);
     }
 }
 

@@ -120,9 +120,9 @@ static inline int pow2_exp(double v)
 constexpr long long kIterCost = 2;   // cost of an iteration in fragment units (item ordering)
 
 template <class Emit, class BlockScale>
-static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterDesc>& iters, std::vector<int>& off,
-                           std::vector<int>& cnt, std::vector<long long>& cost, std::vector<long long>& frags, Emit emit,
-                           BlockScale blockscale)
+static void build_schedule(const gd_tensor* t, int RB, int KW, bool sort_by_lo, std::vector<IterDesc>& iters,
+                           std::vector<int>& off, std::vector<int>& cnt, std::vector<long long>& cost,
+                           std::vector<long long>& frags, Emit emit, BlockScale blockscale)
 {
     const int P = t->P, NO = t->n_out, R = t->R;
     const int NOBx = cdiv(NO, RB), KSx = cdiv(P, KW);
@@ -156,6 +156,10 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, std::vector<IterD
                         }
                         if (lo >= 0) segs.push_back({p, lo});
                     }
+                // split path: segments sorted by chain start, so that consecutive segments
+                // run the same chain code (fewer instruction-cache misses)
+                if (sort_by_lo)
+                    std::stable_sort(segs.begin(), segs.end(), [](const Seg& x, const Seg& y) { return x.lo < y.lo; });
                 size_t s0 = 0;
                 while (s0 < segs.size()) {
                     IterDesc d{};
@@ -381,7 +385,7 @@ static int pack_tensor(gd_tensor* t)
                     frag[f * 1024 + 512 + l * 8 + j] = bl;
                 }
         };
-        build_schedule(t, 32, 16, iters, off, cnt, t->mixed.list_cost, t->mixed.list_frags, emit, blockscale);
+        build_schedule(t, 32, 16, true, iters, off, cnt, t->mixed.list_cost, t->mixed.list_frags, emit, blockscale);
         t->mixed.NOB = t->NOB;
         const uint16_t* dfrag = nullptr;
         if ((rc = upload(t->bufs, frag, &dfrag, &t->bytes))) return rc;
@@ -409,7 +413,7 @@ static int pack_tensor(gd_tensor* t)
                     if (o < NO && q < P && q >= p) frag[f * 256 + j * 64 + l] = part(t, r, delta, t->rowperm[o], p, q);
                 }
         };
-        build_schedule(t, 16, 16, iters, off, cnt, t->f64.list_cost, t->f64.list_frags, emit, blockscale);
+        build_schedule(t, 16, 16, false, iters, off, cnt, t->f64.list_cost, t->f64.list_frags, emit, blockscale);
         t->f64.NOB = t->NOB16;
         const double* dfrag = nullptr;
         if ((rc = upload(t->bufs, frag, &dfrag, &t->bytes))) return rc;

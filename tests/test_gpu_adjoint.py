@@ -158,3 +158,35 @@ def test_autograd_function(oracle):
     lam = w.clone()
     dks, dvf = plan.adjoint(st, gm, 2e-6, 2, lam, kscale=_dev(ks))
     assert torch.equal(gg, lam) and torch.equal(gk, dks) and torch.equal(gv, dvf)
+
+
+def test_adjoint_of_uneven_batch_matches_single_groups(oracle):
+    """Two groups of different shape (one with threshold levels, one without) in one
+    plan: the reverse pass over the batch equals the reverse passes of the groups run
+    alone."""
+    O = oracle
+    t1, cfg1, g1, ks1, vf1, rng = _case(O, N=8, k=2, C=9, seed=13)
+    t2, cfg2, g2, ks2, _, _ = _case(O, N=6, k=1, C=5, seed=14, levels=(0.5,))
+    dt, n = 5e-6, 2
+    w1 = rng.standard_normal(g1.shape)
+    w2 = rng.standard_normal(g2.shape)
+    both = G.Plan([t1, t2], [9, 5], precision="fp64", vfrag=np.concatenate([vf1, np.full(5, 0.5)]))
+    g = _dev(np.concatenate([g1.reshape(-1), g2.reshape(-1)]))
+    ks = _dev(np.concatenate([ks1, ks2]))
+    st, gm = both.rk_forward(g, dt, n, kscale=ks)
+    lam = _dev(np.concatenate([w1.reshape(-1), w2.reshape(-1)]))
+    dks, dvf = both.adjoint(st, gm, dt, n, lam, kscale=ks)
+    outs = []
+    for t, gg, kk, vv, ww in ((t1, g1, ks1, vf1, w1), (t2, g2, ks2, None, w2)):
+        p = G.Plan(t, len(gg), precision="fp64", vfrag=vv)
+        s1, m1 = p.rk_forward(_dev(gg).view(-1), dt, n, kscale=_dev(kk))
+        l1 = _dev(ww).view(-1).clone()
+        d1, v1 = p.adjoint(s1, m1, dt, n, l1, kscale=_dev(kk))
+        outs.append((l1, d1, v1))
+    n1 = g1.size
+    assert torch.allclose(lam[:n1], outs[0][0], rtol=1e-13, atol=0)
+    assert torch.allclose(lam[n1:], outs[1][0], rtol=1e-13, atol=0)
+    assert torch.allclose(dks[:9], outs[0][1], rtol=1e-12, atol=1e-300)
+    assert torch.allclose(dks[9:], outs[1][1], rtol=1e-12, atol=1e-300)
+    assert torch.allclose(dvf[:9], outs[0][2], rtol=1e-12, atol=1e-300)
+    assert float(dvf[9:].abs().max()) == 0.0      # single-level group: no threshold dependence

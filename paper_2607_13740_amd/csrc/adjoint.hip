@@ -224,39 +224,21 @@ __device__ double poly_argmin(int k, const double* c)
     return xb;
 }
 
-__device__ __forceinline__ int find_group_bins(const GD_CONST GroupDev* groups, int n_groups, long long b)
-{
-    int gi = 0;
-    while (gi + 1 < n_groups && b >= groups[gi + 1].gam0) ++gi;
-    return gi;
-}
-
-// lam <- J_limiter^T lam for every bin, from the limited state y and the factor
-// gamma the forward limiter applied (y_i = gamma z_i for i >= 1, y_0 = z_0):
+// Cotangent through the limiter of one bin (k >= 1), from the limited state y and the
+// factor gamma the forward limiter applied (y_i = gamma z_i for i >= 1, y_0 = z_0):
 //   gamma = 1: identity;  gamma = 0 (flattened bin): the higher coefficients get 0;
 //   else, with q = sum_{i>=1} z_i P_i(x*) at the minimiser x* (so gamma = -z_0/q and,
 //   by the envelope theorem, dq/dz_i = P_i(x*)) and S = sum_{i>=1} lam_i z_i:
 //   mu_0 = lam_0 - S/q,   mu_j = gamma lam_j + S z_0 P_j(x*) / q^2.
 // Both are evaluated on u = z / z_0 (scale free: q/z_0 = sum u_i P_i(x*) <= -1), so
-// that bins holding 1e-250 of the mass do not underflow q^2.
-__global__ __launch_bounds__(256) void k_adj_limit(AdjStageArgs a)
+// that bins holding 1e-250 of the mass do not underflow q^2.  lam is updated in place.
+__device__ __forceinline__ void limiter_vjp(int k, double gam, const GD_GLOBAL double* y, double* lam)
 {
-    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.n_bins) return;
-    const GD_CONST GroupDev* groups = cptr(a.groups);
-    const GD_CONST GroupDev* G = groups + find_group_bins(groups, a.n_groups, b);
-    const int N = G->N, k = G->k, K1 = k + 1, P = G->P;
-    const long long lb = b - G->gam0;
-    const int c = (int)(lb / N), j = (int)(lb - (long long)c * N);
-    const size_t base = G->val0 + (size_t)c * P + j * K1;
-    const double gam = a.gamma[b];
-    GD_GLOBAL double* lam = gptr(a.lam) + base;
-    if (gam == 1.0 || k == 0) return;
+    if (gam == 1.0) return;
     if (gam == 0.0) {
         for (int i = 1; i <= k; ++i) lam[i] = 0.0;
         return;
     }
-    const GD_GLOBAL double* y = gptr(a.y) + base;
     double u[4] = {1.0, 0.0, 0.0, 0.0};
     for (int i = 1; i <= k; ++i) u[i] = (y[i] / gam) / y[0];
     const double xs = poly_argmin(k, u);
@@ -271,29 +253,79 @@ __global__ __launch_bounds__(256) void k_adj_limit(AdjStageArgs a)
     lam[0] = l0;
 }
 
-// From mu (the cotangent of a stage's pre-limiter value z = a g_n + b (y + dt L(y))):
-//   acc (=|+=) a mu, prev (=|+=) b mu, and nu = A^T (b dt mu) in slot order, where A is
-// the assembly of Eq. evo: L_{j,i} = (2i+1)/h_j (V_{j,i} - F_{j+1} + (-1)^i F_j).
-// One workgroup per tile of 32 slots, one thread per (slot, bin).
-__global__ __launch_bounds__(kAdjThreads) void k_adj_nu(AdjStageArgs a)
+// lam <- J_limiter^T lam for every bin (used for the limiter applied to the caller's
+// state before the first step).  One thread per bin.
+__global__ __launch_bounds__(256) void k_adj_limit(AdjStageArgs a)
 {
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.n_bins) return;
     const GD_CONST GroupDev* groups = cptr(a.groups);
     int gi = 0;
-    while (gi + 1 < a.n_groups && (int)blockIdx.x >= groups[gi + 1].tile_off) ++gi;
+    while (gi + 1 < a.n_groups && b >= groups[gi + 1].gam0) ++gi;
     const GD_CONST GroupDev* G = groups + gi;
-    const int tile = (int)blockIdx.x - G->tile_off;
+    const int N = G->N, k = G->k, K1 = k + 1;
+    if (k == 0) return;
+    const double gam = gptr(a.gamma)[b];
+    if (gam == 1.0) return;
+    const long long lb = b - G->gam0;
+    const size_t off = (size_t)G->val0 + (size_t)(lb / N) * G->P + (size_t)(lb % N) * K1;
+    GD_GLOBAL double* lam = gptr(a.lam) + off;
+    double l[4];
+    for (int i = 0; i < K1; ++i) l[i] = lam[i];
+    limiter_vjp(k, gam, gptr(a.y) + off, l);
+    for (int i = 0; i < K1; ++i) lam[i] = l[i];
+}
+
+// From the cotangent lam of a stage's output g' = Lim(z), z = a g_n + b (y + dt L(y)):
+//   mu = J_limiter^T lam (when the limiter factors are given), acc (=|+=) a mu,
+//   prev (=|+=) b mu, and nu = A^T (b dt mu) in slot order, where A is the assembly of
+// Eq. evo: L_{j,i} = (2i+1)/h_j (V_{j,i} - F_{j+1} + (-1)^i F_j).
+// One workgroup per kAdjSlots slots (a quarter of a 32-slot tile); mu of these slots
+// is staged in LDS, one thread per (slot, bin) in both phases.
+template <int PMAX>
+__global__ __launch_bounds__(kAdjThreads) void k_adj_nu(AdjStageArgs a)
+{
+    constexpr int SUB = 32 / kAdjSlots;
+    __shared__ double smu[kAdjSlots * PMAX];
+    const GD_CONST GroupDev* groups = cptr(a.groups);
+    const int tile_all = (int)blockIdx.x / SUB, s0 = ((int)blockIdx.x % SUB) * kAdjSlots;
+    int gi = 0;
+    while (gi + 1 < a.n_groups && tile_all >= groups[gi + 1].tile_off) ++gi;
+    const GD_CONST GroupDev* G = groups + gi;
+    const int tile = tile_all - G->tile_off;
     const int N = G->N, k = G->k, K1 = k + 1, P = G->P, n_out = G->n_out, nus = G->KSO * 16;
     const bool conservative = G->conservative != 0;
     const GD_CONST double* h = cptr(G->h);
     const GD_GLOBAL int* perm = gptr(G->perm);
     const GD_GLOBAL double* mu = gptr(a.mu) + G->val0;
+    const GD_GLOBAL double* gamma = a.gamma ? gptr(a.gamma) + G->gam0 : nullptr;
+    const GD_GLOBAL double* ylim = a.ylim ? gptr(a.ylim) + G->val0 : nullptr;
     GD_GLOBAL double* acc = a.acc ? gptr(a.acc) + G->val0 : nullptr;
     GD_GLOBAL double* prev = gptr(a.prev) + G->val0;
     GD_GLOBAL double* nu = gptr(G->nu);
-    const int vbase = (N - 1) + (conservative ? 0 : 1);
-    for (int t = threadIdx.x; t < 32 * N; t += blockDim.x) {
+    // phase 1: mu of every bin of the slots (through the limiter), acc and prev
+    for (int t = threadIdx.x; t < kAdjSlots * N; t += blockDim.x) {
         const int sl = t / N, j = t - sl * N;
-        const int s = tile * 32 + sl;
+        const int s = tile * 32 + s0 + sl;
+        if (s >= G->n_slots) continue;
+        const int c = perm ? perm[s] : s;
+        if (c < 0) continue;
+        const size_t base = (size_t)c * P + j * K1;
+        double m[4];
+        for (int i = 0; i < K1; ++i) m[i] = mu[base + i];
+        if (gamma && k > 0) limiter_vjp(k, gamma[(size_t)c * N + j], ylim + base, m);
+        for (int i = 0; i < K1; ++i) {
+            smu[sl * P + j * K1 + i] = m[i];
+            if (acc) acc[base + i] = a.acc_add ? acc[base + i] + a.a * m[i] : a.a * m[i];
+            prev[base + i] = a.prev_add ? prev[base + i] + a.b * m[i] : a.b * m[i];
+        }
+    }
+    __syncthreads();
+    // phase 2: nu
+    const int vbase = (N - 1) + (conservative ? 0 : 1);
+    for (int t = threadIdx.x; t < kAdjSlots * N; t += blockDim.x) {
+        const int sl = t / N, j = t - sl * N;
+        const int s = tile * 32 + s0 + sl;
         if (s >= G->n_slots) continue;
         const int c = perm ? perm[s] : s;
         GD_GLOBAL double* nrow = nu + (size_t)s * nus;
@@ -301,26 +333,19 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_nu(AdjStageArgs a)
             for (int o = j; o < nus; o += N) nrow[o] = 0.0;
             continue;
         }
-        const size_t base = (size_t)c * P + j * K1;
-        double rho[4], rhol[4];
-        for (int i = 0; i < K1; ++i) {
-            const double m = mu[base + i];
-            rho[i] = a.bdt * m;
-            if (acc) acc[base + i] = a.acc_add ? acc[base + i] + a.a * m : a.a * m;
-            prev[base + i] = a.prev_add ? prev[base + i] + a.b * m : a.b * m;
-        }
+        const double* m = smu + sl * P + j * K1;
+        double rho[4];
+        for (int i = 0; i < K1; ++i) rho[i] = a.bdt * m[i];
         const double hj = h[j];
         // V_{j,i}
         for (int i = 1; i < K1; ++i) nrow[vbase + j * k + i - 1] = rho[i] * (2.0 * i + 1.0) / hj;
         // F_j (interior interface j >= 1): from bin j (as F_j) and bin j-1 (as F_{j+1})
         if (j >= 1) {
             const double hl = h[j - 1];
-            const size_t bl = (size_t)c * P + (j - 1) * K1;
+            const double* ml = m - K1;
             double v = 0.0;
-            for (int i = 0; i < K1; ++i) {
-                rhol[i] = a.bdt * mu[bl + i];
-                v += ((i & 1) ? -1.0 : 1.0) * rho[i] * (2.0 * i + 1.0) / hj - rhol[i] * (2.0 * i + 1.0) / hl;
-            }
+            for (int i = 0; i < K1; ++i)
+                v += ((i & 1) ? -1.0 : 1.0) * rho[i] * (2.0 * i + 1.0) / hj - a.bdt * ml[i] * (2.0 * i + 1.0) / hl;
             nrow[j - 1] = v;
         }
         if (j == N - 1 && !conservative) {
@@ -335,14 +360,17 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_nu(AdjStageArgs a)
 
 // prev += s G with G_p = G2_p + sum over q blocks of the first-sum partials (both
 // parts); dkscale += (1/2) y . G; dvfrag += s (sum of the blend partials) dtheta/dv.
+// One workgroup per kAdjSlots slots, one thread per (slot, coefficient).
 __global__ __launch_bounds__(kAdjThreads) void k_adj_combine(AdjStageArgs a)
 {
-    __shared__ double red[32];
+    constexpr int SUB = 32 / kAdjSlots;
+    __shared__ double red[kAdjSlots];
     const GD_CONST GroupDev* groups = cptr(a.groups);
+    const int tile_all = (int)blockIdx.x / SUB, s0 = ((int)blockIdx.x % SUB) * kAdjSlots;
     int gi = 0;
-    while (gi + 1 < a.n_groups && (int)blockIdx.x >= groups[gi + 1].tile_off) ++gi;
+    while (gi + 1 < a.n_groups && tile_all >= groups[gi + 1].tile_off) ++gi;
     const GD_CONST GroupDev* G = groups + gi;
-    const int tile = (int)blockIdx.x - G->tile_off;
+    const int tile = tile_all - G->tile_off;
     const int P = G->P, NQB = G->NQB, NPS = G->NPS, n_slots = G->n_slots;
     const bool blend = G->R > 1;
     const GD_GLOBAL int* perm = gptr(G->perm);
@@ -350,11 +378,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_combine(AdjStageArgs a)
     GD_GLOBAL double* prev = gptr(a.prev) + G->val0;
     const GD_GLOBAL double* G2 = gptr(G->G2);
     const GD_GLOBAL double* G1p = gptr(G->G1p);
-    if (threadIdx.x < 32) red[threadIdx.x] = 0.0;
+    if (threadIdx.x < kAdjSlots) red[threadIdx.x] = 0.0;
     __syncthreads();
-    for (int t = threadIdx.x; t < 32 * P; t += blockDim.x) {
+    for (int t = threadIdx.x; t < kAdjSlots * P; t += blockDim.x) {
         const int sl = t / P, p = t - sl * P;
-        const int s = tile * 32 + sl;
+        const int s = tile * 32 + s0 + sl;
         if (s >= n_slots) continue;
         const int c = perm ? perm[s] : s;
         if (c < 0) continue;
@@ -371,8 +399,8 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_combine(AdjStageArgs a)
         atomicAdd(&red[sl], 0.5 * y[(size_t)c * P + p] * g);
     }
     __syncthreads();
-    if (threadIdx.x < 32) {
-        const int s = tile * 32 + threadIdx.x;
+    if (threadIdx.x < kAdjSlots) {
+        const int s = tile * 32 + s0 + threadIdx.x;
         if (s < n_slots) {
             const int c = perm ? perm[s] : s;
             if (c >= 0) {
@@ -402,7 +430,12 @@ int launch_adj_limit(const AdjStageArgs& a, hipStream_t s)
 int launch_adj_nu(const AdjStageArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return GD_OK;
-    hipLaunchKernelGGL(k_adj_nu, dim3(a.n_tiles), dim3(kAdjThreads), 0, s, a);
+    if (a.max_p <= 96)
+        hipLaunchKernelGGL(k_adj_nu<96>, dim3(a.n_tiles * (32 / kAdjSlots)), dim3(kAdjThreads), 0, s, a);
+    else if (a.max_p <= 192)
+        hipLaunchKernelGGL(k_adj_nu<192>, dim3(a.n_tiles * (32 / kAdjSlots)), dim3(kAdjThreads), 0, s, a);
+    else
+        return fail(GD_EUNSUPPORTED, "P too large for the reverse stage kernel");
     HIP_TRY(hipGetLastError());
     return GD_OK;
 }
@@ -410,7 +443,7 @@ int launch_adj_nu(const AdjStageArgs& a, hipStream_t s)
 int launch_adj_combine(const AdjStageArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return GD_OK;
-    hipLaunchKernelGGL(k_adj_combine, dim3(a.n_tiles), dim3(kAdjThreads), 0, s, a);
+    hipLaunchKernelGGL(k_adj_combine, dim3(a.n_tiles * (32 / kAdjSlots)), dim3(kAdjThreads), 0, s, a);
     HIP_TRY(hipGetLastError());
     return GD_OK;
 }

@@ -1122,16 +1122,21 @@ static AdjStageArgs adj_args(const gd_plan* pl)
     a.n_groups = int(pl->groups.size());
     a.n_tiles = pl->tiles32;
     a.n_bins = pl->n_bins;
+    a.max_p = pl->max_p;
     return a;
 }
 
-// cotangent of a stage's pre-limiter value -> contributions to the cotangents of g_n
-// (acc) and of the stage input y (prev), through L at y
-static int adj_stage(gd_plan* pl, hipStream_t s, const double* kscale, double* mu, double* acc, int acc_add, double a,
-                     double* prev, int prev_add, double b, double bdt, const double* y, double* dks, double* dvf)
+// cotangent of a stage's output (through its limiter, when the limited state ylim and
+// the factors gamma are given) -> contributions to the cotangents of g_n (acc) and
+// of the stage input y (prev), through L at y
+static int adj_stage(gd_plan* pl, hipStream_t s, const double* kscale, const double* ylim, const double* gamma,
+                     double* mu, double* acc, int acc_add, double a, double* prev, int prev_add, double b, double bdt,
+                     const double* y, double* dks, double* dvf)
 {
     int rc;
     AdjStageArgs A = adj_args(pl);
+    A.ylim = ylim;
+    A.gamma = gamma;
     A.mu = mu;
     A.acc = acc;
     A.acc_add = acc_add;
@@ -1185,14 +1190,17 @@ extern "C" int gd_adjoint(gd_plan* pl, const double* states, const double* gamma
         double* Acc = buf[(cur + 1) % 3];
         double* Y = buf[(cur + 2) % 3];
         // stage 3: g1 = Lim(1/3 gn + 2/3 (y2 + dt L(y2)))
-        if ((rc = adj_limit(pl, s, X, g1, Gm(3ll * n + 3)))) return rc;
-        if ((rc = adj_stage(pl, s, kscale, X, Acc, 0, 1.0 / 3.0, Y, 0, 2.0 / 3.0, 2.0 / 3.0 * dt, y2, dkscale, dvfrag))) return rc;
+        if ((rc = adj_stage(pl, s, kscale, g1, Gm(3ll * n + 3), X, Acc, 0, 1.0 / 3.0, Y, 0, 2.0 / 3.0, 2.0 / 3.0 * dt,
+                            y2, dkscale, dvfrag)))
+            return rc;
         // stage 2: y2 = Lim(3/4 gn + 1/4 (y1 + dt L(y1))); the cotangent of y2 is in Y
-        if ((rc = adj_limit(pl, s, Y, y2, Gm(3ll * n + 2)))) return rc;
-        if ((rc = adj_stage(pl, s, kscale, Y, Acc, 1, 0.75, X, 0, 0.25, 0.25 * dt, y1, dkscale, dvfrag))) return rc;
+        if ((rc = adj_stage(pl, s, kscale, y2, Gm(3ll * n + 2), Y, Acc, 1, 0.75, X, 0, 0.25, 0.25 * dt, y1, dkscale,
+                            dvfrag)))
+            return rc;
         // stage 1: y1 = Lim(gn + dt L(gn)); the cotangent of y1 is in X, that of gn gathers in Acc
-        if ((rc = adj_limit(pl, s, X, y1, Gm(3ll * n + 1)))) return rc;
-        if ((rc = adj_stage(pl, s, kscale, X, nullptr, 0, 0.0, Acc, 1, 1.0, dt, gn, dkscale, dvfrag))) return rc;
+        if ((rc = adj_stage(pl, s, kscale, y1, Gm(3ll * n + 1), X, nullptr, 0, 0.0, Acc, 1, 1.0, dt, gn, dkscale,
+                            dvfrag)))
+            return rc;
         cur = (cur + 1) % 3;
     }
     // the limiter applied to the caller's state before the first step
@@ -1211,7 +1219,8 @@ extern "C" int gd_collision_vjp(gd_plan* pl, const double* g, const double* ksca
     if ((rc = prepare_adjoint(pl))) return rc;
     if (dkscale && (rc = launch_fill_f64(dkscale, pl->n_cells, 0.0, pl->stream))) return rc;
     if (dvfrag && (rc = launch_fill_f64(dvfrag, pl->n_cells, 0.0, pl->stream))) return rc;
-    return adj_stage(pl, pl->stream, kscale, mu, nullptr, 0, 0.0, grad, 1, 0.0, 1.0, g, dkscale, dvfrag);
+    return adj_stage(pl, pl->stream, kscale, nullptr, nullptr, mu, nullptr, 0, 0.0, grad, 1, 0.0, 1.0, g, dkscale,
+                     dvfrag);
 }
 
 // ---------------------------------------------------------------------------- autotuner

@@ -166,7 +166,8 @@ struct StageArgs {
 };
 
 // Kernels of the reverse step (see adjoint.hip).
-constexpr int kAdjThreads = 1024;
+constexpr int kAdjThreads = 256;
+constexpr int kAdjSlots = 8;   // slots per workgroup of the per-slot reverse kernels (4 per tile)
 constexpr int kAdjPs = 32;     // values of p per list of the vector-Jacobian product
 constexpr int kAdjWaves = 4;   // waves per workgroup of the vector-Jacobian product
 struct AdjStageArgs {
@@ -174,10 +175,12 @@ struct AdjStageArgs {
     int n_groups;
     int n_tiles;               // 32-slot tiles over all groups
     long long n_bins;          // bins over all groups
-    const double* gamma;       // k_adj_limit: limiter factors of the stage
+    int max_p;                 // largest P over the groups (sets the LDS size of k_adj_nu)
+    const double* gamma;       // limiter factors of the stage (k_adj_nu: nullptr = no limiter)
     const double* y;           // k_adj_limit: limited state; k_adj_combine: linearisation state
+    const double* ylim;        // k_adj_nu: limited state of the stage (with gamma)
     double* lam;               // k_adj_limit: cotangent, in place
-    const double* mu;          // k_adj_nu: cotangent of the stage's pre-limiter value
+    const double* mu;          // k_adj_nu: cotangent of the stage's output (before the limiter VJP)
     double* acc;               // k_adj_nu: acc (=|+=) a mu (or nullptr)
     int acc_add;
     double a;

@@ -253,40 +253,24 @@ __device__ __forceinline__ void limiter_vjp(int k, double gam, const GD_GLOBAL d
     lam[0] = l0;
 }
 
-// lam <- J_limiter^T lam for every bin (used for the limiter applied to the caller's
-// state before the first step).  One thread per bin.
-__global__ __launch_bounds__(256) void k_adj_limit(AdjStageArgs a)
-{
-    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.n_bins) return;
-    const GD_CONST GroupDev* groups = cptr(a.groups);
-    int gi = 0;
-    while (gi + 1 < a.n_groups && b >= groups[gi + 1].gam0) ++gi;
-    const GD_CONST GroupDev* G = groups + gi;
-    const int N = G->N, k = G->k, K1 = k + 1;
-    if (k == 0) return;
-    const double gam = gptr(a.gamma)[b];
-    if (gam == 1.0) return;
-    const long long lb = b - G->gam0;
-    const size_t off = (size_t)G->val0 + (size_t)(lb / N) * G->P + (size_t)(lb % N) * K1;
-    GD_GLOBAL double* lam = gptr(a.lam) + off;
-    double l[4];
-    for (int i = 0; i < K1; ++i) l[i] = lam[i];
-    limiter_vjp(k, gam, gptr(a.y) + off, l);
-    for (int i = 0; i < K1; ++i) lam[i] = l[i];
-}
-
-// From the cotangent lam of a stage's output g' = Lim(z), z = a g_n + b (y + dt L(y)):
-//   mu = J_limiter^T lam (when the limiter factors are given), acc (=|+=) a mu,
-//   prev (=|+=) b mu, and nu = A^T (b dt mu) in slot order, where A is the assembly of
-// Eq. evo: L_{j,i} = (2i+1)/h_j (V_{j,i} - F_{j+1} + (-1)^i F_j).
-// One workgroup per kAdjSlots slots (a quarter of a 32-slot tile); mu of these slots
-// is staged in LDS, one thread per (slot, bin) in both phases.
+// The per-slot work between two vector-Jacobian contractions of the reverse step, in
+// one kernel per RK stage boundary (see AdjStageArgs):
+//  C. (combine) lam = mu + s G, G_p = G2_p + the first-sum partials of every q block
+//     (both parts) of the previous contraction, linearised at ylin; dkscale +=
+//     (1/2) ylin . G; dvfrag += s (sum of the blend partials) dtheta/dv.  Without
+//     combine, lam = mu.
+//  1. lam <- J_limiter^T lam per bin (when the limiter factors are given); with out,
+//     lam is the result and goes there; else acc (=|+=) a lam, prev (=|+=) b lam and
+//  2. nu = A^T (b dt lam) in slot order, where A is the assembly of Eq. evo:
+//     L_{j,i} = (2i+1)/h_j (V_{j,i} - F_{j+1} + (-1)^i F_j).
+// One workgroup per kAdjSlots slots (a quarter of a 32-slot tile); lam of these slots
+// is staged in LDS between the phases.
 template <int PMAX>
-__global__ __launch_bounds__(kAdjThreads) void k_adj_nu(AdjStageArgs a)
+__global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
 {
     constexpr int SUB = 32 / kAdjSlots;
-    __shared__ double smu[kAdjSlots * PMAX];
+    __shared__ double sl_lam[kAdjSlots * PMAX];
+    __shared__ double red[kAdjSlots];
     const GD_CONST GroupDev* groups = cptr(a.groups);
     const int tile_all = (int)blockIdx.x / SUB, s0 = ((int)blockIdx.x % SUB) * kAdjSlots;
     int gi = 0;
@@ -294,46 +278,107 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_nu(AdjStageArgs a)
     const GD_CONST GroupDev* G = groups + gi;
     const int tile = tile_all - G->tile_off;
     const int N = G->N, k = G->k, K1 = k + 1, P = G->P, n_out = G->n_out, nus = G->KSO * 16;
-    const bool conservative = G->conservative != 0;
+    const int NQB = G->NQB, n_slots = G->n_slots;
+    const bool conservative = G->conservative != 0, blend = G->R > 1;
     const GD_CONST double* h = cptr(G->h);
     const GD_GLOBAL int* perm = gptr(G->perm);
     const GD_GLOBAL double* mu = gptr(a.mu) + G->val0;
     const GD_GLOBAL double* gamma = a.gamma ? gptr(a.gamma) + G->gam0 : nullptr;
     const GD_GLOBAL double* ylim = a.ylim ? gptr(a.ylim) + G->val0 : nullptr;
+    const GD_GLOBAL double* ylin = a.ylin ? gptr(a.ylin) + G->val0 : nullptr;
+    const GD_GLOBAL double* kscale = a.kscale ? gptr(a.kscale) + G->cell0 : nullptr;
+    GD_GLOBAL double* out = a.out ? gptr(a.out) + G->val0 : nullptr;
     GD_GLOBAL double* acc = a.acc ? gptr(a.acc) + G->val0 : nullptr;
-    GD_GLOBAL double* prev = gptr(a.prev) + G->val0;
-    GD_GLOBAL double* nu = gptr(G->nu);
-    // phase 1: mu of every bin of the slots (through the limiter), acc and prev
+    GD_GLOBAL double* prev = a.prev ? gptr(a.prev) + G->val0 : nullptr;
+
+    // ---- phase C: one thread per (slot, coefficient)
+    if (threadIdx.x < kAdjSlots) red[threadIdx.x] = 0.0;
+    if (a.combine) __syncthreads();
+    const GD_GLOBAL double* G2 = gptr(G->G2);
+    const GD_GLOBAL double* G1p = gptr(G->G1p);
+    for (int t = threadIdx.x; t < kAdjSlots * P; t += blockDim.x) {
+        const int sl = t / P, p = t - sl * P;
+        const int s = tile * 32 + s0 + sl;
+        if (s >= n_slots) continue;
+        const int c = perm ? perm[s] : s;
+        if (c < 0) continue;
+        double v = mu[(size_t)c * P + p];
+        if (a.combine) {
+            // second-sum partials: the p ranges present in the block of q = p
+            const int qbp = p / 16, npr = cdiv_dev(min(P, qbp * 16 + 16), kAdjPs);
+            double g = 0.0;
+            for (int ps = 0; ps < npr; ++ps) g += G2[((size_t)ps * n_slots + s) * P + p];
+            for (int qb = p / 16; qb < NQB; ++qb) {
+                g += G1p[((size_t)qb * n_slots + s) * P + p];
+                if (blend) g += G1p[(((size_t)NQB + qb) * n_slots + s) * P + p];
+            }
+            const double sc = kscale ? kscale[c] : 1.0;
+            v += sc * g;
+            atomicAdd(&red[sl], 0.5 * ylin[(size_t)c * P + p] * g);
+        }
+        sl_lam[sl * P + p] = v;
+    }
+    __syncthreads();
+    if (a.combine && threadIdx.x < kAdjSlots) {
+        const int s = tile * 32 + s0 + threadIdx.x;
+        if (s < n_slots) {
+            const int c = perm ? perm[s] : s;
+            if (c >= 0) {
+                if (a.dkscale) a.dkscale[G->cell0 + c] += red[threadIdx.x];
+                if (a.dvfrag && blend) {
+                    double d = 0.0;
+                    for (int qb = 0; qb < NQB; ++qb) {
+                        const int npr = cdiv_dev(min(P, qb * 16 + 16), kAdjPs);
+                        for (int ps = 0; ps < npr; ++ps) d += G->Dth[((size_t)ps * NQB + qb) * n_slots + s];
+                    }
+                    const double sc = kscale ? kscale[c] : 1.0;
+                    a.dvfrag[G->cell0 + c] += sc * d * G->dthdv[s];
+                }
+            }
+        }
+    }
+
+    // ---- phase 1: one thread per (slot, bin)
     for (int t = threadIdx.x; t < kAdjSlots * N; t += blockDim.x) {
         const int sl = t / N, j = t - sl * N;
         const int s = tile * 32 + s0 + sl;
-        if (s >= G->n_slots) continue;
+        if (s >= n_slots) continue;
         const int c = perm ? perm[s] : s;
         if (c < 0) continue;
         const size_t base = (size_t)c * P + j * K1;
-        double m[4];
-        for (int i = 0; i < K1; ++i) m[i] = mu[base + i];
-        if (gamma && k > 0) limiter_vjp(k, gamma[(size_t)c * N + j], ylim + base, m);
+        double* m = sl_lam + sl * P + j * K1;
+        if (gamma && k > 0) {
+            double l[4];
+            for (int i = 0; i < K1; ++i) l[i] = m[i];
+            limiter_vjp(k, gamma[(size_t)c * N + j], ylim + base, l);
+            for (int i = 0; i < K1; ++i) m[i] = l[i];
+        }
         for (int i = 0; i < K1; ++i) {
-            smu[sl * P + j * K1 + i] = m[i];
+            if (out) {
+                out[base + i] = m[i];
+                continue;
+            }
             if (acc) acc[base + i] = a.acc_add ? acc[base + i] + a.a * m[i] : a.a * m[i];
-            prev[base + i] = a.prev_add ? prev[base + i] + a.b * m[i] : a.b * m[i];
+            if (prev) prev[base + i] = a.prev_add ? prev[base + i] + a.b * m[i] : a.b * m[i];
         }
     }
+    if (out) return;
     __syncthreads();
-    // phase 2: nu
+
+    // ---- phase 2: nu, one thread per (slot, bin)
+    GD_GLOBAL double* nu = gptr(G->nu);
     const int vbase = (N - 1) + (conservative ? 0 : 1);
     for (int t = threadIdx.x; t < kAdjSlots * N; t += blockDim.x) {
         const int sl = t / N, j = t - sl * N;
         const int s = tile * 32 + s0 + sl;
-        if (s >= G->n_slots) continue;
+        if (s >= n_slots) continue;
         const int c = perm ? perm[s] : s;
         GD_GLOBAL double* nrow = nu + (size_t)s * nus;
         if (c < 0) {
             for (int o = j; o < nus; o += N) nrow[o] = 0.0;
             continue;
         }
-        const double* m = smu + sl * P + j * K1;
+        const double* m = sl_lam + sl * P + j * K1;
         double rho[4];
         for (int i = 0; i < K1; ++i) rho[i] = a.bdt * m[i];
         const double hj = h[j];
@@ -358,92 +403,16 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_nu(AdjStageArgs a)
     }
 }
 
-// prev += s G with G_p = G2_p + sum over q blocks of the first-sum partials (both
-// parts); dkscale += (1/2) y . G; dvfrag += s (sum of the blend partials) dtheta/dv.
-// One workgroup per kAdjSlots slots, one thread per (slot, coefficient).
-__global__ __launch_bounds__(kAdjThreads) void k_adj_combine(AdjStageArgs a)
-{
-    constexpr int SUB = 32 / kAdjSlots;
-    __shared__ double red[kAdjSlots];
-    const GD_CONST GroupDev* groups = cptr(a.groups);
-    const int tile_all = (int)blockIdx.x / SUB, s0 = ((int)blockIdx.x % SUB) * kAdjSlots;
-    int gi = 0;
-    while (gi + 1 < a.n_groups && tile_all >= groups[gi + 1].tile_off) ++gi;
-    const GD_CONST GroupDev* G = groups + gi;
-    const int tile = tile_all - G->tile_off;
-    const int P = G->P, NQB = G->NQB, NPS = G->NPS, n_slots = G->n_slots;
-    const bool blend = G->R > 1;
-    const GD_GLOBAL int* perm = gptr(G->perm);
-    const GD_GLOBAL double* y = gptr(a.y) + G->val0;
-    GD_GLOBAL double* prev = gptr(a.prev) + G->val0;
-    const GD_GLOBAL double* G2 = gptr(G->G2);
-    const GD_GLOBAL double* G1p = gptr(G->G1p);
-    if (threadIdx.x < kAdjSlots) red[threadIdx.x] = 0.0;
-    __syncthreads();
-    for (int t = threadIdx.x; t < kAdjSlots * P; t += blockDim.x) {
-        const int sl = t / P, p = t - sl * P;
-        const int s = tile * 32 + s0 + sl;
-        if (s >= n_slots) continue;
-        const int c = perm ? perm[s] : s;
-        if (c < 0) continue;
-        // second-sum partials: the p ranges present in the block of q = p
-        const int qbp = p / 16, npr = cdiv_dev(min(P, qbp * 16 + 16), kAdjPs);
-        double g = 0.0;
-        for (int ps = 0; ps < npr; ++ps) g += G2[((size_t)ps * n_slots + s) * P + p];
-        for (int qb = p / 16; qb < NQB; ++qb) {
-            g += G1p[((size_t)qb * n_slots + s) * P + p];
-            if (blend) g += G1p[(((size_t)NQB + qb) * n_slots + s) * P + p];
-        }
-        const double sc = a.kscale ? a.kscale[G->cell0 + c] : 1.0;
-        prev[(size_t)c * P + p] += sc * g;
-        atomicAdd(&red[sl], 0.5 * y[(size_t)c * P + p] * g);
-    }
-    __syncthreads();
-    if (threadIdx.x < kAdjSlots) {
-        const int s = tile * 32 + s0 + threadIdx.x;
-        if (s < n_slots) {
-            const int c = perm ? perm[s] : s;
-            if (c >= 0) {
-                if (a.dkscale) a.dkscale[G->cell0 + c] += red[threadIdx.x];
-                if (a.dvfrag && blend) {
-                    double d = 0.0;
-                    for (int qb = 0; qb < NQB; ++qb) {
-                        const int npr = cdiv_dev(min(P, qb * 16 + 16), kAdjPs);
-                        for (int ps = 0; ps < npr; ++ps) d += G->Dth[((size_t)ps * NQB + qb) * n_slots + s];
-                    }
-                    const double sc = a.kscale ? a.kscale[G->cell0 + c] : 1.0;
-                    a.dvfrag[G->cell0 + c] += sc * d * G->dthdv[s];
-                }
-            }
-        }
-    }
-}
-
-int launch_adj_limit(const AdjStageArgs& a, hipStream_t s)
-{
-    if (a.n_bins == 0) return GD_OK;
-    hipLaunchKernelGGL(k_adj_limit, dim3((unsigned)((a.n_bins + 255) / 256)), dim3(256), 0, s, a);
-    HIP_TRY(hipGetLastError());
-    return GD_OK;
-}
-
-int launch_adj_nu(const AdjStageArgs& a, hipStream_t s)
+int launch_adj_boundary(const AdjStageArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return GD_OK;
+    const dim3 grid((unsigned)a.n_tiles * (32 / kAdjSlots));
     if (a.max_p <= 96)
-        hipLaunchKernelGGL(k_adj_nu<96>, dim3(a.n_tiles * (32 / kAdjSlots)), dim3(kAdjThreads), 0, s, a);
+        hipLaunchKernelGGL(k_adj_boundary<96>, grid, dim3(kAdjThreads), 0, s, a);
     else if (a.max_p <= 192)
-        hipLaunchKernelGGL(k_adj_nu<192>, dim3(a.n_tiles * (32 / kAdjSlots)), dim3(kAdjThreads), 0, s, a);
+        hipLaunchKernelGGL(k_adj_boundary<192>, grid, dim3(kAdjThreads), 0, s, a);
     else
         return fail(GD_EUNSUPPORTED, "P too large for the reverse stage kernel");
-    HIP_TRY(hipGetLastError());
-    return GD_OK;
-}
-
-int launch_adj_combine(const AdjStageArgs& a, hipStream_t s)
-{
-    if (a.n_tiles == 0) return GD_OK;
-    hipLaunchKernelGGL(k_adj_combine, dim3(a.n_tiles * (32 / kAdjSlots)), dim3(kAdjThreads), 0, s, a);
     HIP_TRY(hipGetLastError());
     return GD_OK;
 }

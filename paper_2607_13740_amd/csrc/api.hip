@@ -1121,49 +1121,55 @@ static AdjStageArgs adj_args(const gd_plan* pl)
     a.groups = pl->groups_dev;
     a.n_groups = int(pl->groups.size());
     a.n_tiles = pl->tiles32;
-    a.n_bins = pl->n_bins;
     a.max_p = pl->max_p;
     return a;
 }
 
-// cotangent of a stage's output (through its limiter, when the limited state ylim and
-// the factors gamma are given) -> contributions to the cotangents of g_n (acc) and
-// of the stage input y (prev), through L at y
-static int adj_stage(gd_plan* pl, hipStream_t s, const double* kscale, const double* ylim, const double* gamma,
-                     double* mu, double* acc, int acc_add, double a, double* prev, int prev_add, double b, double bdt,
-                     const double* y, double* dks, double* dvf)
+// One boundary of the reverse step: the partial sums of the previous vector-Jacobian
+// contraction (linearised at lin, when set) are combined into the cotangent mu, the
+// stage's limiter adjoint is applied (ylim, gamma), and the result either goes to out
+// or updates acc and prev and assembles nu for the next contraction.
+struct Boundary {
+    const double* lin = nullptr;
+    const double* mu = nullptr;
+    const double* ylim = nullptr;
+    const double* gamma = nullptr;
+    double* out = nullptr;
+    double* acc = nullptr;
+    int acc_add = 0;
+    double a = 0.0;
+    double* prev = nullptr;
+    int prev_add = 0;
+    double b = 0.0;
+    double bdt = 0.0;
+};
+
+static int adj_boundary(gd_plan* pl, hipStream_t s, const double* kscale, double* dks, double* dvf, const Boundary& B)
 {
-    int rc;
     AdjStageArgs A = adj_args(pl);
-    A.ylim = ylim;
-    A.gamma = gamma;
-    A.mu = mu;
-    A.acc = acc;
-    A.acc_add = acc_add;
-    A.a = a;
-    A.prev = prev;
-    A.prev_add = prev_add;
-    A.b = b;
-    A.bdt = bdt;
-    if ((rc = launch_adj_nu(A, s))) return rc;
-    ContractArgs c{pl->groups_dev, pl->adj_items, y, pl->n_adj_items};
-    if ((rc = launch_adjoint_fp64(c, pl->ksomax, s))) return rc;
-    AdjStageArgs C = adj_args(pl);
-    C.y = y;
-    C.prev = prev;
-    C.kscale = kscale;
-    C.dkscale = dks;
-    C.dvfrag = dvf;
-    return launch_adj_combine(C, s);
+    A.combine = B.lin != nullptr;
+    A.ylin = B.lin;
+    A.kscale = kscale;
+    A.dkscale = dks;
+    A.dvfrag = dvf;
+    A.mu = B.mu;
+    A.ylim = B.ylim;
+    A.gamma = B.gamma;
+    A.out = B.out;
+    A.acc = B.acc;
+    A.acc_add = B.acc_add;
+    A.a = B.a;
+    A.prev = B.prev;
+    A.prev_add = B.prev_add;
+    A.b = B.b;
+    A.bdt = B.bdt;
+    return launch_adj_boundary(A, s);
 }
 
-static int adj_limit(gd_plan* pl, hipStream_t s, double* lam, const double* y, const double* gamma)
+static int adj_contract(gd_plan* pl, hipStream_t s, const double* y)
 {
-    AdjStageArgs A = adj_args(pl);
-    A.lam = lam;
-    A.y = y;
-    A.gamma = gamma;
-    return launch_adj_limit(A, s);
+    ContractArgs c{pl->groups_dev, pl->adj_items, y, pl->n_adj_items};
+    return launch_adjoint_fp64(c, pl->ksomax, s);
 }
 
 extern "C" int gd_adjoint(gd_plan* pl, const double* states, const double* gammas, const double* kscale, double dt,
@@ -1173,14 +1179,15 @@ extern "C" int gd_adjoint(gd_plan* pl, const double* states, const double* gamma
     int rc;
     if ((rc = prepare_adjoint(pl))) return rc;
     hipStream_t s = pl->stream;
-    const size_t V = size_t(pl->n_values), B = size_t(pl->n_bins);
+    const size_t V = size_t(pl->n_values), NB = size_t(pl->n_bins);
     auto S = [&](long long i) { return states + i * V; };
-    auto Gm = [&](long long i) { return gammas + i * B; };
+    auto Gm = [&](long long i) { return gammas + i * NB; };
     if (dkscale && (rc = launch_fill_f64(dkscale, pl->n_cells, 0.0, s))) return rc;
     if (dvfrag && (rc = launch_fill_f64(dvfrag, pl->n_cells, 0.0, s))) return rc;
     // three cotangent buffers rotate: the caller's lam and two of the plan
     double* buf[3] = {lam, pl->adj_buf[0], pl->adj_buf[1]};
     int cur = 0;
+    const double* lin = nullptr;   // state of the contraction whose partial sums are pending
     for (int n = n_steps - 1; n >= 0; --n) {
         const double* gn = S(3ll * n);
         const double* y1 = S(3ll * n + 1);
@@ -1189,24 +1196,28 @@ extern "C" int gd_adjoint(gd_plan* pl, const double* states, const double* gamma
         double* X = buf[cur];
         double* Acc = buf[(cur + 1) % 3];
         double* Y = buf[(cur + 2) % 3];
-        // stage 3: g1 = Lim(1/3 gn + 2/3 (y2 + dt L(y2)))
-        if ((rc = adj_stage(pl, s, kscale, g1, Gm(3ll * n + 3), X, Acc, 0, 1.0 / 3.0, Y, 0, 2.0 / 3.0, 2.0 / 3.0 * dt,
-                            y2, dkscale, dvfrag)))
-            return rc;
+        Boundary B;
+        // stage 3: g1 = Lim(1/3 gn + 2/3 (y2 + dt L(y2))); the cotangent of g1 is in X
+        B = Boundary{lin, X, g1, Gm(3ll * n + 3), nullptr, Acc, 0, 1.0 / 3.0, Y, 0, 2.0 / 3.0, 2.0 / 3.0 * dt};
+        if ((rc = adj_boundary(pl, s, kscale, dkscale, dvfrag, B)) || (rc = adj_contract(pl, s, y2))) return rc;
         // stage 2: y2 = Lim(3/4 gn + 1/4 (y1 + dt L(y1))); the cotangent of y2 is in Y
-        if ((rc = adj_stage(pl, s, kscale, y2, Gm(3ll * n + 2), Y, Acc, 1, 0.75, X, 0, 0.25, 0.25 * dt, y1, dkscale,
-                            dvfrag)))
-            return rc;
+        B = Boundary{y2, Y, y2, Gm(3ll * n + 2), nullptr, Acc, 1, 0.75, X, 0, 0.25, 0.25 * dt};
+        if ((rc = adj_boundary(pl, s, kscale, dkscale, dvfrag, B)) || (rc = adj_contract(pl, s, y1))) return rc;
         // stage 1: y1 = Lim(gn + dt L(gn)); the cotangent of y1 is in X, that of gn gathers in Acc
-        if ((rc = adj_stage(pl, s, kscale, y1, Gm(3ll * n + 1), X, nullptr, 0, 0.0, Acc, 1, 1.0, dt, gn, dkscale,
-                            dvfrag)))
-            return rc;
+        B = Boundary{y1, X, y1, Gm(3ll * n + 1), nullptr, nullptr, 0, 0.0, Acc, 1, 1.0, dt};
+        if ((rc = adj_boundary(pl, s, kscale, dkscale, dvfrag, B)) || (rc = adj_contract(pl, s, gn))) return rc;
+        lin = gn;
         cur = (cur + 1) % 3;
     }
-    // the limiter applied to the caller's state before the first step
-    if ((rc = adj_limit(pl, s, buf[cur], S(0), Gm(0)))) return rc;
-    if (cur != 0) HIP_TRY(hipMemcpyAsync(lam, buf[cur], V * sizeof(double), hipMemcpyDeviceToDevice, s));
-    return GD_OK;
+    // the last combine and the limiter applied to the caller's state before the first
+    // step, into lam
+    Boundary B;
+    B.lin = lin;
+    B.mu = buf[cur];
+    B.ylim = S(0);
+    B.gamma = Gm(0);
+    B.out = lam;
+    return adj_boundary(pl, s, kscale, dkscale, dvfrag, B);
 }
 
 // single right-hand-side vector-Jacobian product (test and composition support):
@@ -1219,8 +1230,16 @@ extern "C" int gd_collision_vjp(gd_plan* pl, const double* g, const double* ksca
     if ((rc = prepare_adjoint(pl))) return rc;
     if (dkscale && (rc = launch_fill_f64(dkscale, pl->n_cells, 0.0, pl->stream))) return rc;
     if (dvfrag && (rc = launch_fill_f64(dvfrag, pl->n_cells, 0.0, pl->stream))) return rc;
-    return adj_stage(pl, pl->stream, kscale, nullptr, nullptr, mu, nullptr, 0, 0.0, grad, 1, 0.0, 1.0, g, dkscale,
-                     dvfrag);
+    Boundary B;
+    B.mu = mu;
+    B.bdt = 1.0;
+    if ((rc = adj_boundary(pl, pl->stream, kscale, nullptr, nullptr, B)) || (rc = adj_contract(pl, pl->stream, g)))
+        return rc;
+    B = Boundary{};
+    B.lin = g;
+    B.mu = grad;
+    B.out = grad;
+    return adj_boundary(pl, pl->stream, kscale, dkscale, dvfrag, B);
 }
 
 // ---------------------------------------------------------------------------- autotuner

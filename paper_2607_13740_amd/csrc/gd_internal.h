@@ -174,22 +174,22 @@ struct AdjStageArgs {
     const GroupDev* groups;
     int n_groups;
     int n_tiles;               // 32-slot tiles over all groups
-    long long n_bins;          // bins over all groups
-    int max_p;                 // largest P over the groups (sets the LDS size of k_adj_nu)
-    const double* gamma;       // limiter factors of the stage (k_adj_nu: nullptr = no limiter)
-    const double* y;           // k_adj_limit: limited state; k_adj_combine: linearisation state
-    const double* ylim;        // k_adj_nu: limited state of the stage (with gamma)
-    double* lam;               // k_adj_limit: cotangent, in place
-    const double* mu;          // k_adj_nu: cotangent of the stage's output (before the limiter VJP)
-    double* acc;               // k_adj_nu: acc (=|+=) a mu (or nullptr)
+    int max_p;                 // largest P over the groups (sets the LDS size)
+    int combine;               // add s G of the previous contraction (linearised at ylin) to mu
+    const double* ylin;
+    const double* mu;          // cotangent of the stage's output (before the combine and the limiter VJP)
+    const double* gamma;       // limiter factors of the stage, or nullptr (no limiter)
+    const double* ylim;        // limited state of the stage (with gamma)
+    double* out;               // if set: the cotangent after the limiter goes here, nothing else
+    double* acc;               // acc (=|+=) a lam (or nullptr)
     int acc_add;
     double a;
-    double* prev;              // k_adj_nu: prev (=|+=) b mu; k_adj_combine: prev += s G
+    double* prev;              // prev (=|+=) b lam (or nullptr)
     int prev_add;
     double b;
-    double bdt;                // b dt
+    double bdt;                // b dt: nu = A^T (b dt lam)
     const double* kscale;
-    double* dkscale;           // k_adj_combine outputs (+=), [cells] or nullptr
+    double* dkscale;           // combine outputs (+=), [cells] or nullptr
     double* dvfrag;
 };
 
@@ -201,9 +201,7 @@ int launch_project(const double* samples, const double* wP, double* coef, int C,
 int launch_contract_mixed(const ContractArgs& a, int ksmax, int waves, int tpw, hipStream_t s);
 int launch_contract_fp64(const ContractArgs& a, int ksmax, int waves, hipStream_t s);
 int launch_adjoint_fp64(const ContractArgs& a, int ksomax, hipStream_t s);
-int launch_adj_limit(const AdjStageArgs& a, hipStream_t s);
-int launch_adj_nu(const AdjStageArgs& a, hipStream_t s);
-int launch_adj_combine(const AdjStageArgs& a, hipStream_t s);
+int launch_adj_boundary(const AdjStageArgs& a, hipStream_t s);
 int launch_fill_f64(double* p, long long n, double v, hipStream_t s);
 
 } // namespace gd

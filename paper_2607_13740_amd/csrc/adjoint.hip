@@ -44,7 +44,7 @@ template <int W>
 struct AdjItem {
     const GD_CONST GroupDev* gp;
     const double* gplan;
-    int r, ob0, ob1, tile0;
+    int r, ob0, ob1, tile0, ntile;   // ntile: tiles of the item inside its bracket
     uint4* buf0;
     uint4* buf1;
 
@@ -62,7 +62,7 @@ struct AdjItem {
         const int col = lane & 15, rsub = lane >> 4;
         const int slot = tile * 16 + col;
         int cell = -1;
-        if (tile < gp->tiles16 && slot < n_slots) cell = perm ? perm[slot] : slot;
+        if (wave < ntile && tile < gp->tiles16 && slot < n_slots) cell = perm ? perm[slot] : slot;
         const int ccl = cell >= 0 ? cell : 0;
         const double th = (cell >= 0 && theta) ? theta[slot] : 0.0;
         const GD_GLOBAL double* gcell = gptr(gplan) + gp->val0 + (size_t)ccl * P;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(64 * W) void k_adjoint_fp64(ContractArgs a)
     __shared__ uint4 buf1[kFragBudget * 128];
     const int4 it = cptr(a.items)[blockIdx.x];
     if (it.x < 0) return;
-    AdjItem<W> f{cptr(a.groups) + it.x, a.g, it.y, it.z & 0xffff, it.z >> 16, it.w, buf0, buf1};
+    AdjItem<W> f{cptr(a.groups) + it.x, a.g, it.y, it.z & 0x3ff, (it.z >> 10) & 0x3ff, it.w, it.z >> 20, buf0, buf1};
     dispatch_ks<KSMAX>(f.gp->KSO, f);
 }
 

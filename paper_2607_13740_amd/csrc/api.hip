@@ -608,9 +608,9 @@ static int dcopy(gd_plan* pl, T** p, const std::vector<T>& v)
     return GD_OK;
 }
 
-// cells are sorted into threshold brackets padded to 256 slots, so that every
-// contraction workgroup (at most 8 tiles of 32 slots) reads one level
-static constexpr int kSlotGranule = 256;
+// cells are sorted into threshold brackets padded to 32 slots (one split tile, two
+// FP64 tiles); a contraction work item covers the tiles of one bracket only
+static constexpr int kSlotGranule = 32;
 
 // Work items of the contraction for the plan's variant.  The hardware hands
 // workgroup b to XCD b % 8, and each XCD has its own L2.  With xcd ordering on, the
@@ -622,8 +622,9 @@ static constexpr int kSlotGranule = 256;
 // Item list of one contraction over every group of the plan: the lists of schedule
 // `which` (0: the plan's forward precision, 1: the FP64 vector-Jacobian product),
 // workgroups over W consecutive tiles of ts slots.
-static void make_items(const gd_plan* pl, int which, int W, int rows, int xcd, std::vector<int4>& h, double* flops)
+static int make_items(const gd_plan* pl, int which, int W, int rows, int xcd, std::vector<int4>& h, double* flops)
 {
+    // item word z: first row block | end row block << 10 | valid tiles << 20
     const bool mixed = which == 0 && pl->prec == GD_PREC_MIXED_F16X3;
     const int ts = mixed ? 32 : 16;
     struct It {
@@ -638,6 +639,7 @@ static void make_items(const gd_plan* pl, int which, int W, int rows, int xcd, s
         if (G.C == 0) continue;
         const Schedule& S = which == 1 ? G.t->adj : (mixed ? G.t->mixed : G.t->f64);
         const int NOB = S.NOB;
+        if (NOB > 1023 || W > 2047) return fail(GD_EUNSUPPORTED, "too many row blocks for the work-item encoding");
         const int nr = rows <= 0 ? NOB : std::min(NOB, rows);
         for (const Bracket& b : G.brackets) {
             const int t0 = b.s0 / ts, t1 = cdiv(b.s0 + b.n, ts);
@@ -650,7 +652,8 @@ static void make_items(const gd_plan* pl, int which, int W, int rows, int xcd, s
                     f += S.list_frags[size_t(b.r) * NOB + o];
                 }
                 for (int tile = t0; tile < t1; tile += W) {
-                    v.push_back({c, int4{int(gi), b.r, ob | (ob1 << 16), tile}, f});
+                    const int nt = std::min(W, t1 - tile);
+                    v.push_back({c, int4{int(gi), b.r, ob | (ob1 << 10) | (nt << 20), tile}, f});
                     total += c;
                 }
             }
@@ -683,6 +686,7 @@ static void make_items(const gd_plan* pl, int which, int W, int rows, int xcd, s
         // split path: 3 products of 32x32x16 per fragment and tile; FP64: 4 of 16x16x4
         fl += double(it.frags) * W * (mixed ? 3.0 * 2 * 32 * 32 * 16 : 4.0 * 2 * 16 * 16 * 4);
     if (flops) *flops = fl;
+    return GD_OK;
 }
 
 static int upload_items(const std::vector<int4>& h, int4** dev, size_t* cap)
@@ -702,8 +706,8 @@ static int build_items(gd_plan* pl)
 {
     std::vector<int4> h;
     double fl = 0.0;
-    make_items(pl, 0, pl->waves * pl->tpw, pl->rows, pl->xcd, h, &fl);
-    int rc = upload_items(h, &pl->items, &pl->items_cap);
+    int rc = make_items(pl, 0, pl->waves * pl->tpw, pl->rows, pl->xcd, h, &fl);
+    if (!rc) rc = upload_items(h, &pl->items, &pl->items_cap);
     if (rc) return rc;
     pl->n_items = int(h.size());
     pl->exec_flops = fl;
@@ -1073,7 +1077,7 @@ static int prepare_adjoint(gd_plan* pl)
     for (double*& b : pl->adj_buf)
         if ((rc = dalloc(pl, &b, pl->n_values))) return rc;
     std::vector<int4> h;
-    make_items(pl, 1, kAdjWaves, 1, 1, h, nullptr);
+    if ((rc = make_items(pl, 1, kAdjWaves, 1, 1, h, nullptr))) return rc;
     size_t cap = 0;
     if ((rc = upload_items(h, &pl->adj_items, &cap))) return rc;
     pl->n_adj_items = int(h.size());

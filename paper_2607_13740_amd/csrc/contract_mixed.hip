@@ -56,7 +56,7 @@ struct MixedSeg {
 template <int W, int T>
 struct MixedItem {
     const GD_CONST GroupDev* gp;
-    int r, ob0, ob1, tile0;
+    int r, ob0, ob1, tile0, ntile;   // ntile: tiles of the item inside its bracket
     uint4* buf0;
     uint4* buf1;
 
@@ -79,7 +79,7 @@ struct MixedItem {
 #pragma unroll
         for (int t = 0; t < T; ++t) {
             const int tile = tile0 + wave * T + t;
-            const bool tv = tile < n_tiles;
+            const bool tv = wave * T + t < ntile && tile < n_tiles;
             const int tcl = tv ? tile : n_tiles - 1;
             slot[t] = tile * 32 + (lane & 31);
             sv[t] = tv && slot[t] < n_slots;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(64 * W, T == 2 ? 2 : 1) void k_contract_mixed(Contr
     __shared__ uint4 buf1[kFragBudget * 128];
     const int4 it = cptr(a.items)[blockIdx.x];
     if (it.x < 0) return;   // padding of an XCD's range
-    MixedItem<W, T> f{cptr(a.groups) + it.x, it.y, it.z & 0xffff, it.z >> 16, it.w, buf0, buf1};
+    MixedItem<W, T> f{cptr(a.groups) + it.x, it.y, it.z & 0x3ff, (it.z >> 10) & 0x3ff, it.w, it.z >> 20, buf0, buf1};
     dispatch_ks<KSMAX>(f.gp->KS, f);
 }
 

@@ -130,9 +130,10 @@ struct GroupDev {
     const double* dthdv;       // [n_slots] d theta / d v_frag of the slot's cell
 };
 
-// One contraction workgroup: {group, level, ob0 | ob1 << 16, first tile}.  The
-// workgroup's waves take consecutive tiles (32 slots split path, 16 slots FP64) and
-// run the lists (level, ob0..ob1-1) of the group's tensor.
+// One contraction workgroup: {group, level, ob0 | ob1 << 10 | ntile << 20, first
+// tile}.  The workgroup's waves take consecutive tiles (32 slots split path, 16 slots
+// FP64), the first ntile of them inside the bracket of the level, and run the lists
+// (level, ob0..ob1-1) of the group's tensor.
 struct ContractArgs {
     const GroupDev* groups;
     const int4* items;

@@ -144,10 +144,11 @@ def cpu_baseline(w, params, seconds):
                       f"Gauss-Legendre sums in C (gcc -O2, OpenMP across cells), {dt:.1f} s"}
 
 
-def measured_traffic():
-    """HBM bytes of one split-FP16 contraction launch from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE measurement, scaled by the copy-kernel factors; None when the
-    kernel source has changed since the counters were taken."""
+def measured_traffic(variant):
+    """HBM bytes of one split-FP16 contraction launch in the given work-item variant,
+    from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE measurement scaled by the
+    copy-kernel factors; None when the kernel source has changed since the counters
+    were taken or the variant was not measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_contract_mixed_c3_batched_traffic.json")
     if not os.path.exists(path):
@@ -156,7 +157,11 @@ def measured_traffic():
     h = hashlib.sha256()
     for f in rec["source_files"]:
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    return rec["traffic_bytes_per_launch"] if h.hexdigest() == rec["source_sha256"] else None
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    key = f"{variant['waves']},{variant['tiles_per_wave']},{variant['rows']},{variant['xcd']}"
+    v = rec["variants"].get(key)
+    return v["traffic_bytes_per_launch"] if v else None
 
 
 def moment_weights(t, pmax=3, R=32):
@@ -345,7 +350,7 @@ def main():
                    "contraction_variant": mixed["variant"], "step": "one captured HIP graph per RK step"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_F16_TFLOPS,
-                     "traffic": measured_traffic() if w.name == "c3_batched" else None,
+                     "traffic": measured_traffic(mixed["variant"]) if w.name == "c3_batched" else None,
                      "kernel": "k_contract_mixed", "kernel_ms": mixed["kernel_ms"],
                      "algorithmic_flops_per_launch": flops_launch,
                      "flops_per_cell_eval": flops_launch / C,

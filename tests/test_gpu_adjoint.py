@@ -116,6 +116,37 @@ def test_rk_adjoint_matches_oracle_differences(oracle, prec):
     assert np.max(np.abs(dvf - fd)) <= tol * np.abs(fd).max(), (dvf, fd)
 
 
+@pytest.mark.parametrize("N,k,dt,n", [(12, 0, 1e-5, 2), (10, 1, 1e-5, 2), (28, 3, 5e-6, 1)])
+def test_rk_adjoint_orders_and_wide_state(oracle, N, k, dt, n):
+    """Orders 0, 1 and 3, the last with P = 112 (more than 96 coefficients: the wide
+    reverse-stage and vector-Jacobian instantiations): FP64 adjoint against oracle
+    differences for the initial state, kernel scales and thresholds."""
+    O = oracle
+    t, cfg, g, ks, vf, rng = _case(O, N=N, k=k, C=4, seed=17)
+    C, P = g.shape
+    w = rng.standard_normal((C, P))
+    plan = G.Plan(t, C, precision="fp64", vfrag=vf)
+    st, gm, v = plan.rk_forward(_dev(g).view(-1), dt, n, kscale=_dev(ks), count_violations=True)
+    assert v == 0
+    if k > 0:
+        assert (gm[:plan.n_bins].cpu().numpy() < 1.0).sum() > 0
+    lam = _dev(w).view(-1).clone()
+    dks, dvf = plan.adjoint(st, gm, dt, n, lam, kscale=_dev(ks))
+    lam, dks, dvf = lam.cpu().numpy().reshape(C, P), dks.cpu().numpy(), dvf.cpu().numpy()
+    loss = lambda gg=g, kk=ks, vv=vf: _loss_oracle(O, cfg, gg, kk, vv, dt, n, w)
+    d = rng.standard_normal((C, P)) * g
+    h = 1e-6
+    fd = (loss(gg=g + h * d) - loss(gg=g - h * d)) / (2 * h)
+    assert np.max(np.abs((lam * d).sum(axis=1) - fd) / np.abs(fd)) <= 1e-7, ((lam * d).sum(axis=1), fd)
+    hk = 1e-5
+    fd = (loss(kk=ks * (1 + hk)) - loss(kk=ks * (1 - hk))) / (2 * hk * ks)
+    assert np.max(np.abs(dks - fd)) <= 1e-7 * np.abs(fd).max(), (dks, fd)
+    hv = 1e-5
+    assert np.min(np.abs(vf[:, None] - np.array(LV)[None, :])) > 2 * hv
+    fd = (loss(vv=vf + hv) - loss(vv=vf - hv)) / (2 * hv)
+    assert np.max(np.abs(dvf - fd)) <= 1e-7 * np.abs(fd).max(), (dvf, fd)
+
+
 def test_mass_gradient(oracle):
     """Total mass is conserved by every stage and untouched by the limiter, so for
     Loss = sum_j h_j g_j^0(final) the gradient is h_j on the averages, zero on the

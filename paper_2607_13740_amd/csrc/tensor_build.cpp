@@ -18,7 +18,6 @@
 
 #include <algorithm>
 #include <atomic>
-#include <mutex>
 #include <thread>
 #include <cmath>
 #include <cstring>
@@ -300,28 +299,33 @@ void build_tensor(const TensorSpec& sp, HostTensor& out)
         }
     }
 
-    const int npts = int(pts.size());
+    // points feeding the same rows (the Q points of one bin) form a group that one
+    // thread sums in a fixed order, so that the tensor is the same on every run
+    std::vector<int> grp{0};
+    for (int t = 1; t < int(pts.size()); ++t)
+        if (pts[t].row0 != pts[t - 1].row0) grp.push_back(t);
+    const int ngrp = int(grp.size());
+    grp.push_back(int(pts.size()));
     std::atomic<int> next{0};
-    std::mutex mu;
     auto worker = [&]() {
         std::vector<double> B(size_t(R) * P * P), acc;
         std::vector<Node> un, vn;
         un.reserve((N + 2) * Q);
         vn.reserve((N + 2) * Q);
-        for (int t = next++; t < npts; t = next++) {
-            flux_form(c, pts[t].x, B, un, vn, acc);
-            std::lock_guard<std::mutex> lock(mu);
-            for (int r = 0; r < R; ++r)
-                for (int i = 0; i < pts[t].nrow; ++i) {
-                    const double cf = pts[t].coef[i];
-                    double* dst = &out.T[(size_t(r) * NO + pts[t].row0 + i) * P * P];
-                    const double* src = &B[size_t(r) * P * P];
-                    for (int q = 0; q < P * P; ++q) dst[q] += cf * src[q];
-                }
-        }
+        for (int gi = next++; gi < ngrp; gi = next++)
+            for (int t = grp[gi]; t < grp[gi + 1]; ++t) {
+                flux_form(c, pts[t].x, B, un, vn, acc);
+                for (int r = 0; r < R; ++r)
+                    for (int i = 0; i < pts[t].nrow; ++i) {
+                        const double cf = pts[t].coef[i];
+                        double* dst = &out.T[(size_t(r) * NO + pts[t].row0 + i) * P * P];
+                        const double* src = &B[size_t(r) * P * P];
+                        for (int q = 0; q < P * P; ++q) dst[q] += cf * src[q];
+                    }
+            }
     };
     unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
-    nth = std::min<unsigned>(nth, unsigned(npts));
+    nth = std::min<unsigned>(nth, unsigned(ngrp));
     std::vector<std::thread> th;
     for (unsigned i = 1; i < nth; ++i) th.emplace_back(worker);
     worker();

@@ -85,12 +85,23 @@ def time_steps(plan, g, w, ks, steps, warmup):
     plan.rk_step(g, w.dt, steps, kscale=ks)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # distribution of single-step durations: HIP events around each replay on the
+    # plan's stream (torch's current stream, on which the plan was created)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in ev:
+        a.record()
+        plan.rk_step(g, w.dt, 1, kscale=ks)
+        b.record()
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    pct = lambda q: per[min(len(per) - 1, int(q * (len(per) - 1) + 0.5))]
+    dist = {"p10": pct(0.1), "p50": pct(0.5), "p90": pct(0.9)}
     plan.timing(True)
     plan.rk_step(g, w.dt, max(2, steps // 4), kscale=ks)
     kms, launches = plan.contraction_time()
     sms, slaunches = plan.stage_time()
     plan.timing(False)
-    return (t1 - t0) * 1e3 / steps, kms / max(1, launches), launches, sms / max(1, slaunches)
+    return (t1 - t0) * 1e3 / steps, kms / max(1, launches), launches, sms / max(1, slaunches), dist
 
 
 def cpu_baseline(w, params, seconds):
@@ -132,16 +143,29 @@ def cpu_baseline(w, params, seconds):
             tot += time.perf_counter() - t0
         return tot
 
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cores = O.set_threads(0)
     n = max(1, min(cores, 16, w.cells))
     dt = run(n)
     m = int(min(4096, max(n, seconds / max(dt / n, 1e-9))))
     m = max(n, (m // cores) * cores) if m > cores else m
     m = min(m, w.cells)
     dt = run(m)
+    # one thread, on a few cells (about a tenth of the budget)
+    O.set_threads(1)
+    m1 = int(max(1, min(m, 0.1 * seconds / max(dt * cores / m, 1e-9))))
+    dt1 = run(m1)
+    O.set_threads(cores)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": m / dt, "unit": "cell-evals/s", "cores": cores, "kind": "oracle",
             "sample": f"first {m} cells of {w.name}, one right-hand-side evaluation each, FP64 nested "
-                      f"Gauss-Legendre sums in C (gcc -O2, OpenMP across cells), {dt:.1f} s"}
+                      f"Gauss-Legendre sums in C (gcc -O2, OpenMP across cells), {dt:.1f} s",
+            "one_thread": {"value": m1 / dt1, "sample": f"first {m1} cells, {dt1:.1f} s"},
+            "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
 def measured_traffic(variant):
@@ -288,9 +312,9 @@ def main():
             tune = {"waves": vv[0], "rows": vv[1], "xcd": vv[2], "tiles_per_wave": tp, "fixed": True}
         else:
             tune = plan.autotune(g, kscale=ks)
-        ms, kms, launches, sms = time_steps(plan, g, w, ks, args.steps, args.warmup)
+        ms, kms, launches, sms, dist = time_steps(plan, g, w, ks, args.steps, args.warmup)
         res[prec] = {"ms_per_step": ms, "kernel_ms": kms, "launches": launches, "plan": plan, "stage_ms": sms,
-                     "variant": plan.variant(), "tune": tune}
+                     "variant": plan.variant(), "tune": tune, "step_ms_dist": dist}
         print(f"# {prec}: {ms:.3f} ms/step, contraction {kms:.4f} ms/launch over {launches} launches, "
               f"stage kernel {sms:.4f} ms/launch, "
               f"variant {res[prec]['variant']}", file=sys.stderr, flush=True)
@@ -358,6 +382,7 @@ def main():
                      "executed_mfma_tflops": exec_flops / (mixed["kernel_ms"] * 1e-3) / 1e12,
                      "mfma_utilisation": exec_flops / (mixed["kernel_ms"] * 1e-3) / 1e12 / PEAK_F16_TFLOPS},
         "stage_kernel_ms": mixed["stage_ms"],
+        "step_ms_single_replays": mixed["step_ms_dist"],
         "tensor_init_s": t_init,
         "mass_drift_mixed": mixed["mass_drift"],
         "accuracy_vs_fp64_gpu": acc,
@@ -366,6 +391,7 @@ def main():
         f = res["fp64"]
         f_evals = 3.0 * C / (f["ms_per_step"] * 1e-3)
         out["fp64_gpu"] = {"value": f_evals, "ms_per_step": f["ms_per_step"], "kernel_ms": f["kernel_ms"],
+                           "step_ms_single_replays": f["step_ms_dist"],
                            "achieved_tflops": flops_launch / (f["kernel_ms"] * 1e-3) / 1e12,
                            "variant": f["variant"],
                            "peak_tflops": PEAK_F64_TFLOPS, "mass_drift": f["mass_drift"]}

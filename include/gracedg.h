@@ -202,7 +202,7 @@ int gd_rk_forward(gd_plan* plan, double* g, const double* kscale, double dt, int
                   double* gammas, long long* violations);
 int gd_adjoint(gd_plan* plan, const double* states, const double* gammas, const double* kscale, double dt,
                int n_steps, double* lam, double* dkscale, double* dvfrag);
-int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, double* mu, double* grad,
+int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, const double* mu, double* grad,
                      double* dkscale, double* dvfrag);
 
 /*

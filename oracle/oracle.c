@@ -39,6 +39,7 @@
  *    applied to the initial state and after every RK stage.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -535,4 +536,11 @@ double oracle_cfl_dt(const ocfg* c, int C, const double* g, const double* kscale
     }
     free(e);
     return best;
+}
+
+/* threads of the batch loops (timing of the oracle itself); n <= 0 keeps the default */
+int oracle_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
 }

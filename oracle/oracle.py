@@ -64,6 +64,8 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         dp = ctypes.POINTER(ctypes.c_double)
         cp = ctypes.POINTER(_Cfg)
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_threads.restype = ctypes.c_int
         lib.oracle_n_out.argtypes = [cp]
         lib.oracle_n_out.restype = ctypes.c_int
         lib.oracle_edges.argtypes = [cp, dp]
@@ -135,6 +137,12 @@ class Config:
             lv = np.ascontiguousarray(self.levels, dtype=np.float64)
             return len(lv), lv
         return 0, None
+
+
+def set_threads(n: int) -> int:
+    """OpenMP threads of the batch loops (n <= 0 keeps the current setting); returns
+    the number in use."""
+    return int(_load().oracle_set_threads(int(n)))
 
 
 def edges(cfg: Config) -> np.ndarray:

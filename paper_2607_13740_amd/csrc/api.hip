@@ -1226,7 +1226,7 @@ extern "C" int gd_adjoint(gd_plan* pl, const double* states, const double* gamma
 
 // single right-hand-side vector-Jacobian product (test and composition support):
 // grad += J_L(g)^T mu, dkscale += d(mu . L)/ds, dvfrag += d(mu . L)/dv
-extern "C" int gd_collision_vjp(gd_plan* pl, const double* g, const double* kscale, double* mu, double* grad,
+extern "C" int gd_collision_vjp(gd_plan* pl, const double* g, const double* kscale, const double* mu, double* grad,
                                 double* dkscale, double* dvfrag)
 {
     if (!pl || !g || !mu || !grad) return fail(GD_EINVAL, "null argument");

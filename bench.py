@@ -298,12 +298,13 @@ def main():
     w = W.WORKLOADS[args.workload]
     print(f"# workload {describe(w)}", file=sys.stderr, flush=True)
     tensors, counts, g0, ks, vf, t_init, params = build_inputs(w, dev)
-    infos = [t.info() for t in tensors]
     C = w.cells
-    flops_launch = sum(i["flops_per_eval"] * c for i, c in zip(infos, counts))
+    flops_launch = None
     res = {}
     for prec in (("mixed",) if args.no_fp64 else ("mixed", "fp64")):
         plan = G.Plan(tensors, counts, precision=prec, vfrag=vf)
+        # 2 nnz per cell of its level's folded tensor (+ the level-difference part)
+        flops_launch = plan.algorithmic_flops()
         g = g0.clone()
         if args.variant:
             vv = [int(x) for x in args.variant.split(",")] + [1]

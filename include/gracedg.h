@@ -239,6 +239,14 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, const
 int gd_plan_set_variant(gd_plan* plan, int waves, int tiles_per_wave, int rows, int xcd);
 int gd_plan_variant(const gd_plan* plan, int* waves, int* tiles_per_wave, int* rows, int* xcd, int* n_items,
                     double* exec_flops);
+/*
+ * gd_plan_algorithmic_flops -- the flops one right-hand-side evaluation of every
+ * cell of the plan must do, whatever the precision or blocking: per cell
+ * 2 nnz of the folded tensor of its threshold level (Sec. 3.3), plus 2 nnz of the
+ * difference to the next level for a cell between two levels (the blend of the
+ * level tensors).  Host value into *flops.
+ */
+int gd_plan_algorithmic_flops(const gd_plan* plan, double* flops);
 int gd_plan_autotune(gd_plan* plan, const double* g, const double* kscale, const char* cache_path, int* waves,
                      int* tiles_per_wave, int* rows, int* xcd);
 int gd_plan_use_graph(gd_plan* plan, int enable);

@@ -54,6 +54,7 @@ struct gd_tensor {
     int KS = 0, NOB = 0;       // split-FP16 path: K steps of 16, row blocks of 32
     int KS4 = 0, NOB16 = 0;    // FP64 path: K steps of 4, row blocks of 16
     long long nnz = 0;
+    std::vector<long long> nnz_level, nnz_delta;   // per level r: folded level, level r+1 minus r
     size_t bytes = 0;
     bool packed = false;       // device layouts uploaded (by the first plan)
     std::vector<std::unique_ptr<DevBuf>> bufs;
@@ -89,12 +90,16 @@ static inline double part(const gd_tensor* t, int r, int delta, int o, int p, in
 
 static void count_nnz(gd_tensor* t)
 {
-    long long n = 0;
-    for (int o = 0; o < t->n_out; ++o)
-        for (int p = 0; p < t->P; ++p)
-            for (int q = p; q < t->P; ++q)
-                if (fold(t, 0, o, p, q) != 0.0) ++n;
-    t->nnz = n;
+    t->nnz_level.assign(t->R, 0);
+    t->nnz_delta.assign(t->R, 0);
+    for (int r = 0; r < t->R; ++r)
+        for (int o = 0; o < t->n_out; ++o)
+            for (int p = 0; p < t->P; ++p)
+                for (int q = p; q < t->P; ++q) {
+                    if (fold(t, r, o, p, q) != 0.0) ++t->nnz_level[r];
+                    if (r + 1 < t->R && part(t, r, 1, o, p, q) != 0.0) ++t->nnz_delta[r];
+                }
+    t->nnz = t->nnz_level[0];
 }
 
 static void make_pairs(int P, std::vector<std::pair<int, int>>& pairs)
@@ -1259,6 +1264,20 @@ static std::string tune_key(const gd_plan* pl)
              std::to_string(G.C) + "b" + std::to_string(G.brackets.size());
     }
     return k;
+}
+
+extern "C" int gd_plan_algorithmic_flops(const gd_plan* pl, double* flops)
+{
+    if (!pl || !flops) return fail(GD_EINVAL, "null argument");
+    double f = 0.0;
+    for (const Group& G : pl->groups)
+        for (const Bracket& b : G.brackets) {
+            const gd_tensor* t = G.t;
+            const long long nz = t->nnz_level[b.r] + (b.r + 1 < t->R ? t->nnz_delta[b.r] : 0);
+            f += 2.0 * double(nz) * double(b.n);
+        }
+    *flops = f;
+    return GD_OK;
 }
 
 extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* kscale, const char* cache_path,

@@ -91,6 +91,7 @@ def lib():
             "gd_plan_autotune": ([_VP, _VP, _VP, ctypes.c_char_p] + [ctypes.POINTER(ctypes.c_int)] * 4, ctypes.c_int),
             "gd_plan_use_graph": ([_VP, ctypes.c_int], ctypes.c_int),
             "gd_plan_bins": ([_VP, ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+            "gd_plan_algorithmic_flops": ([_VP, _DP], ctypes.c_int),
             "gd_rk_forward": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP,
                                ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_adjoint": ([_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
@@ -303,6 +304,13 @@ class Plan:
                                      ctypes.byref(n), ctypes.byref(f)))
         return {"waves": w.value, "tiles_per_wave": t.value, "rows": r.value, "xcd": x.value, "n_items": n.value,
                 "exec_flops": f.value}
+
+    def algorithmic_flops(self):
+        """Flops one right-hand-side evaluation of every cell must do (2 nnz of the
+        folded tensor of each cell's level, plus its level-difference part)."""
+        f = ctypes.c_double()
+        _check(lib().gd_plan_algorithmic_flops(self.h, ctypes.byref(f)))
+        return f.value
 
     def autotune(self, g, kscale=None, cache_path=None):
         """Time every contraction variant on state g and keep the fastest."""

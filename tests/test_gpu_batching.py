@@ -218,3 +218,34 @@ def test_full_size_uneven_workload_sampled(oracle, prec):
         assert _eps(Yg, Yo).max() <= tol, (cfg.N, cfg.k)
         voff += n * P
         roff += n * no
+
+
+def test_algorithmic_flops_count_each_cells_level():
+    """gd_plan_algorithmic_flops: per cell 2 nnz of the folded tensor of its bracket's
+    level plus 2 nnz of the difference to the next level, counted here from the
+    exported FP64 tensors; an uneven plan adds its single-level group."""
+    lv = W.VFRAG_LEVELS
+    N, k, C = 6, 2, 90
+    t = G.Tensor(N, k, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=lv, conservative=True)
+    t2 = G.Tensor(5, 1, 1e-4, 1e8, kernel="additive", frag="powerlaw", levels=(0.5,), conservative=True)
+    P, NO, R = t.P, t.n_out, len(lv)
+    iu = np.triu_indices(P)
+
+    def fold(T, P=P, NO=NO, iu=iu):
+        T = T.reshape(NO, P, P)
+        F = T + T.transpose(0, 2, 1)
+        d = np.arange(P)
+        F[:, d, d] = T[:, d, d]
+        return F[:, iu[0], iu[1]]
+
+    Fs = [fold(t.export(r)) for r in range(R)]
+    rng = np.random.default_rng(5)
+    vf = rng.uniform(0.25, 1.05, C)
+    r = np.clip(np.searchsorted(np.array(lv), vf, side="right") - 1, 0, R - 2)
+    want = sum(2.0 * (np.count_nonzero(Fs[ri]) + np.count_nonzero(Fs[ri + 1] - Fs[ri])) for ri in r)
+    plan = G.Plan(t, C, precision="mixed", vfrag=vf)
+    assert plan.algorithmic_flops() == want
+    P2, NO2 = t2.P, t2.n_out
+    want2 = 2.0 * np.count_nonzero(fold(t2.export(0), P2, NO2, np.triu_indices(P2))) * 7
+    both = G.Plan([t, t2], [C, 7], precision="fp64", vfrag=np.concatenate([vf, np.full(7, 0.5)]))
+    assert both.algorithmic_flops() == want + want2

@@ -45,7 +45,15 @@ enum {
     GD_KERNEL_CONST = 0,          /* K = 1                                        */
     GD_KERNEL_ADDITIVE = 1,       /* K = u + v                                    */
     GD_KERNEL_MULTIPLICATIVE = 2, /* K = u v                                      */
-    GD_KERNEL_BALLISTIC = 3       /* K = (u^1/3 + v^1/3)^2 dv, dv = v0(u^-1/6+v^-1/6) */
+    GD_KERNEL_BALLISTIC = 3,      /* K = (u^1/3 + v^1/3)^2 dv, dv = v0(u^-1/6+v^-1/6) */
+    GD_KERNEL_MAXWELL = 4         /* Sec. 4.5: relative speeds Maxwellian with the
+                                     constant rms v0; with the cross section
+                                     sigma = pi (u^1/3 + v^1/3)^2 the coagulation
+                                     rate is sigma v0 beta_coag(v_bounce) and the
+                                     fragmentation rate sigma v0 beta_frag(v_frag),
+                                     beta_* the probabilities of a speed below the
+                                     bouncing threshold / above the fragmentation
+                                     threshold (no sharp split of node pairs)       */
 };
 
 /* Fragment distribution b(w,u,v) of a fragmenting collision (Sec. 2.2, Sec. 4.4,
@@ -55,7 +63,13 @@ enum {
     GD_FRAG_NONE = 0,            /* pure coagulation                                */
     GD_FRAG_POWERLAW = 1,        /* b = A w^alpha on [x_min, u+v], no remnant       */
     GD_FRAG_UNIFORM_BINARY = 2,  /* b = 2/u 1[w<=u] + 2/v 1[w<=v] (Sec. 4.4)         */
-    GD_FRAG_REMNANT_ONLY = 3     /* b = delta(w-(u+v)): fragmentation == coagulation */
+    GD_FRAG_REMNANT_ONLY = 3,    /* b = delta(w-(u+v)): fragmentation == coagulation */
+    GD_FRAG_GENERAL = 4          /* Eq. break with Eq. mfrag: b = A w^alpha on
+                                    [x_min, m_frag] + delta(w - m_left), m_frag(u,v)
+                                    set by the mass ratio (destructive, transition,
+                                    cratering, transition, mass transfer), m_left =
+                                    u + v - m_frag, A from local mass conservation;
+                                    inner integrals of App. B (Eqs. inte1/inte2)   */
 };
 
 /* Arithmetic of the contraction. */
@@ -68,7 +82,9 @@ enum {
 
 typedef struct {
     int kind;        /* GD_KERNEL_*                                     */
-    double v0;       /* velocity scale of dv (and of the ballistic K)   */
+    double v0;       /* velocity scale of dv (and of the ballistic K);
+                        GD_KERNEL_MAXWELL: the rms relative speed       */
+    double v_bounce; /* GD_KERNEL_MAXWELL: bouncing threshold v_b       */
 } gd_kernel;
 
 typedef struct {
@@ -76,9 +92,11 @@ typedef struct {
     double alpha;          /* power-law index (-11/6 in the paper)             */
     int n_levels;          /* number of threshold levels (>= 1)                */
     const double* levels;  /* host array, ascending.  n_levels == 1: the sharp
-                              threshold levels[0] for every cell.  n_levels > 1:
-                              a cell with threshold v uses the linear blend of
-                              the two neighbouring level operators (clamped)    */
+                              threshold levels[0] for every cell (with
+                              GD_KERNEL_MAXWELL: the fragmentation threshold v_f
+                              of beta_frag).  n_levels > 1: a cell with threshold
+                              v uses the linear blend of the two neighbouring
+                              level operators (clamped)                         */
 } gd_frag_law;
 
 typedef struct {

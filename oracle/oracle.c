@@ -31,6 +31,14 @@
  *    of zero length are skipped (Sec. 3.3, the A..B partial-bin sums);
  *  - the sharp collision outcome: a node pair (u,v) fragments iff
  *    dv(u,v) = v0 (u^-1/6 + v^-1/6) > v_frag, else it coagulates;
+ *  - the Maxwellian kernel of Sec. 4.5 keeps the paper's pi in the cross
+ *    section and takes the rms speed constant (the paper's toy model), so both
+ *    outcome probabilities are constants; every node pair coagulates and
+ *    fragments with these weights (no sharp split);
+ *  - the general breakage law (Eq. break with Eq. mfrag): a remnant at or below
+ *    x_min is outside the domain and contributes to neither inner integral; the
+ *    volume moments use the same node rule as every other law (F at the Gauss
+ *    nodes of the bin);
  *  - per-cell v_frag between tabulated levels: the raw flux vector is the
  *    linear blend of the two neighbouring level evaluations (clamped at the
  *    ends);
@@ -44,8 +52,8 @@
 #include <string.h>
 
 /* ---- enums mirrored by value in oracle.py (not shared with the library) ---- */
-enum { OK_CONST = 0, OK_ADDITIVE = 1, OK_MULTIPLICATIVE = 2, OK_BALLISTIC = 3 };
-enum { OF_NONE = 0, OF_POWERLAW = 1, OF_UNIFORM_BINARY = 2, OF_REMNANT_ONLY = 3 };
+enum { OK_CONST = 0, OK_ADDITIVE = 1, OK_MULTIPLICATIVE = 2, OK_BALLISTIC = 3, OK_MAXWELL = 4 };
+enum { OF_NONE = 0, OF_POWERLAW = 1, OF_UNIFORM_BINARY = 2, OF_REMNANT_ONLY = 3, OF_GENERAL = 4 };
 
 typedef struct {
     int N, k, Q;            /* mass bins, Legendre degree, GL points per piece */
@@ -56,6 +64,7 @@ typedef struct {
     double v0;              /* relative-velocity scale of the threshold          */
     int frag;               /* OF_*                                              */
     double alpha;           /* power-law index of the fragment distribution      */
+    double vb;              /* bouncing threshold of the Maxwellian kernel        */
 } ocfg;
 
 /* per-evaluation parameters that vary by cell */
@@ -126,9 +135,25 @@ static double rel_velocity(const ocfg* c, double u, double v)
     return c->v0 * (pow(u, -1.0 / 6.0) + pow(v, -1.0 / 6.0));
 }
 
+/* Probability that the relative speed is at most V when speeds follow the
+ * Maxwellian of Sec. 4.5 with rms s (the paper's closed form of beta_coag). */
+static double maxwell_cdf(double V, double s)
+{
+    double a = sqrt(3.0 / (2.0 * s * s));
+    return erf(a * V) - V * sqrt(6.0 / (M_PI * s * s)) * exp(-3.0 * V * V / (2.0 * s * s));
+}
+
 /* split into coagulating and fragmenting parts at one node pair */
 static void kernel_split(const ocfg* c, const ocell* p, double u, double v, double* kc, double* kf)
 {
+    if (c->kern == OK_MAXWELL) {
+        /* K_coag = sigma dv_rms beta_coag, K_frag = sigma dv_rms beta_frag (Sec. 4.5) */
+        double r = cbrt(u) + cbrt(v);
+        double sv = p->kscale * M_PI * r * r * c->v0;
+        *kc = sv * maxwell_cdf(c->vb, c->v0);
+        *kf = (c->frag == OF_NONE) ? 0.0 : sv * (1.0 - maxwell_cdf(p->vfrag, c->v0));
+        return;
+    }
     double K = p->kscale * kernel_K(c, u, v);
     if (c->frag == OF_NONE) { *kc = K; *kf = 0.0; return; }
     if (rel_velocity(c, u, v) > p->vfrag) { *kc = 0.0; *kf = K; }
@@ -137,6 +162,25 @@ static void kernel_split(const ocfg* c, const ocell* p, double u, double v, doub
 
 /* ------------------------------------------- inner w-integrals (App. B, inte1/2)
  * Pw = int_x^{u+v} w b(w,u,v) dw ,  Nw = int_{x_min}^x w b(w,u,v) dw              */
+
+/* mass of the power-law fragments of a (u,v) collision, Eq. mfrag (after Li 2022),
+ * with the mass ratio q = max(u,v)/min(u,v) */
+static double mfrag_general(double u, double v)
+{
+    double S = u + v, q = (u > v) ? u / v : v / u;
+    if (q <= 10.0) return S;                                                        /* destructive   */
+    if (q <= 12.0) return S / (1.0 + q) * (6.5 + 4.5 * cos((q - 10.0) / (12.0 - 10.0) * M_PI));
+    if (q <= 15.0) return S * 2.0 / (1.0 + q);                                      /* cratering     */
+    if (q <= 50.0) return S / (1.0 + q) * (1.45 + 0.55 * cos((q - 15.0) / (50.0 - 15.0) * M_PI));
+    return S * 0.9 / (1.0 + q);                                                     /* mass transfer */
+}
+
+/* A/(2+alpha) of the power-law part, A = (2+alpha) m_frag/(m_frag^(2+alpha) - x_min^(2+alpha)) */
+static double general_norm(const ocfg* c, double mf)
+{
+    double be = 2.0 + c->alpha;
+    return mf / (pow(mf, be) - pow(c->xmin, be));
+}
 static double Pw(const ocfg* c, double x, double u, double v)
 {
     double S = u + v;
@@ -156,6 +200,13 @@ static double Pw(const ocfg* c, double x, double u, double v)
     }
     case OF_REMNANT_ONLY:
         return (x < S) ? S : 0.0;
+    case OF_GENERAL: {
+        /* Eq. inte1: power law above x (x < m_frag) plus the remnant (x < m_left) */
+        double mf = mfrag_general(u, v), ml = S - mf, be = 2.0 + c->alpha, r = 0.0;
+        if (x < mf && mf > c->xmin) r += general_norm(c, mf) * (pow(mf, be) - pow(x, be));
+        if (x < ml) r += ml;
+        return r;
+    }
     default:
         return 0.0;
     }
@@ -177,6 +228,20 @@ static double Nw(const ocfg* c, double x, double u, double v)
     }
     case OF_REMNANT_ONLY:
         return (c->xmin < S && S < x) ? S : 0.0;
+    case OF_GENERAL: {
+        /* Eq. inte2: power law from x_min up to min(x, m_frag) plus the remnant
+         * when it lies inside (x_min, x); with m_frag <= x_min the whole fragment
+         * mass is below every x (the ratio of the formula is 1) */
+        double mf = mfrag_general(u, v), ml = S - mf, be = 2.0 + c->alpha, r;
+        if (mf > c->xmin) {
+            double top = (x < mf) ? x : mf;
+            r = general_norm(c, mf) * (pow(top, be) - pow(c->xmin, be));
+        } else {
+            r = mf;
+        }
+        if (c->xmin < ml && ml < x) r += ml;
+        return r;
+    }
     default:
         return 0.0;
     }
@@ -404,6 +469,15 @@ int oracle_inner(const ocfg* c, double x, double u, double v, double* pw, double
 {
     *pw = Pw(c, x, u, v);
     *nw = Nw(c, x, u, v);
+    return 0;
+}
+
+/* the two rates of a node pair and the fragment mass of the general law, for unit tests */
+int oracle_rates(const ocfg* c, double u, double v, double kscale, double vfrag, double* kc, double* kf, double* mf)
+{
+    ocell p = { vfrag, kscale };
+    kernel_split(c, &p, u, v, kc, kf);
+    *mf = mfrag_general(u, v);
     return 0;
 }
 

@@ -32,8 +32,8 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # enum values of oracle.c
-KERNELS = {"const": 0, "additive": 1, "multiplicative": 2, "ballistic": 3}
-FRAGS = {"none": 0, "powerlaw": 1, "uniform_binary": 2, "remnant_only": 3}
+KERNELS = {"const": 0, "additive": 1, "multiplicative": 2, "ballistic": 3, "maxwell": 4}
+FRAGS = {"none": 0, "powerlaw": 1, "uniform_binary": 2, "remnant_only": 3, "general": 4}
 
 
 def build(force: bool = True) -> str:
@@ -50,7 +50,7 @@ class _Cfg(ctypes.Structure):
                 ("s", ctypes.POINTER(ctypes.c_double)), ("w", ctypes.POINTER(ctypes.c_double)),
                 ("xmin", ctypes.c_double), ("xmax", ctypes.c_double),
                 ("conservative", ctypes.c_int), ("kern", ctypes.c_int), ("v0", ctypes.c_double),
-                ("frag", ctypes.c_int), ("alpha", ctypes.c_double)]
+                ("frag", ctypes.c_int), ("alpha", ctypes.c_double), ("vb", ctypes.c_double)]
 
 
 _lib = None
@@ -68,6 +68,9 @@ def _load():
         lib.oracle_set_threads.restype = ctypes.c_int
         lib.oracle_n_out.argtypes = [cp]
         lib.oracle_n_out.restype = ctypes.c_int
+        lib.oracle_rates.argtypes = [cp, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     dp, dp, dp]
+        lib.oracle_rates.restype = ctypes.c_int
         lib.oracle_edges.argtypes = [cp, dp]
         lib.oracle_edges.restype = ctypes.c_int
         lib.oracle_flux_points.argtypes = [cp, dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
@@ -107,6 +110,7 @@ class Config:
     v0: float = 1.0
     alpha: float = -11.0 / 6.0
     vfrag: float = 0.5          # threshold when no per-cell value is given
+    vb: float = 0.0             # bouncing threshold (Maxwellian kernel, Sec. 4.5)
     levels: tuple = ()          # per-cell threshold table (>= 2 entries) or empty
     _keep: list = field(default_factory=list, repr=False)
 
@@ -125,7 +129,7 @@ class Config:
         self._keep = [s, w]
         c = _Cfg(self.N, self.k, self.q, _dp(s), _dp(w), float(self.xmin), float(self.xmax),
                  int(bool(self.conservative)), KERNELS[self.kernel], float(self.v0),
-                 FRAGS[self.frag], float(self.alpha))
+                 FRAGS[self.frag], float(self.alpha), float(self.vb))
         return c
 
     @property
@@ -216,6 +220,15 @@ def inner(cfg: Config, x: float, u: float, v: float):
     c = cfg._c()
     _load().oracle_inner(ctypes.byref(c), float(x), float(u), float(v), _dp(pw), _dp(nw))
     return float(pw[0]), float(nw[0])
+
+
+def rates(cfg: Config, u: float, v: float, kscale: float = 1.0, vfrag=None):
+    """(K_coag, K_frag, m_frag of the general law) at one node pair (Sec. 4.5, Eq. mfrag)."""
+    out = [np.zeros(1) for _ in range(3)]
+    c = cfg._c()
+    vf = cfg.vfrag if vfrag is None else vfrag
+    _load().oracle_rates(ctypes.byref(c), float(u), float(v), float(kscale), float(vf), *(_dp(o) for o in out))
+    return tuple(float(o[0]) for o in out)
 
 
 def cfl_dt(cfg: Config, g, kscale=None, vfrag=None) -> float:

@@ -438,8 +438,12 @@ extern "C" int gd_init_tensor(const gd_kernel* kernel, const gd_frag_law* frag, 
 {
     if (!kernel || !frag || !grid || !out) return fail(GD_EINVAL, "null argument");
     if (bins < 2 || bins > 256 || order < 0 || order > 3) return fail(GD_EINVAL, "bins must be 2..256, order 0..3");
-    if (kernel->kind < 0 || kernel->kind > 3) return fail(GD_EINVAL, "unknown kernel");
-    if (frag->kind < 0 || frag->kind > 3) return fail(GD_EINVAL, "unknown fragmentation law");
+    if (kernel->kind < 0 || kernel->kind > GD_KERNEL_MAXWELL) return fail(GD_EINVAL, "unknown kernel");
+    if (frag->kind < 0 || frag->kind > GD_FRAG_GENERAL) return fail(GD_EINVAL, "unknown fragmentation law");
+    if (kernel->kind == GD_KERNEL_MAXWELL && (!(kernel->v0 > 0.0) || !(kernel->v_bounce >= 0.0)))
+        return fail(GD_EINVAL, "the Maxwellian kernel needs v0 > 0 and v_bounce >= 0");
+    if ((frag->kind == GD_FRAG_POWERLAW || frag->kind == GD_FRAG_GENERAL) && !(frag->alpha != -2.0))
+        return fail(GD_EINVAL, "alpha = -2 has no power-law normalisation");
     if (!(grid->x_min > 0.0) || !(grid->x_max > grid->x_min)) return fail(GD_EINVAL, "need 0 < x_min < x_max");
     if (grid->quad_points < 0 || grid->quad_points > 32) return fail(GD_EINVAL, "quad_points must be 0..32");
     if (frag->kind != GD_FRAG_NONE && (frag->n_levels < 1 || frag->n_levels > 64 || !frag->levels))
@@ -451,6 +455,7 @@ extern "C" int gd_init_tensor(const gd_kernel* kernel, const gd_frag_law* frag, 
     TensorSpec& sp = t->spec;
     sp.kernel = kernel->kind;
     sp.v0 = kernel->v0;
+    sp.v_bounce = kernel->v_bounce;
     sp.frag = frag->kind;
     sp.alpha = frag->alpha;
     if (frag->kind != GD_FRAG_NONE) sp.levels.assign(frag->levels, frag->levels + frag->n_levels);

@@ -83,6 +83,9 @@ struct Ctx {
     std::vector<double> s, w;
     double beta;              // 2 + alpha
     double xmin_beta;
+    // Maxwellian kernel: outcome probabilities (coagulation; fragmentation per level)
+    double p_coag = 1.0;
+    std::vector<double> p_frag;
 };
 
 // composite rule over [a,b], split at edges (Sec. 3.3, the partial bins A..B)
@@ -123,6 +126,35 @@ double rel_speed(const TensorSpec& sp, double u, double v)
     return sp.v0 * (std::pow(u, -1.0 / 6.0) + std::pow(v, -1.0 / 6.0));
 }
 
+// Probability that a Maxwellian relative speed with rms s is below vb (sticking)
+// or above vf (fragmentation), Sec. 4.5: with a = sqrt(3/2)/s the speed CDF is
+// erf(a V) - (2/sqrt(pi)) a V exp(-a^2 V^2).
+double maxwell_below(double vb, double s)
+{
+    const double z = std::sqrt(1.5) * vb / s;
+    return std::erf(z) - 2.0 / std::sqrt(M_PI) * z * std::exp(-z * z);
+}
+double maxwell_above(double vf, double s) { return 1.0 - maxwell_below(vf, s); }
+
+// Geometric cross section times the rms speed of the Maxwellian kernel.
+double maxwell_rate(const TensorSpec& sp, double u, double v)
+{
+    const double r = std::cbrt(u) + std::cbrt(v);
+    return M_PI * r * r * sp.v0;
+}
+
+// Mass of the power-law fragments of a (u,v) collision by the mass-ratio law of
+// Eq. mfrag; the rest, u + v minus this, is the remnant.  (u+v)/(1+q) = min(u,v).
+double general_frag_mass(double u, double v)
+{
+    const double lo = std::min(u, v), q = std::max(u, v) / lo;
+    if (q <= 10.0) return u + v;                                                  // destructive
+    if (q <= 12.0) return lo * (6.5 + 4.5 * std::cos(M_PI * (q - 10.0) / 2.0));  // transition I
+    if (q <= 15.0) return 2.0 * lo;                                               // cratering
+    if (q <= 50.0) return lo * (1.45 + 0.55 * std::cos(M_PI * (q - 15.0) / 35.0)); // transition II
+    return 0.9 * lo;                                                              // mass transfer
+}
+
 // fragment mass above x produced by a (u,v) collision: int_x^{u+v} w b(w,u,v) dw
 double mass_above(const Ctx& c, double x, double u, double v)
 {
@@ -140,6 +172,17 @@ double mass_above(const Ctx& c, double x, double u, double v)
         return r;
     }
     case GD_FRAG_REMNANT_ONLY: return x < S ? S : 0.0;
+    case GD_FRAG_GENERAL: {
+        // power law A w^alpha on [x_min, m_frag], A/(2+alpha) = m_frag/(m_frag^b - x_min^b)
+        // (Eq. inte1); a fragment mass at or below x_min lies below every x
+        const double mf = general_frag_mass(u, v), rem = S - mf;
+        double r = (x < rem) ? rem : 0.0;
+        if (mf > c.sp->x_min && x < mf) {
+            const double mb = std::pow(mf, c.beta);
+            r += mf * (mb - std::pow(x, c.beta)) / (mb - c.xmin_beta);
+        }
+        return r;
+    }
     default: return 0.0;
     }
 }
@@ -159,6 +202,18 @@ double mass_below(const Ctx& c, double x, double u, double v)
         return (a * a - xm * xm) / u + (b * b - xm * xm) / v;
     }
     case GD_FRAG_REMNANT_ONLY: return (xm < S && S < x) ? S : 0.0;
+    case GD_FRAG_GENERAL: {
+        // Eq. inte2
+        const double mf = general_frag_mass(u, v), rem = S - mf;
+        double r = (xm < rem && rem < x) ? rem : 0.0;
+        if (mf > xm) {
+            const double mb = std::pow(mf, c.beta);
+            r += mf * (std::pow(std::min(x, mf), c.beta) - c.xmin_beta) / (mb - c.xmin_beta);
+        } else {
+            r += mf;
+        }
+        return r;
+    }
     default: return 0.0;
     }
 }
@@ -171,6 +226,7 @@ void flux_form(const Ctx& c, double x, std::vector<double>& B, std::vector<Node>
     const int N = sp.bins, K1 = sp.order + 1, P = N * K1;
     const int R = std::max(1, int(sp.levels.size()));
     const bool frag = sp.frag != GD_FRAG_NONE;
+    const bool maxwell = sp.kernel == GD_KERNEL_MAXWELL;
     std::fill(B.begin(), B.end(), 0.0);
     double Pu[16], Pv[16];
     acc.assign(size_t(R) * P, 0.0);
@@ -199,15 +255,22 @@ void flux_form(const Ctx& c, double x, std::vector<double>& B, std::vector<Node>
         for (const Node& v : vn) {
             double h = c.e[v.bin + 1] - c.e[v.bin];
             legendre_all(sp.order, 2.0 * (v.x - 0.5 * (c.e[v.bin] + c.e[v.bin + 1])) / h, Pv, nullptr);
-            double K = kernel_value(sp, u.x, v.x);
-            double coag = K / v.x;
-            double fr = 0.0, dv = 0.0;
-            if (frag) {
-                fr = K * mass_above(c, x, u.x, v.x) / (v.x * (u.x + v.x));
-                dv = rel_speed(sp, u.x, v.x);
+            const double above = frag ? mass_above(c, x, u.x, v.x) / (v.x * (u.x + v.x)) : 0.0;
+            double coag, fr = 0.0, dv = 0.0;
+            if (maxwell) {
+                const double K = maxwell_rate(sp, u.x, v.x);
+                coag = K * c.p_coag / v.x;
+                fr = K * above;   // times the level's fragmentation probability
+            } else {
+                const double K = kernel_value(sp, u.x, v.x);
+                coag = K / v.x;
+                fr = K * above;
+                if (frag) dv = rel_speed(sp, u.x, v.x);
             }
             for (int r = 0; r < R; ++r) {
-                double val = (!frag || dv <= sp.levels[r]) ? coag : fr;
+                double val;
+                if (maxwell) val = coag + (frag ? fr * c.p_frag[r] : 0.0);
+                else val = (!frag || dv <= sp.levels[r]) ? coag : fr;
                 if (val == 0.0) continue;
                 double* ar = &acc[size_t(r) * P + v.bin * K1];
                 for (int b = 0; b < K1; ++b) ar[b] += v.w * Pv[b] * val;
@@ -223,14 +286,18 @@ void flux_form(const Ctx& c, double x, std::vector<double>& B, std::vector<Node>
         double vmax = sp.conservative ? sp.x_max - u.x + sp.x_min : sp.x_max;
         pieces(c, sp.x_min, vmax, vn);
         for (const Node& v : vn) {
-            double dv = rel_speed(sp, u.x, v.x);
             double h = c.e[v.bin + 1] - c.e[v.bin];
             legendre_all(sp.order, 2.0 * (v.x - 0.5 * (c.e[v.bin] + c.e[v.bin + 1])) / h, Pv, nullptr);
-            double val = -kernel_value(sp, u.x, v.x) * mass_below(c, x, u.x, v.x) / (v.x * (u.x + v.x));
+            const double K = maxwell ? maxwell_rate(sp, u.x, v.x) : kernel_value(sp, u.x, v.x);
+            const double val = -K * mass_below(c, x, u.x, v.x) / (v.x * (u.x + v.x));
+            const double dv = maxwell ? 0.0 : rel_speed(sp, u.x, v.x);
             for (int r = 0; r < R; ++r) {
-                if (!(dv > sp.levels[r]) || val == 0.0) continue;
+                double vr;
+                if (maxwell) vr = val * c.p_frag[r];
+                else vr = (dv > sp.levels[r]) ? val : 0.0;
+                if (vr == 0.0) continue;
                 double* ar = &acc[size_t(r) * P + v.bin * K1];
-                for (int b = 0; b < K1; ++b) ar[b] += v.w * Pv[b] * val;
+                for (int b = 0; b < K1; ++b) ar[b] += v.w * Pv[b] * vr;
             }
         }
         close_u(u);
@@ -269,6 +336,10 @@ void build_tensor(const TensorSpec& sp, HostTensor& out)
     gauss_legendre(Q, c.s, c.w);
     c.beta = 2.0 + sp.alpha;
     c.xmin_beta = std::pow(sp.x_min, c.beta);
+    if (sp.kernel == GD_KERNEL_MAXWELL) {
+        c.p_coag = maxwell_below(sp.v_bounce, sp.v0);
+        for (double vf : sp.levels) c.p_frag.push_back(maxwell_above(vf, sp.v0));
+    }
 
     out.P = P;
     out.n_out = NO;

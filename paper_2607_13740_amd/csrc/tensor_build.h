@@ -10,6 +10,7 @@ namespace gd {
 struct TensorSpec {
     int kernel = GD_KERNEL_CONST;
     double v0 = 1.0;
+    double v_bounce = 0.0;
     int frag = GD_FRAG_NONE;
     double alpha = -11.0 / 6.0;
     std::vector<double> levels{1e300};   // fragmentation thresholds (>= 1 entry)

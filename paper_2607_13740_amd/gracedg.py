@@ -17,8 +17,8 @@ LIB_PATH = os.path.join(_HERE, "libgracedg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "gracedg.h")
 
 GD_OK, GD_EINVAL, GD_EHIP, GD_ENOMEM, GD_EUNSUPPORTED = 0, -1, -2, -3, -4
-KERNELS = {"const": 0, "additive": 1, "multiplicative": 2, "ballistic": 3}
-FRAGS = {"none": 0, "powerlaw": 1, "uniform_binary": 2, "remnant_only": 3}
+KERNELS = {"const": 0, "additive": 1, "multiplicative": 2, "ballistic": 3, "maxwell": 4}
+FRAGS = {"none": 0, "powerlaw": 1, "uniform_binary": 2, "remnant_only": 3, "general": 4}
 PREC = {"fp64": 0, "mixed": 1}
 
 
@@ -29,7 +29,7 @@ class GDError(RuntimeError):
 
 
 class _Kernel(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int), ("v0", ctypes.c_double)]
+    _fields_ = [("kind", ctypes.c_int), ("v0", ctypes.c_double), ("v_bounce", ctypes.c_double)]
 
 
 class _Frag(ctypes.Structure):
@@ -137,9 +137,9 @@ class Tensor:
     """Collision tensor for one kernel, fragment law, grid and order (gd_init_tensor)."""
 
     def __init__(self, bins, order, x_min, x_max, kernel="const", frag="none", alpha=-11.0 / 6.0,
-                 levels=(0.5,), v0=1.0, conservative=False, quad_points=0):
+                 levels=(0.5,), v0=1.0, conservative=False, quad_points=0, v_bounce=0.0):
         self.levels = np.ascontiguousarray(levels, dtype=np.float64)
-        k = _Kernel(KERNELS[kernel], float(v0))
+        k = _Kernel(KERNELS[kernel], float(v0), float(v_bounce))
         f = _Frag(FRAGS[frag], float(alpha), int(len(self.levels)),
                   self.levels.ctypes.data_as(_DP))
         g = _Grid(float(x_min), float(x_max), int(bool(conservative)), int(quad_points))

@@ -30,13 +30,22 @@ CONFIGS = {
     "ball_nc_k2": (12, 2, 1e-4, 1e8, "ballistic", "powerlaw", False, 0.5),
     "ziff_k3": (10, 3, 1e-6, 1e3, "multiplicative", "uniform_binary", False, -1.0),
     "big_k3": (48, 3, 1e-4, 1e8, "additive", "powerlaw", True, 0.5),
+    # Sec. 4.5 coupled aggregation-breakage: Maxwellian outcomes (rms 0.5, v_b = 0.1,
+    # v_f = 1) with the general breakage law (Eq. break, Eq. mfrag), alpha = -1.83
+    "coupled_k2": (20, 2, 1e-6, 1e3, "maxwell", "general", True, 1.0),
+    "coupled_nc_k3": (16, 3, 1e-6, 1e3, "maxwell", "general", False, 1.0),
+    "ball_general_k2": (24, 2, 1e-4, 1e8, "ballistic", "general", True, 0.5),
 }
 
 
 def _pair(O, name):
     N, k, xmin, xmax, kern, frag, cons, vf = CONFIGS[name]
-    t = G.Tensor(N, k, xmin, xmax, kernel=kern, frag=frag, levels=(vf,), conservative=cons)
-    cfg = O.Config(N=N, k=k, xmin=xmin, xmax=xmax, kernel=kern, frag=frag, conservative=cons, vfrag=vf)
+    alpha = -1.83 if frag == "general" else -11.0 / 6.0
+    mx = kern == "maxwell"
+    t = G.Tensor(N, k, xmin, xmax, kernel=kern, frag=frag, levels=(vf,), conservative=cons, alpha=alpha,
+                 **(dict(v0=0.5, v_bounce=0.1) if mx else {}))
+    cfg = O.Config(N=N, k=k, xmin=xmin, xmax=xmax, kernel=kern, frag=frag, conservative=cons, vfrag=vf,
+                   alpha=alpha, **(dict(v0=0.5, vb=0.1) if mx else {}))
     return t, cfg
 
 
@@ -174,17 +183,22 @@ def test_rk_matches_oracle_constant_kernel(oracle, prec):
     assert O.error_c(cfg, gg, lambda x: O.g_const(x, 1.0)) < 0.05
 
 
+@pytest.mark.parametrize("name", ["ball_k2", "coupled_k2"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_rk_matches_oracle_fragmentation(oracle, prec):
-    """Ballistic kernel with the power-law fragmentation, conservative flux, per-cell
-    kernel scale; 20 steps at the C2 time step, several cells."""
+def test_rk_matches_oracle_fragmentation(oracle, prec, name):
+    """Ballistic kernel with the power-law fragmentation, and the coupled model of
+    Sec. 4.5 (Maxwellian outcomes, general breakage with remnants); conservative
+    flux, per-cell kernel scale; 20 steps, several cells.  The step is half the Eq. dt
+    bound for the first; for the second (whose tail bins hold almost no mass, where
+    that bound is no stability bound) a fixed 0.2, at which the oracle reports no
+    violation (0.78, half the bound, gives hundreds)."""
     O = oracle
-    t, cfg = _pair(O, "ball_k2")
+    t, cfg = _pair(O, name)
     C = 40
     g, p = _states(O, cfg, C, seed=9)
     ks = p["kscale"]
     g, _ = O.limit(cfg, g)
-    dt, n = 0.5 * O.cfl_dt(cfg, g, kscale=ks), 20
+    dt, n = (0.5 * O.cfl_dt(cfg, g, kscale=ks) if name == "ball_k2" else 0.2), 20
     go, vo = O.rk(cfg, g, dt, n, kscale=ks)
     plan = G.Plan(t, C, precision=prec)
     gd = torch.tensor(g, device=DEV).view(-1)
@@ -194,7 +208,10 @@ def test_rk_matches_oracle_fragmentation(oracle, prec):
     err = np.max(np.abs((gg - go) * h), axis=1) / np.max(np.abs(go * h), axis=1)
     assert vo == 0
     _check_tail_negativity(gg, h, cfg.k + 1, v, prec)
-    assert err.max() <= (1e-11 if prec == "fp64" else 1e-6), err.max()
+    # FP64: rounding-order differences of ~1e-16 pass through 20 limited steps; with the
+    # coupled model's large rates at dt = 0.2 one cell of 40 reaches 4e-11 (the others
+    # 1e-15): the limiter's active set in a low-mass bin is the amplifier
+    assert err.max() <= (1e-6 if prec == "mixed" else 1e-11 if name == "ball_k2" else 1e-10), err.max()
     # exact mass conservation of the conservative flux, in FP64 bookkeeping
     m0 = (g * h)[:, ::cfg.k + 1].sum(axis=1)
     m1 = (gg * h)[:, ::cfg.k + 1].sum(axis=1)

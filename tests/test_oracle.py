@@ -99,6 +99,113 @@ def test_uniform_binary_inner_integrals(oracle):
         assert nw == pytest.approx(en, rel=1e-9, abs=1e-13)
 
 
+# ------------------------------------------ general breakage law and Maxwellian outcomes
+def _maxwell_pdf(v, s):
+    """Maxwellian distribution of relative speeds with rms s (Sec. 4.5)."""
+    return 4 * np.pi * v * v * (3.0 / (2 * np.pi * s * s)) ** 1.5 * np.exp(-3 * v * v / (2 * s * s))
+
+
+@pytest.mark.parametrize("s,vb,vf", [(0.5, 0.1, 1.0), (1.3, 0.4, 2.0)])
+def test_maxwell_outcome_probabilities(oracle, s, vb, vf):
+    """Sec. 4.5: K_coag = sigma dv_rms P(speed < v_b), K_frag = sigma dv_rms P(speed > v_f),
+    sigma = pi (u^1/3 + v^1/3)^2, against quadrature of the Maxwellian itself; the
+    per-cell kernel scale multiplies both."""
+    O = oracle
+    cfg = _cfg(O, N=4, k=1, xmin=1e-3, xmax=10.0, kernel="maxwell", frag="general", v0=s, vb=vb, alpha=-1.83)
+    pc = integrate.quad(_maxwell_pdf, 0, vb, args=(s,), epsabs=0, epsrel=1e-13)[0]
+    pf = integrate.quad(_maxwell_pdf, vf, np.inf, args=(s,), epsabs=0, epsrel=1e-13)[0]
+    assert integrate.quad(_maxwell_pdf, 0, np.inf, args=(s,))[0] == pytest.approx(1.0, rel=1e-12)
+    for u, v in [(1e-3, 1e-3), (0.2, 7.0), (3.0, 3.5)]:
+        sig = np.pi * (u ** (1 / 3) + v ** (1 / 3)) ** 2
+        kc, kf, _ = O.rates(cfg, u, v, kscale=1.7, vfrag=vf)
+        assert kc == pytest.approx(1.7 * sig * s * pc, rel=1e-11)
+        assert kf == pytest.approx(1.7 * sig * s * pf, rel=1e-11)
+
+
+def test_general_fragment_mass_law(oracle):
+    """Eq. mfrag (after Li 2022): m_frag/(u+v) = 1 up to q = 10, 2/(1+q) on the cratering
+    plateau (12, 15], 0.9/(1+q) beyond 50, with the cosine transitions joining the
+    plateaus continuously; symmetric in the two masses."""
+    O = oracle
+    cfg = _cfg(O, N=4, k=1, xmin=1e-6, xmax=10.0, frag="general", alpha=-1.83)
+    mf = lambda u, v: O.rates(cfg, u, v)[2]
+    small = 0.37
+    for q in (1.0, 3.0, 10.0):
+        assert mf(small, q * small) == pytest.approx(small * (1 + q), rel=1e-15)
+    for q in (12.5, 13.0, 15.0):
+        assert mf(small, q * small) == pytest.approx(2 * small, rel=1e-14)
+    for q in (50.5, 80.0, 1e4):
+        assert mf(q * small, small) == pytest.approx(0.9 * small, rel=1e-14)
+    for q in (10.0, 12.0, 15.0, 50.0):
+        lo, hi = mf(small, q * (1 - 1e-9) * small), mf(small, q * (1 + 1e-9) * small)
+        assert abs(hi - lo) <= 1e-6 * small * (1 + q), q
+    for q in (10.7, 11.5, 20.0, 37.0):
+        assert mf(small, q * small) == mf(q * small, small)
+        # inside the transitions m_frag lies between the neighbouring plateaus' values
+        assert min(2, 11 if q < 12 else 0.9) * small <= mf(small, q * small) <= max(2, 11 if q < 12 else 0.9) * small + 1e-15
+
+
+@pytest.mark.parametrize("u,v", [(0.5, 2.0), (0.1, 1.15), (0.1, 1.4), (0.02, 0.6), (0.01, 3.0), (1e-6, 0.9)])
+def test_general_inner_integrals(oracle, u, v):
+    """Eqs. inte1/inte2: power law A w^alpha on [x_min, m_frag] plus the remnant
+    delta(w - m_left), against adaptive quadrature; local mass conservation
+    Pw + Nw = u + v (Eq. break) whenever the remnant lies inside the domain."""
+    O = oracle
+    xmin = 1e-6
+    cfg = _cfg(O, N=4, k=1, xmin=xmin, xmax=10.0, frag="general", alpha=-1.83)
+    m_f = O.rates(cfg, u, v)[2]
+    m_l = u + v - m_f
+    be = 2.0 + cfg.alpha
+    A = be * m_f / (m_f ** be - xmin ** be)
+    for x in (1.5e-6, 1e-3, 0.05, 0.3, 0.8, 2.5, 0.999 * m_l, 1.001 * m_l):
+        pw, nw = O.inner(cfg, x, u, v)
+        ep = integrate.quad(lambda w: w * A * w ** cfg.alpha, x, m_f, epsabs=0, epsrel=1e-12)[0] if x < m_f else 0.0
+        en = integrate.quad(lambda w: w * A * w ** cfg.alpha, xmin, min(x, m_f), epsabs=0, epsrel=1e-12)[0]
+        inside = xmin < m_l
+        ep += m_l if (inside and x < m_l) else 0.0
+        en += m_l if (inside and m_l < x) else 0.0
+        assert pw == pytest.approx(ep, rel=1e-10, abs=1e-15 * (u + v)), (x, pw, ep)
+        assert nw == pytest.approx(en, rel=1e-10, abs=1e-15 * (u + v)), (x, nw, en)
+        if inside and x <= u + v:
+            assert pw + nw == pytest.approx(u + v, rel=1e-12)
+
+
+def test_general_law_is_powerlaw_below_mass_ratio_ten(oracle):
+    """Eq. mfrag: for mass ratios up to 10 the collision is destructive (m_frag = u+v, no
+    remnant), so on a domain spanning less than a factor 10 the general law and the
+    pure power law give the same operator."""
+    O = oracle
+    base = dict(N=5, k=2, xmin=1.0, xmax=8.0, kernel="ballistic", conservative=True, vfrag=0.1, alpha=-1.83)
+    cg, cp = _cfg(O, frag="general", **base), _cfg(O, frag="powerlaw", **base)
+    g = O.project(cg, lambda x: np.exp(-0.3 * x) * (1 + 0.1 * x))
+    Yg, Lg, _ = O.rhs(cg, g)
+    Yp, Lp, _ = O.rhs(cp, g)
+    assert np.max(np.abs(Yg - Yp)) <= 1e-13 * np.max(np.abs(Yp))
+    assert np.max(np.abs(Yp)) > 0
+
+
+def test_general_law_conserves_mass(oracle):
+    """Secs. 3.3 and 4.5: the coupled aggregation-breakage model (Maxwellian outcomes,
+    general breakage) on [1e-6, 1e3] from g0 = x e^-x conserves the total mass to
+    round-off under the conservative flux, and the remnant-bearing collisions move
+    mass (the operator differs from the destructive power law)."""
+    O = oracle
+    base = dict(N=10, k=2, xmin=1e-6, xmax=1e3, kernel="maxwell", v0=0.5, vb=0.1, vfrag=1.0, conservative=True,
+                alpha=-1.83)
+    cfg = _cfg(O, frag="general", **base)
+    g = O.project(cfg, lambda x: x * np.exp(-x))
+    g, _ = O.limit(cfg, g)
+    h = np.diff(O.edges(cfg))
+    m0 = (h * g.reshape(10, 3)[:, 0]).sum()
+    # Eq. dt bounds the averages only; a step of 1 stays violation-free here (5 does not)
+    g1, viol = O.rk(cfg, g, 1.0, 10)
+    assert viol == 0
+    assert abs((h * g1.reshape(10, 3)[:, 0]).sum() - m0) / m0 < 1e-13
+    Lp = O.rhs(_cfg(O, frag="powerlaw", **base), g)[1]
+    Lg = O.rhs(cfg, g)[1]
+    assert np.max(np.abs(Lg - Lp)) > 1e-3 * np.max(np.abs(Lp))
+
+
 # -------------------------------------------------- truncated fluxes by brute force
 def _piecewise_g(O, cfg, coeffs):
     e = O.edges(cfg)

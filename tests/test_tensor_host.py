@@ -17,6 +17,10 @@ CASES = [
     (7, 2, 1e-4, 1e8, "ballistic", "powerlaw", False, (0.5,)),
     (5, 2, 1e-6, 1e3, "multiplicative", "uniform_binary", False, (-1.0,)),
     (6, 1, 1e-4, 1e8, "ballistic", "remnant_only", True, (0.5,)),
+    # Sec. 4.5: Maxwellian outcomes (rms 0.5, v_b = 0.1, v_f = 1) with the general breakage law
+    (8, 2, 1e-6, 1e3, "maxwell", "general", True, (1.0,)),
+    (6, 3, 1e-6, 1e3, "maxwell", "general", False, (1.0,)),
+    (7, 1, 1e-4, 1e8, "ballistic", "general", True, (0.5,)),
 ]
 
 
@@ -24,8 +28,11 @@ CASES = [
 def test_tensor_contraction_matches_oracle(oracle, case):
     O = oracle
     N, k, xmin, xmax, kern, frag, cons, lv = case
-    t = G.Tensor(N, k, xmin, xmax, kernel=kern, frag=frag, levels=lv, conservative=cons)
-    cfg = O.Config(N=N, k=k, xmin=xmin, xmax=xmax, kernel=kern, frag=frag, conservative=cons, vfrag=lv[0])
+    mx = dict(v0=0.5, v_bounce=0.1) if kern == "maxwell" else {}
+    alpha = -1.83 if frag == "general" else -11.0 / 6.0
+    t = G.Tensor(N, k, xmin, xmax, kernel=kern, frag=frag, levels=lv, conservative=cons, alpha=alpha, **mx)
+    cfg = O.Config(N=N, k=k, xmin=xmin, xmax=xmax, kernel=kern, frag=frag, conservative=cons, vfrag=lv[0],
+                   alpha=alpha, **({"v0": 0.5, "vb": 0.1} if mx else {}))
     assert np.allclose(t.edges(), O.edges(cfg), rtol=1e-14, atol=0)
     T = t.export(0)
     assert T.shape == (cfg.n_out, cfg.P, cfg.P)

@@ -188,17 +188,19 @@ def test_rk_matches_oracle_constant_kernel(oracle, prec):
 def test_rk_matches_oracle_fragmentation(oracle, prec, name):
     """Ballistic kernel with the power-law fragmentation, and the coupled model of
     Sec. 4.5 (Maxwellian outcomes, general breakage with remnants); conservative
-    flux, per-cell kernel scale; 20 steps, several cells.  The step is half the Eq. dt
-    bound for the first; for the second (whose tail bins hold almost no mass, where
-    that bound is no stability bound) a fixed 0.2, at which the oracle reports no
-    violation (0.78, half the bound, gives hundreds)."""
+    flux, per-cell kernel scale; several cells.  The first runs 20 steps of half the
+    Eq. dt bound.  The second runs 10 steps of 0.05 (the oracle reports hundreds of
+    violations at half the bound, 0.78): its fragments pile up in the lowest bins,
+    which grow by ~10% per step of 0.2, and over longer horizons that growth
+    amplifies the contraction's rounding (one-step errors stay at 1e-7 split-FP16,
+    1e-15 FP64)."""
     O = oracle
     t, cfg = _pair(O, name)
     C = 40
     g, p = _states(O, cfg, C, seed=9)
     ks = p["kscale"]
     g, _ = O.limit(cfg, g)
-    dt, n = (0.5 * O.cfl_dt(cfg, g, kscale=ks) if name == "ball_k2" else 0.2), 20
+    dt, n = (0.5 * O.cfl_dt(cfg, g, kscale=ks), 20) if name == "ball_k2" else (0.05, 10)
     go, vo = O.rk(cfg, g, dt, n, kscale=ks)
     plan = G.Plan(t, C, precision=prec)
     gd = torch.tensor(g, device=DEV).view(-1)
@@ -208,10 +210,7 @@ def test_rk_matches_oracle_fragmentation(oracle, prec, name):
     err = np.max(np.abs((gg - go) * h), axis=1) / np.max(np.abs(go * h), axis=1)
     assert vo == 0
     _check_tail_negativity(gg, h, cfg.k + 1, v, prec)
-    # FP64: rounding-order differences of ~1e-16 pass through 20 limited steps; with the
-    # coupled model's large rates at dt = 0.2 one cell of 40 reaches 4e-11 (the others
-    # 1e-15): the limiter's active set in a low-mass bin is the amplifier
-    assert err.max() <= (1e-6 if prec == "mixed" else 1e-11 if name == "ball_k2" else 1e-10), err.max()
+    assert err.max() <= (1e-11 if prec == "fp64" else 1e-6), err.max()
     # exact mass conservation of the conservative flux, in FP64 bookkeeping
     m0 = (g * h)[:, ::cfg.k + 1].sum(axis=1)
     m1 = (gg * h)[:, ::cfg.k + 1].sum(axis=1)

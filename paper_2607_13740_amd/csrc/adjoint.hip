@@ -305,13 +305,23 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
         double v = mu[(size_t)c * P + p];
         if (a.combine) {
             // second-sum partials: the p ranges present in the block of q = p
+            // (fixed trip counts, so that all partial loads are in flight together)
             const int qbp = p / 16, npr = cdiv_dev(min(P, qbp * 16 + 16), kAdjPs);
-            double g = 0.0;
-            for (int ps = 0; ps < npr; ++ps) g += G2[((size_t)ps * n_slots + s) * P + p];
-            for (int qb = p / 16; qb < NQB; ++qb) {
-                g += G1p[((size_t)qb * n_slots + s) * P + p];
-                if (blend) g += G1p[(((size_t)NQB + qb) * n_slots + s) * P + p];
+            double g2[kAdjMaxNPS], g1[kAdjMaxNQB], g1d[kAdjMaxNQB];
+#pragma unroll
+            for (int ps = 0; ps < kAdjMaxNPS; ++ps)
+                g2[ps] = (ps < npr) ? G2[((size_t)ps * n_slots + s) * P + p] : 0.0;
+#pragma unroll
+            for (int qb = 0; qb < kAdjMaxNQB; ++qb) {
+                const bool in = qb >= qbp && qb < NQB;
+                g1[qb] = in ? G1p[((size_t)qb * n_slots + s) * P + p] : 0.0;
+                g1d[qb] = (in && blend) ? G1p[(((size_t)NQB + qb) * n_slots + s) * P + p] : 0.0;
             }
+            double g = 0.0;
+#pragma unroll
+            for (int ps = 0; ps < kAdjMaxNPS; ++ps) g += g2[ps];
+#pragma unroll
+            for (int qb = 0; qb < kAdjMaxNQB; ++qb) g += g1[qb] + g1d[qb];
             const double sc = kscale ? kscale[c] : 1.0;
             v += sc * g;
             atomicAdd(&red[sl], 0.5 * ylin[(size_t)c * P + p] * g);
@@ -327,9 +337,15 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
                 if (a.dkscale) a.dkscale[G->cell0 + c] += red[threadIdx.x];
                 if (a.dvfrag && blend) {
                     double d = 0.0;
-                    for (int qb = 0; qb < NQB; ++qb) {
+#pragma unroll
+                    for (int qb = 0; qb < kAdjMaxNQB; ++qb) {
                         const int npr = cdiv_dev(min(P, qb * 16 + 16), kAdjPs);
-                        for (int ps = 0; ps < npr; ++ps) d += G->Dth[((size_t)ps * NQB + qb) * n_slots + s];
+                        double dq[kAdjMaxNPS];
+#pragma unroll
+                        for (int ps = 0; ps < kAdjMaxNPS; ++ps)
+                            dq[ps] = (qb < NQB && ps < npr) ? G->Dth[((size_t)ps * NQB + qb) * n_slots + s] : 0.0;
+#pragma unroll
+                        for (int ps = 0; ps < kAdjMaxNPS; ++ps) d += dq[ps];
                     }
                     const double sc = kscale ? kscale[c] : 1.0;
                     a.dvfrag[G->cell0 + c] += sc * d * G->dthdv[s];

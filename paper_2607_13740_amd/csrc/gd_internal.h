@@ -171,6 +171,8 @@ constexpr int kAdjThreads = 256;
 constexpr int kAdjSlots = 8;   // slots per workgroup of the per-slot reverse kernels (4 per tile)
 constexpr int kAdjPs = 32;     // values of p per list of the vector-Jacobian product
 constexpr int kAdjWaves = 4;   // waves per workgroup of the vector-Jacobian product
+constexpr int kAdjMaxNQB = 12; // q blocks of 16 for P <= 192
+constexpr int kAdjMaxNPS = 6;  // p ranges of kAdjPs for P <= 192
 struct AdjStageArgs {
     const GroupDev* groups;
     int n_groups;

@@ -59,8 +59,15 @@ __device__ __forceinline__ int limit_bin(int k, double* c, double& gamma)
         gamma = 0.0;
         viol = avg < 0.0;
     } else {
-        const double m = poly_min(k, c);
-        gamma = (m < 0.0) ? fmin(1.0, avg / (avg - m)) : 1.0;
+        // |P_i| <= 1 on [-1,1]: avg - sum |c_i| >= 0 proves the minimum nonnegative
+        double lb = avg;
+        for (int i = 1; i <= k; ++i) lb -= fabs(c[i]);
+        if (lb >= 0.0) {
+            gamma = 1.0;
+        } else {
+            const double m = poly_min(k, c);
+            gamma = (m < 0.0) ? fmin(1.0, avg / (avg - m)) : 1.0;
+        }
     }
     for (int i = 1; i <= k; ++i) c[i] *= gamma;
     return viol;
@@ -185,7 +192,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                 const double Fl = (j == 0) ? 0.0 : pos(j * K1 - 1);
                 const double Fr = (j + 1 < N || !conservative) ? pos((j + 1) * K1 - 1) : 0.0;
                 const int vbase = (N - 1) + (conservative ? 0 : 1);
-                const double hj = h[j];
+                const double ihj = 1.0 / h[j];
                 if (raw) {
                     GD_GLOBAL double* rw = raw + (size_t)c * n_out;
                     if (j >= 1) rw[j - 1] = Fl;
@@ -198,12 +205,12 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                     const double V = (i == 0) ? 0.0 : pos(j * K1 + i - 1);
                     if (raw && i > 0) raw[(size_t)c * n_out + vbase + j * k + i - 1] = V;
                     const double sgn = (i & 1) ? -1.0 : 1.0;
-                    const double L = (2.0 * i + 1.0) / hj * (V - Fr + sgn * Fl);
+                    const double L = (2.0 * i + 1.0) * ihj * (V - Fr + sgn * Fl);
                     switch (a.mode) {
                     case 0: v[i] = L; break;
                     case 1: v[i] = xs[i] + a.dt * L; break;
                     case 2: v[i] = 0.75 * xn[i] + 0.25 * (xs[i] + a.dt * L); break;
-                    default: v[i] = xn[i] / 3.0 + 2.0 / 3.0 * (xs[i] + a.dt * L); break;
+                    default: v[i] = (1.0 / 3.0) * xn[i] + (2.0 / 3.0) * (xs[i] + a.dt * L); break;
                     }
                 }
             }

@@ -33,6 +33,14 @@ def test_invalid_arguments_are_rejected():
     assert L.gd_init_tensor(ctypes.byref(k2), ctypes.byref(f), 8, 1, ctypes.byref(g), ctypes.byref(h)) == G.GD_EINVAL
     with pytest.raises(G.GDError):
         G.Tensor(8, 1, 1e-3, 1e3, frag="powerlaw", levels=(0.6, 0.5))   # levels must ascend
+    with pytest.raises(G.GDError, match="Maxwellian"):
+        G.Tensor(8, 1, 1e-3, 1e3, kernel="maxwell", v0=0.0, frag="general", levels=(1.0,))
+    with pytest.raises(G.GDError, match="Maxwellian"):
+        G.Tensor(8, 1, 1e-3, 1e3, kernel="maxwell", v0=0.5, v_bounce=-0.1, frag="general", levels=(1.0,))
+    with pytest.raises(G.GDError, match="alpha"):
+        G.Tensor(8, 1, 1e-3, 1e3, frag="general", alpha=-2.0, levels=(1.0,))
+    f9 = G._Frag(9, -11 / 6, 1, lv.ctypes.data_as(G._DP))
+    assert L.gd_init_tensor(ctypes.byref(k), ctypes.byref(f9), 8, 1, ctypes.byref(g), ctypes.byref(h)) == G.GD_EINVAL
 
 
 def test_tensor_info_counts():

@@ -402,14 +402,56 @@ static void raw_flux_cell(const ocfg* c, const double* e, const double* g, doubl
  * Minimum of sum_i g^i P_i on [-1,1]: the end points and the real roots of the
  * derivative inside (-1,1).  For k <= 3 the derivative is at most quadratic:
  *   p'(xi) = g1 + 3 g2 xi + g3 (15 xi^2 - 3)/2.                                    */
+
+/* value of sum_i gi[i] P_i(x) */
+static double bin_poly(int k, const double* gi, double x)
+{
+    double v = 0.0;
+    for (int i = 0; i <= k; ++i) v += gi[i] * legendre(i, x);
+    return v;
+}
+
+static double bin_dpoly(int k, const double* gi, double x)
+{
+    double v = 0.0;
+    for (int i = 1; i <= k; ++i) v += gi[i] * legendre_d(i, x);
+    return v;
+}
+
+/* minimum of the bin polynomial over [-1,1] (Eq. gamma): the end points and the
+ * zeros of its derivative inside.  k <= 3: the derivative is at most quadratic and
+ * its roots come from the stable quadratic formula.  k >= 4: the derivative is
+ * scanned on a uniform grid of 4096 cells; every sign change is bisected to the
+ * last bit (a pair of zeros closer than a cell bounds a local minimum whose depth
+ * below the grid values is second order in the cell width). */
 static double bin_min(int k, const double* gi)
 {
-    double m = 0.0, cand[4];
-    int nc = 0;
-    cand[nc++] = -1.0;
-    cand[nc++] = 1.0;
+    double m = bin_poly(k, gi, -1.0), v1 = bin_poly(k, gi, 1.0);
+    if (v1 < m) m = v1;
+    if (k >= 4) {
+        const int n = 4096;
+        double xa = -1.0, da = bin_dpoly(k, gi, xa);
+        for (int t = 1; t <= n; ++t) {
+            double xb = -1.0 + 2.0 * (double)t / (double)n, db = bin_dpoly(k, gi, xb);
+            if (da < 0.0 && db >= 0.0) {
+                double lo = xa, hi = xb;
+                for (int it = 0; it < 200 && hi > lo; ++it) {
+                    double mid = 0.5 * (lo + hi);
+                    if (mid <= lo || mid >= hi) break;
+                    if (bin_dpoly(k, gi, mid) < 0.0) lo = mid; else hi = mid;
+                }
+                double v = bin_poly(k, gi, 0.5 * (lo + hi));
+                if (v < m) m = v;
+            }
+            xa = xb;
+            da = db;
+        }
+        return m;
+    }
     double g1 = k >= 1 ? gi[1] : 0.0, g2 = k >= 2 ? gi[2] : 0.0, g3 = k >= 3 ? gi[3] : 0.0;
     double A = 7.5 * g3, B = 3.0 * g2, Cc = g1 - 1.5 * g3;
+    double cand[2];
+    int nc = 0;
     if (A != 0.0) {
         double disc = B * B - 4.0 * A * Cc;
         if (disc >= 0.0) {
@@ -421,13 +463,11 @@ static double bin_min(int k, const double* gi)
     } else if (B != 0.0) {
         cand[nc++] = -Cc / B;
     }
-    int first = 1;
     for (int t = 0; t < nc; ++t) {
         double x = cand[t];
         if (x < -1.0 || x > 1.0) continue;
-        double val = 0.0;
-        for (int i = 0; i <= k; ++i) val += gi[i] * legendre(i, x);
-        if (first || val < m) { m = val; first = 0; }
+        double val = bin_poly(k, gi, x);
+        if (val < m) m = val;
     }
     return m;
 }
@@ -533,7 +573,7 @@ int oracle_rhs(const ocfg* c, int C, const double* g, const double* kscale, cons
 /* limiter in place over a batch; returns the violation count */
 long oracle_limit(const ocfg* c, int C, double* g)
 {
-    if (check(c) || c->k > 3) return -1;
+    if (check(c) || c->k > 4) return -1;
     int P = c->N * (c->k + 1);
     long viol = 0;
     for (int cell = 0; cell < C; ++cell) viol += limit_cell(c->N, c->k, g + (size_t)cell * P);
@@ -545,7 +585,7 @@ long oracle_limit(const ocfg* c, int C, double* g)
 long oracle_rk(const ocfg* c, int C, double* g, const double* kscale, const double* vfrag,
                double vfrag_default, int nlev, const double* lev, double dt, int n_steps)
 {
-    if (check(c) || c->k > 3 || C < 0 || n_steps < 0) return -1;
+    if (check(c) || c->k > 4 || C < 0 || n_steps < 0) return -1;
     int P = c->N * (c->k + 1), no = n_out(c);
     double* e = malloc(sizeof(double) * (c->N + 1));
     make_edges(c, e);

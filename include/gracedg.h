@@ -37,7 +37,7 @@ enum {
     GD_EINVAL = -1,   /* bad argument (shape, enum, null pointer)              */
     GD_EHIP = -2,     /* HIP runtime error                                      */
     GD_ENOMEM = -3,   /* device or host allocation failed                       */
-    GD_EUNSUPPORTED = -4 /* combination not built (e.g. order > 3 in limiter)  */
+    GD_EUNSUPPORTED = -4 /* combination not built (e.g. P above the kernels' limit) */
 };
 
 /* Collision kernel K(u,v) (Secs. 4.2-4.5). */
@@ -128,7 +128,8 @@ typedef struct {
  * with the log grid e_j = x_min (x_max/x_min)^(j/N) and Gauss-Legendre sums
  * split at every bin edge.  T is built in FP64 on the host and uploaded in the
  * layouts of both contraction precisions.  Synchronous.  *out receives a handle
- * that the caller releases with gd_free_tensor.
+ * that the caller releases with gd_free_tensor.  Limits: 2 <= bins <= 256,
+ * 0 <= order <= 4, P = bins*(order+1) <= 192; GD_EINVAL otherwise.
  */
 int gd_init_tensor(const gd_kernel* kernel, const gd_frag_law* frag, int bins, int order,
                    const gd_grid* grid, gd_tensor** out);

@@ -15,6 +15,7 @@
 // sum_p g_p sum_q M^diff_p[q] g_q.
 #include <algorithm>
 
+#include "bin_poly.h"
 #include "contract_common.h"
 
 namespace gd {
@@ -181,50 +182,7 @@ int launch_adjoint_fp64(const ContractArgs& a, int ksomax, hipStream_t s)
 // ---------------------------------------------------------------------------- per-bin pieces
 __device__ __forceinline__ int cdiv_dev(int a, int b) { return (a + b - 1) / b; }
 
-__device__ __forceinline__ double leg(int i, double x)
-{
-    switch (i) {
-    case 0: return 1.0;
-    case 1: return x;
-    case 2: return 1.5 * x * x - 0.5;
-    default: return 2.5 * x * x * x - 1.5 * x;
-    }
-}
-
-// Location of the minimum over [-1,1] of sum_i c_i P_i (k <= 3): end points and the
-// real roots of the derivative inside (-1,1).
-__device__ double poly_argmin(int k, const double* c)
-{
-    auto val = [&](double x) {
-        double v = 0.0;
-        for (int i = 0; i <= k; ++i) v += c[i] * leg(i, x);
-        return v;
-    };
-    double xb = -1.0, mb = val(-1.0);
-    if (val(1.0) < mb) { xb = 1.0; mb = val(1.0); }
-    if (k < 2) return xb;
-    const double A = (k >= 3) ? 7.5 * c[3] : 0.0;
-    const double B = 3.0 * c[2];
-    const double C = c[1] - ((k >= 3) ? 1.5 * c[3] : 0.0);
-    double r[2];
-    int nr = 0;
-    if (A != 0.0) {
-        const double d = B * B - 4.0 * A * C;
-        if (d >= 0.0) {
-            const double sq = sqrt(d);
-            const double qq = -0.5 * (B + copysign(sq, B));
-            if (qq != 0.0) { r[nr++] = qq / A; r[nr++] = C / qq; }
-            else r[nr++] = 0.0;
-        }
-    } else if (B != 0.0) {
-        r[nr++] = -C / B;
-    }
-    for (int t = 0; t < nr; ++t)
-        if (r[t] > -1.0 && r[t] < 1.0 && val(r[t]) < mb) { xb = r[t]; mb = val(r[t]); }
-    return xb;
-}
-
-// Cotangent through the limiter of one bin (k >= 1), from the limited state y and the
+// Cotangent through the limiter of one bin (1 <= k <= 4), from the limited state y and the
 // factor gamma the forward limiter applied (y_i = gamma z_i for i >= 1, y_0 = z_0):
 //   gamma = 1: identity;  gamma = 0 (flattened bin): the higher coefficients get 0;
 //   else, with q = sum_{i>=1} z_i P_i(x*) at the minimiser x* (so gamma = -z_0/q and,
@@ -239,9 +197,10 @@ __device__ __forceinline__ void limiter_vjp(int k, double gam, const GD_GLOBAL d
         for (int i = 1; i <= k; ++i) lam[i] = 0.0;
         return;
     }
-    double u[4] = {1.0, 0.0, 0.0, 0.0};
+    double u[kMaxOrder + 1] = {1.0};
     for (int i = 1; i <= k; ++i) u[i] = (y[i] / gam) / y[0];
-    const double xs = poly_argmin(k, u);
+    double xs;
+    bin_min(k, u, &xs);
     double qt = 0.0, St = 0.0;
     for (int i = 1; i <= k; ++i) {
         qt += u[i] * leg(i, xs);
@@ -364,7 +323,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
         const size_t base = (size_t)c * P + j * K1;
         double* m = sl_lam + sl * P + j * K1;
         if (gamma && k > 0) {
-            double l[4];
+            double l[kMaxOrder + 1];
             for (int i = 0; i < K1; ++i) l[i] = m[i];
             limiter_vjp(k, gamma[(size_t)c * N + j], ylim + base, l);
             for (int i = 0; i < K1; ++i) m[i] = l[i];
@@ -395,7 +354,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
             continue;
         }
         const double* m = sl_lam + sl * P + j * K1;
-        double rho[4];
+        double rho[kMaxOrder + 1];
         for (int i = 0; i < K1; ++i) rho[i] = a.bdt * m[i];
         const double hj = h[j];
         // V_{j,i}

@@ -437,7 +437,7 @@ extern "C" int gd_init_tensor(const gd_kernel* kernel, const gd_frag_law* frag, 
                               const gd_grid* grid, gd_tensor** out)
 {
     if (!kernel || !frag || !grid || !out) return fail(GD_EINVAL, "null argument");
-    if (bins < 2 || bins > 256 || order < 0 || order > 3) return fail(GD_EINVAL, "bins must be 2..256, order 0..3");
+    if (bins < 2 || bins > 256 || order < 0 || order > 4) return fail(GD_EINVAL, "bins must be 2..256, order 0..4");
     if (kernel->kind < 0 || kernel->kind > GD_KERNEL_MAXWELL) return fail(GD_EINVAL, "unknown kernel");
     if (frag->kind < 0 || frag->kind > GD_FRAG_GENERAL) return fail(GD_EINVAL, "unknown fragmentation law");
     if (kernel->kind == GD_KERNEL_MAXWELL && (!(kernel->v0 > 0.0) || !(kernel->v_bounce >= 0.0)))

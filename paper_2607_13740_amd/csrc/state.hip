@@ -5,48 +5,12 @@
 // (Eq. init).
 #include <algorithm>
 
+#include "bin_poly.h"
 #include "gd_internal.h"
 
 namespace gd {
 
 typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
-
-// Value of sum_i c_i P_i(x), degree k <= 3.
-__device__ __forceinline__ double poly_val(int k, const double* c, double x)
-{
-    double v = c[0];
-    if (k >= 1) v += c[1] * x;
-    if (k >= 2) v += c[2] * (1.5 * x * x - 0.5);
-    if (k >= 3) v += c[3] * (2.5 * x * x * x - 1.5 * x);
-    return v;
-}
-
-// Minimum over [-1,1]: end points and the real roots of the derivative
-// c1 + 3 c2 x + c3 (15 x^2 - 3)/2 inside (-1,1) (the analytic minimum of Eq. gamma).
-__device__ double poly_min(int k, const double* c)
-{
-    double m = fmin(poly_val(k, c, -1.0), poly_val(k, c, 1.0));
-    if (k < 2) return m;
-    const double A = (k >= 3) ? 7.5 * c[3] : 0.0;
-    const double B = 3.0 * c[2];
-    const double C = c[1] - ((k >= 3) ? 1.5 * c[3] : 0.0);
-    double r[2];
-    int nr = 0;
-    if (A != 0.0) {
-        const double d = B * B - 4.0 * A * C;
-        if (d >= 0.0) {
-            const double sq = sqrt(d);
-            const double qq = -0.5 * (B + copysign(sq, B));
-            if (qq != 0.0) { r[nr++] = qq / A; r[nr++] = C / qq; }
-            else r[nr++] = 0.0;
-        }
-    } else if (B != 0.0) {
-        r[nr++] = -C / B;
-    }
-    for (int t = 0; t < nr; ++t)
-        if (r[t] > -1.0 && r[t] < 1.0) m = fmin(m, poly_val(k, c, r[t]));
-    return m;
-}
 
 // Limiter of one bin in registers: g^i <- gamma g^i (i >= 1) with
 // gamma = min(1, avg / (avg - min)); a non-positive average flattens the bin and a
@@ -65,7 +29,7 @@ __device__ __forceinline__ int limit_bin(int k, double* c, double& gamma)
         if (lb >= 0.0) {
             gamma = 1.0;
         } else {
-            const double m = poly_min(k, c);
+            const double m = bin_min(k, c);
             gamma = (m < 0.0) ? fmin(1.0, avg / (avg - m)) : 1.0;
         }
     }
@@ -163,11 +127,11 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
         const int sl = t / N, j = t - sl * N;
         const int s = tile * 32 + sl;
         const int c = scell[sl];
-        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        double v[kMaxOrder + 1] = {};
         if (c >= 0) {
             const size_t base = (size_t)c * P + j * K1;
             // bin coefficients, as 16-byte vectors when K1 is even (base is then even)
-            auto load = [&](const GD_GLOBAL double* src, double (&x)[4]) {
+            auto load = [&](const GD_GLOBAL double* src, double (&x)[kMaxOrder + 1]) {
                 if (vec) {
                     const GD_GLOBAL double2* s2 = reinterpret_cast<const GD_GLOBAL double2*>(src + base);
                     for (int i2 = 0; i2 < K1 / 2; ++i2) {
@@ -198,7 +162,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                     if (j >= 1) rw[j - 1] = Fl;
                     if (j == N - 1 && !conservative) rw[N - 1] = Fr;
                 }
-                double xs[4] = {0.0, 0.0, 0.0, 0.0}, xn[4] = {0.0, 0.0, 0.0, 0.0};
+                double xs[kMaxOrder + 1] = {}, xn[kMaxOrder + 1] = {};
                 if (a.mode >= 1) load(gs, xs);
                 if (a.mode >= 2) load(gn, xn);
                 for (int i = 0; i < K1; ++i) {

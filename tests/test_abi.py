@@ -27,7 +27,7 @@ def test_invalid_arguments_are_rejected():
     assert L.gd_init_tensor(ctypes.byref(k), ctypes.byref(f), 8, 1, ctypes.byref(g), ctypes.byref(h)) == G.GD_EINVAL
     assert b"x_min" in L.gd_last_error()
     g = G._Grid(1e-3, 1e3, 0, 0)
-    assert L.gd_init_tensor(ctypes.byref(k), ctypes.byref(f), 8, 4, ctypes.byref(g), ctypes.byref(h)) == G.GD_EINVAL
+    assert L.gd_init_tensor(ctypes.byref(k), ctypes.byref(f), 8, 5, ctypes.byref(g), ctypes.byref(h)) == G.GD_EINVAL
     assert L.gd_init_tensor(ctypes.byref(k), ctypes.byref(f), 100, 3, ctypes.byref(g), ctypes.byref(h)) == G.GD_EINVAL
     k2 = G._Kernel(9, 1.0)
     assert L.gd_init_tensor(ctypes.byref(k2), ctypes.byref(f), 8, 1, ctypes.byref(g), ctypes.byref(h)) == G.GD_EINVAL

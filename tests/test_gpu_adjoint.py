@@ -116,9 +116,9 @@ def test_rk_adjoint_matches_oracle_differences(oracle, prec):
     assert np.max(np.abs(dvf - fd)) <= tol * np.abs(fd).max(), (dvf, fd)
 
 
-@pytest.mark.parametrize("N,k,dt,n", [(12, 0, 1e-5, 2), (10, 1, 1e-5, 2), (28, 3, 5e-6, 1)])
+@pytest.mark.parametrize("N,k,dt,n", [(12, 0, 1e-5, 2), (10, 1, 1e-5, 2), (28, 3, 5e-6, 1), (8, 4, 1e-5, 2)])
 def test_rk_adjoint_orders_and_wide_state(oracle, N, k, dt, n):
-    """Orders 0, 1 and 3, the last with P = 112 (more than 96 coefficients: the wide
+    """Orders 0, 1, 3 and 4, order 3 with P = 112 (more than 96 coefficients: the wide
     reverse-stage and vector-Jacobian instantiations): FP64 adjoint against oracle
     differences for the initial state, kernel scales and thresholds."""
     O = oracle

@@ -35,6 +35,9 @@ CONFIGS = {
     "coupled_k2": (20, 2, 1e-6, 1e3, "maxwell", "general", True, 1.0),
     "coupled_nc_k3": (16, 3, 1e-6, 1e3, "maxwell", "general", False, 1.0),
     "ball_general_k2": (24, 2, 1e-4, 1e8, "ballistic", "general", True, 0.5),
+    # order 4 (P = 100 and 80)
+    "ball_k4": (20, 4, 1e-4, 1e8, "ballistic", "powerlaw", True, 0.5),
+    "const_nc_k4": (16, 4, 1e-3, 1e5, "const", "none", False, 1e300),
 }
 
 
@@ -183,7 +186,7 @@ def test_rk_matches_oracle_constant_kernel(oracle, prec):
     assert O.error_c(cfg, gg, lambda x: O.g_const(x, 1.0)) < 0.05
 
 
-@pytest.mark.parametrize("name", ["ball_k2", "coupled_k2"])
+@pytest.mark.parametrize("name", ["ball_k2", "coupled_k2", "ball_k4"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 def test_rk_matches_oracle_fragmentation(oracle, prec, name):
     """Ballistic kernel with the power-law fragmentation, and the coupled model of
@@ -200,7 +203,7 @@ def test_rk_matches_oracle_fragmentation(oracle, prec, name):
     g, p = _states(O, cfg, C, seed=9)
     ks = p["kscale"]
     g, _ = O.limit(cfg, g)
-    dt, n = (0.5 * O.cfl_dt(cfg, g, kscale=ks), 20) if name == "ball_k2" else (0.05, 10)
+    dt, n = (0.05, 10) if name == "coupled_k2" else (0.5 * O.cfl_dt(cfg, g, kscale=ks), 20)
     go, vo = O.rk(cfg, g, dt, n, kscale=ks)
     plan = G.Plan(t, C, precision=prec)
     gd = torch.tensor(g, device=DEV).view(-1)

@@ -21,6 +21,9 @@ CASES = [
     (8, 2, 1e-6, 1e3, "maxwell", "general", True, (1.0,)),
     (6, 3, 1e-6, 1e3, "maxwell", "general", False, (1.0,)),
     (7, 1, 1e-4, 1e8, "ballistic", "general", True, (0.5,)),
+    # order 4
+    (6, 4, 1e-4, 1e8, "ballistic", "powerlaw", True, (0.5,)),
+    (5, 4, 1e-3, 1e5, "const", "none", False, (1e300,)),
 ]
 
 

@@ -91,7 +91,7 @@ struct Schedule {
 
 // One group of a plan as the kernels see it: the tensor of the group in the plan's
 // precision and the group's slot buffers.  Slots are the cells of the group sorted
-// by threshold bracket, each bracket padded to a multiple of 256 slots.
+// by threshold bracket, each bracket padded to a multiple of 32 slots.
 struct GroupDev {
     const uint4* frag;
     const IterDesc* iters;

@@ -302,3 +302,45 @@ def test_full_size_batched_workload_sampled(oracle, prec):
     h = torch.tensor(np.diff(t.edges()), device=DEV)
     L0 = L.view(w.cells, w.bins, w.order + 1)[:, :, 0] * h
     assert float((L0.sum(1).abs() / L0.abs().sum(1)).max()) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_large_batch_sampled(oracle, prec):
+    """A batch of 3 * 2^20 + 37 cells (48 times the benchmark's), P = 96, per-cell kernel
+    scale and threshold: byte offsets into the state and raw-flux arrays pass 2^31.  The
+    states are the first 4096 cells of the benchmark workload repeated, with distinct
+    kernel scales and thresholds per cell; sampled cells (the first, the last, the ragged
+    tail and random ones) are compared with the oracle, and one RK step keeps every
+    cell's mass."""
+    O = oracle
+    w = W.WORKLOADS["c3_batched"]
+    t = G.Tensor(w.bins, w.order, w.x_min, w.x_max, kernel=w.kernel, frag=w.frag, levels=w.levels,
+                 conservative=w.conservative)
+    C, B = 3 * (1 << 20) + 37, 4096
+    p = W.lognormal_cells(B, w.seed)
+    base = t.project(torch.tensor(W.samples(w, t.projection_points(), cells=B, params=p), device=DEV)).view(B, -1)
+    rep = torch.arange(C, device=DEV) % B
+    g0 = base[rep].contiguous().view(-1)
+    rng = np.random.default_rng(8)
+    ks_h = np.exp(0.5 * rng.standard_normal(C))
+    vf_h = rng.uniform(0.3, 1.0, C)
+    ks = torch.tensor(ks_h, device=DEV)
+    print(f"large batch {prec}: C={C} values={g0.numel()}", flush=True)
+    plan = G.Plan(t, C, precision=prec, vfrag=vf_h)
+    raw = torch.zeros(plan.n_raw, dtype=torch.float64, device=DEV)
+    plan.collision_rhs(g0, kscale=ks, raw=raw)
+    torch.cuda.synchronize()
+    idx = np.concatenate([[0, 1, C - 37, C - 1], rng.choice(C, 12, replace=False)])
+    cfg = O.Config(N=w.bins, k=w.order, xmin=w.x_min, xmax=w.x_max, kernel=w.kernel, frag=w.frag,
+                   conservative=w.conservative, levels=w.levels)
+    gs = g0.view(C, -1)[torch.tensor(idx, device=DEV)].cpu().numpy()
+    Yo, _, _ = O.rhs(cfg, gs, kscale=ks_h[idx], vfrag=vf_h[idx])
+    Yg = raw.view(C, -1)[torch.tensor(idx, device=DEV)].cpu().numpy()
+    assert _eps(Yg, Yo).max() <= (1e-12 if prec == "fp64" else 1e-6)
+    h = torch.tensor(np.repeat(np.diff(t.edges()), w.order + 1), device=DEV)
+    m0 = (g0.view(C, -1) * h)[:, ::w.order + 1].sum(1)
+    plan.rk_step(g0, w.dt, 1, kscale=ks)
+    m1 = (g0.view(C, -1) * h)[:, ::w.order + 1].sum(1)
+    assert float(((m1 - m0).abs() / m0).max()) <= 1e-12
+    del plan, raw, g0
+    torch.cuda.empty_cache()

@@ -183,7 +183,8 @@ int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, doubl
  *  dt          : time step (no CFL check is made on the device).
  *  violations  : host pointer or NULL; if non-NULL the call synchronises the
  *                stream and stores the number of bins found with a negative
- *                average by the limiter (such a bin is flattened, its mass kept).
+ *                average by the limiter (such a bin is flattened, its mass kept),
+ *                or with a non-finite coefficient.
  */
 int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_steps, long long* violations);
 

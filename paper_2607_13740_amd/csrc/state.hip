@@ -19,9 +19,10 @@ __device__ __forceinline__ int limit_bin(int k, double* c, double& gamma)
 {
     const double avg = c[0];
     int viol = 0;
-    if (avg <= 0.0) {
+    if (!(avg > 0.0) || avg == INFINITY) {
+        // a negative (or non-finite) average cannot be repaired by scaling: reported
         gamma = 0.0;
-        viol = avg < 0.0;
+        viol = !(avg == 0.0);
     } else {
         // |P_i| <= 1 on [-1,1]: avg - sum |c_i| >= 0 proves the minimum nonnegative
         double lb = avg;
@@ -30,6 +31,7 @@ __device__ __forceinline__ int limit_bin(int k, double* c, double& gamma)
             gamma = 1.0;
         } else {
             const double m = bin_min(k, c);
+            viol = !(m > -INFINITY);   // a non-finite higher coefficient
             gamma = (m < 0.0) ? fmin(1.0, avg / (avg - m)) : 1.0;
         }
     }

@@ -234,6 +234,21 @@ def test_violation_counter_fires_beyond_cfl(oracle):
     assert vo > 0 and v > 0
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_violation_counter_reports_nonfinite_state(prec):
+    """A NaN average or a NaN higher coefficient in one bin is reported by the
+    limiter's counter (it cannot be repaired); finite states report nothing."""
+    t = G.Tensor(8, 2, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=(0.5,), conservative=True)
+    plan = G.Plan(t, 3, precision=prec)
+    g = torch.zeros(plan.n_values, dtype=torch.float64, device=DEV)
+    g.view(3, 8, 3)[:, :, 0] = 1.0
+    assert plan.rk_step(g.clone(), 1e-12, 1, count_violations=True) == 0
+    for at in ((1, 3, 0), (2, 5, 2)):
+        gb = g.clone()
+        gb.view(3, 8, 3)[at] = float("nan")
+        assert plan.rk_step(gb, 1e-12, 1, count_violations=True) > 0, at
+
+
 def test_projection_matches_oracle(oracle):
     O = oracle
     t, cfg = _pair(O, "ball_k3")

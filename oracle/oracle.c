@@ -580,6 +580,31 @@ long oracle_limit(const ocfg* c, int C, double* g)
     return viol;
 }
 
+/* One SSP-RK3 step (Eq. RK3) of one cell in place on gn, with the limiter after
+ * every stage; returns the violations found.  Work arrays of P (y1, y2, L),
+ * n_out (Y) and N+1 (fe) doubles. */
+static long rk3_cell(const ocfg* c, const double* e, double* gn, double ks, double vf, int nlev,
+                     const double* lev, double dt, double* y1, double* y2, double* L, double* Y, double* fe)
+{
+    int P = c->N * (c->k + 1);
+    long viol = 0;
+    raw_flux_cell(c, e, gn, ks, vf, nlev, lev, Y, fe);
+    assemble_L(c, e, Y, L);
+    for (int t = 0; t < P; ++t) y1[t] = gn[t] + dt * L[t];
+    viol += limit_cell(c->N, c->k, y1);
+
+    raw_flux_cell(c, e, y1, ks, vf, nlev, lev, Y, fe);
+    assemble_L(c, e, Y, L);
+    for (int t = 0; t < P; ++t) y2[t] = 0.75 * gn[t] + 0.25 * (y1[t] + dt * L[t]);
+    viol += limit_cell(c->N, c->k, y2);
+
+    raw_flux_cell(c, e, y2, ks, vf, nlev, lev, Y, fe);
+    assemble_L(c, e, Y, L);
+    for (int t = 0; t < P; ++t) gn[t] = gn[t] / 3.0 + 2.0 / 3.0 * (y2[t] + dt * L[t]);
+    viol += limit_cell(c->N, c->k, gn);
+    return viol;
+}
+
 /* n_steps of SSP-RK3 (Eq. RK3) with the limiter on the initial state and after
  * every stage.  g is [C][N(k+1)] in place. */
 long oracle_rk(const ocfg* c, int C, double* g, const double* kscale, const double* vfrag,
@@ -601,21 +626,61 @@ long oracle_rk(const ocfg* c, int C, double* g, const double* kscale, const doub
         double ks = kscale ? kscale[cell] : 1.0;
         double vf = vfrag ? vfrag[cell] : vfrag_default;
         viol += limit_cell(c->N, c->k, gn);
-        for (int n = 0; n < n_steps; ++n) {
+        for (int n = 0; n < n_steps; ++n) viol += rk3_cell(c, e, gn, ks, vf, nlev, lev, dt, y1, y2, L, Y, fe);
+        free(y1); free(y2); free(L); free(Y); free(fe);
+    }
+    free(e);
+    return viol;
+}
+
+/* Per-cell time steps under the CFL bound (Eq. dt), n_sub sub-steps of SSP-RK3
+ * toward the common end time t_end.  t is [C], the time each cell has reached
+ * (in/out).  In every sub-step a cell with t < t_end takes
+ *     dt = min(dt_max, t_end - t, cfl * B),
+ *     B  = min over bins with F(e_{j+1}) > F(e_j) and g_j^0 > 0 of h_j g_j^0 / (F(e_{j+1}) - F(e_j)),
+ * B from the fluxes of its state at the start of the sub-step; t becomes t_end when
+ * dt = t_end - t, else t + dt.  A cell with t >= t_end (or dt = 0) is left as it
+ * is.  Only a bin that loses mass can turn negative in a forward-Euler stage, and
+ * a bin with a zero average cannot be kept positive by any step, so both are left
+ * out of B.  The limiter acts on the start state and after every stage, as in
+ * oracle_rk. */
+long oracle_rk_adaptive(const ocfg* c, int C, double* g, const double* kscale, const double* vfrag,
+                        double vfrag_default, int nlev, const double* lev, double cfl, double dt_max,
+                        double t_end, int n_sub, double* t)
+{
+    if (check(c) || c->k > 4 || C < 0 || n_sub < 0 || !(cfl > 0.0) || !(dt_max > 0.0)) return -1;
+    int P = c->N * (c->k + 1), no = n_out(c);
+    double* e = malloc(sizeof(double) * (c->N + 1));
+    make_edges(c, e);
+    long viol = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : viol)
+    for (int cell = 0; cell < C; ++cell) {
+        double* gn = g + (size_t)cell * P;
+        double* y1 = malloc(sizeof(double) * P);
+        double* y2 = malloc(sizeof(double) * P);
+        double* L = malloc(sizeof(double) * P);
+        double* Y = malloc(sizeof(double) * no);
+        double* fe = malloc(sizeof(double) * (c->N + 1));
+        double ks = kscale ? kscale[cell] : 1.0;
+        double vf = vfrag ? vfrag[cell] : vfrag_default;
+        viol += limit_cell(c->N, c->k, gn);
+        for (int n = 0; n < n_sub; ++n) {
+            double rem = t_end - t[cell];
+            if (!(rem > 0.0)) break;
             raw_flux_cell(c, e, gn, ks, vf, nlev, lev, Y, fe);
-            assemble_L(c, e, Y, L);
-            for (int t = 0; t < P; ++t) y1[t] = gn[t] + dt * L[t];
-            viol += limit_cell(c->N, c->k, y1);
-
-            raw_flux_cell(c, e, y1, ks, vf, nlev, lev, Y, fe);
-            assemble_L(c, e, Y, L);
-            for (int t = 0; t < P; ++t) y2[t] = 0.75 * gn[t] + 0.25 * (y1[t] + dt * L[t]);
-            viol += limit_cell(c->N, c->k, y2);
-
-            raw_flux_cell(c, e, y2, ks, vf, nlev, lev, Y, fe);
-            assemble_L(c, e, Y, L);
-            for (int t = 0; t < P; ++t) gn[t] = gn[t] / 3.0 + 2.0 / 3.0 * (y2[t] + dt * L[t]);
-            viol += limit_cell(c->N, c->k, gn);
+            double B = INFINITY;
+            for (int j = 0; j < c->N; ++j) {
+                double d = fe[j + 1] - fe[j], gj = gn[j * (c->k + 1)];
+                if (d > 0.0 && gj > 0.0) {
+                    double b = (e[j + 1] - e[j]) * gj / d;
+                    if (b < B) B = b;
+                }
+            }
+            double dt = dt_max < rem ? dt_max : rem;
+            if (cfl * B < dt) dt = cfl * B;
+            if (!(dt > 0.0)) break;
+            viol += rk3_cell(c, e, gn, ks, vf, nlev, lev, dt, y1, y2, L, Y, fe);
+            t[cell] = (dt == rem) ? t_end : t[cell] + dt;
         }
         free(y1); free(y2); free(L); free(Y); free(fe);
     }

@@ -82,6 +82,9 @@ def _load():
         lib.oracle_rk.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp,
                                   ctypes.c_double, ctypes.c_int]
         lib.oracle_rk.restype = ctypes.c_long
+        lib.oracle_rk_adaptive.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+        lib.oracle_rk_adaptive.restype = ctypes.c_long
         lib.oracle_cfl_dt.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
         lib.oracle_cfl_dt.restype = ctypes.c_double
         lib.oracle_inner.argtypes = [cp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp, dp]
@@ -211,6 +214,24 @@ def rk(cfg: Config, g, dt: float, n_steps: int, kscale=None, vfrag=None):
                           float(dt), int(n_steps))
     assert v >= 0
     return g, int(v)
+
+
+def rk_adaptive(cfg: Config, g, cfl: float, dt_max: float, t_end: float, n_sub: int, t=None,
+                kscale=None, vfrag=None):
+    """n_sub sub-steps of SSP-RK3 with a per-cell step under the CFL bound (Eq. dt):
+    dt_c = min(dt_max, t_end - t_c, cfl * B_c), B_c the bound over the bins losing
+    mass at the sub-step's start.  Returns (g, t, violations); t (per cell, default
+    zeros) is the time each cell has reached."""
+    g, C, ks, vf = _cells(cfg, g, kscale, vfrag)
+    g = g.copy()
+    t = np.zeros(C) if t is None else np.ascontiguousarray(t, dtype=np.float64).copy()
+    assert t.shape == (C,)
+    nl, lv = cfg._levels()
+    c = cfg._c()
+    v = _load().oracle_rk_adaptive(ctypes.byref(c), C, _dp(g), _dp(ks), _dp(vf), float(cfg.vfrag), nl, _dp(lv),
+                                   float(cfl), float(dt_max), float(t_end), int(n_sub), _dp(t))
+    assert v >= 0
+    return g, t, int(v)
 
 
 def inner(cfg: Config, x: float, u: float, v: float):

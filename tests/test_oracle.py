@@ -11,6 +11,8 @@ import pytest
 from numpy.polynomial import legendre as npleg
 from scipy import integrate
 
+from paper_2607_13740_amd import workloads as W
+
 
 def _cfg(O, **kw):
     return O.Config(**kw)
@@ -554,3 +556,86 @@ def test_projection_reproduces_polynomials(oracle):
     assert np.allclose(O.evaluate(cfg, g, xs), 2.0 + 0.3 * xs - 0.01 * xs ** 3, rtol=1e-12)
     assert O.moments(cfg, g, 1)[0] == pytest.approx(
         integrate.quad(lambda x: 2.0 + 0.3 * x - 0.01 * x ** 3, e[0], e[-1], points=list(e[1:-1]))[0], rel=1e-12)
+
+
+# --------------------------------------------------------------- per-cell time steps (Eq. dt)
+def test_adaptive_step_is_the_largest_positive_euler_step(oracle):
+    """Eq. dt: the bound is the largest step for which a forward-Euler stage keeps
+    every bin average nonnegative.  With cfl = 1 the selected step empties one bin
+    to round-off and leaves the others nonnegative; cfl = 1/2 halves it exactly."""
+    O = oracle
+    cfg = _lognormal_cfg(O)
+    g, _ = O.limit(cfg, O.project(cfg, _ln_g0))
+    _, t1, v = O.rk_adaptive(cfg, g, 1.0, 1e30, 1e30, 1)
+    assert v == 0 and 0.0 < t1[0] < np.inf
+    _, L, _ = O.rhs(cfg, g)
+    avg = g.reshape(cfg.N, cfg.k + 1)[:, 0]
+    after = avg + t1[0] * L.reshape(cfg.N, cfg.k + 1)[:, 0]
+    assert (after / avg).min() >= -1e-12
+    assert (after / avg).min() <= 1e-9
+    # a longer step would drive that bin negative
+    longer = avg + 1.001 * t1[0] * L.reshape(cfg.N, cfg.k + 1)[:, 0]
+    assert (longer / avg).min() < -1e-4
+    _, t2, _ = O.rk_adaptive(cfg, g, 0.5, 1e30, 1e30, 1)
+    assert t2[0] == 0.5 * t1[0]
+    # only bins that lose mass enter the bound: the cell's bound equals the
+    # separately computed one of the whole batch's CFL check
+    assert t1[0] == pytest.approx(O.cfl_dt(cfg, g), rel=1e-14)
+
+
+def test_adaptive_step_reduces_to_fixed_step(oracle):
+    """When dt_max is below the CFL bound in every sub-step the sub-steps are fixed
+    SSP-RK3 steps of dt_max (bit for bit) and the clock adds dt_max each time."""
+    O = oracle
+    cfg = _lognormal_cfg(O)
+    g, _ = O.limit(cfg, O.project(cfg, _ln_g0))
+    dt = 0.25 * O.cfl_dt(cfg, g)
+    ga, ta, va = O.rk_adaptive(cfg, g, 1.0, dt, 1e30, 20)
+    gf, vf = O.rk(cfg, g, dt, 20)
+    assert va == vf == 0
+    assert np.array_equal(ga, gf)
+    t = 0.0
+    for _ in range(20):
+        t += dt
+    assert ta[0] == t
+
+
+def test_adaptive_cells_stop_at_end_time(oracle):
+    """Cells with different rates (kernel scales) take different numbers of
+    sub-steps; each reaches t_end exactly and is then left as it is (the start
+    limiter of a later call aside); the conservative flux keeps every cell's mass."""
+    O = oracle
+    cfg = _lognormal_cfg(O)
+    g0, _ = O.limit(cfg, O.project(cfg, _ln_g0))
+    ks = np.array([0.2, 1.0, 5.0, 25.0])
+    g = np.tile(g0, (4, 1))
+    t_end = 3.0 * O.cfl_dt(cfg, g0)
+    # (a tenth of the bound: the bound of the sub-step's start state does not cover
+    # its later stages, and at half the bound the fastest cell ends with a few
+    # negative averages)
+    gs, ts, v = O.rk_adaptive(cfg, g, 0.1, 1e30, t_end, 6, kscale=ks)
+    # the slow cell is done after 6 sub-steps, the fast ones are not
+    assert ts[0] == t_end and ts[-1] < t_end
+    gl, tl, v = O.rk_adaptive(cfg, g, 0.1, 1e30, t_end, 400, kscale=ks)
+    assert v == 0 and np.all(tl == t_end)
+    assert np.array_equal(gl[0], gs[0])
+    again, ta, _ = O.rk_adaptive(cfg, gl, 0.1, 1e30, t_end, 5, t=tl, kscale=ks)
+    lim, _ = O.limit(cfg, gl)
+    assert np.array_equal(again, lim) and np.all(ta == t_end)
+    h = np.diff(O.edges(cfg))
+    m0 = (h * g0.reshape(cfg.N, -1)[:, 0]).sum()
+    m1 = (h * gl.reshape(4, cfg.N, -1)[:, :, 0]).sum(axis=1)
+    assert np.max(np.abs(m1 - m0)) / m0 < 1e-13
+
+
+def test_adaptive_steps_reach_the_closed_form(oracle):
+    """The C1 problem (constant kernel, g0 = x e^{-x}) advanced to tau = 1 with
+    per-cell steps lands on the closed form to the discretisation error, as the
+    fixed steps do."""
+    O = oracle
+    w = W.WORKLOADS["c1_const"]
+    cfg = _cfg(O, N=w.bins, k=w.order, xmin=w.x_min, xmax=w.x_max, kernel=w.kernel)
+    g0 = O.project(cfg, W.xexp_density)
+    g1, t1, v = O.rk_adaptive(cfg, g0, 0.5, 0.05, 1.0, 100)
+    assert v == 0 and t1[0] == 1.0
+    assert O.error_c(cfg, g1, lambda x: O.g_const(x, 1.0)) < 0.05

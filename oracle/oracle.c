@@ -637,18 +637,22 @@ long oracle_rk(const ocfg* c, int C, double* g, const double* kscale, const doub
  * toward the common end time t_end.  t is [C], the time each cell has reached
  * (in/out).  In every sub-step a cell with t < t_end takes
  *     dt = min(dt_max, t_end - t, cfl * B),
- *     B  = min over bins with F(e_{j+1}) > F(e_j) and g_j^0 > 0 of h_j g_j^0 / (F(e_{j+1}) - F(e_j)),
+ *     B  = min over bins with F(e_{j+1}) - F(e_j) > floor * max_i |F(e_i)| and
+ *          g_j^0 > 0 of h_j g_j^0 / (F(e_{j+1}) - F(e_j)),
  * B from the fluxes of its state at the start of the sub-step; t becomes t_end when
  * dt = t_end - t, else t + dt.  A cell with t >= t_end (or dt = 0) is left as it
  * is.  Only a bin that loses mass can turn negative in a forward-Euler stage, and
  * a bin with a zero average cannot be kept positive by any step, so both are left
- * out of B.  The limiter acts on the start state and after every stage, as in
- * oracle_rk. */
+ * out of B; floor = 0 is the bound as printed, floor > 0 also leaves out bins whose
+ * net outflow is below that fraction of the cell's largest edge flux (their
+ * positivity is left to the limiter).  The limiter acts on the start state and
+ * after every stage, as in oracle_rk. */
 long oracle_rk_adaptive(const ocfg* c, int C, double* g, const double* kscale, const double* vfrag,
                         double vfrag_default, int nlev, const double* lev, double cfl, double dt_max,
-                        double t_end, int n_sub, double* t)
+                        double floor, double t_end, int n_sub, double* t)
 {
-    if (check(c) || c->k > 4 || C < 0 || n_sub < 0 || !(cfl > 0.0) || !(dt_max > 0.0)) return -1;
+    if (check(c) || c->k > 4 || C < 0 || n_sub < 0 || !(cfl > 0.0) || !(dt_max > 0.0) || !(floor >= 0.0))
+        return -1;
     int P = c->N * (c->k + 1), no = n_out(c);
     double* e = malloc(sizeof(double) * (c->N + 1));
     make_edges(c, e);
@@ -668,10 +672,13 @@ long oracle_rk_adaptive(const ocfg* c, int C, double* g, const double* kscale, c
             double rem = t_end - t[cell];
             if (!(rem > 0.0)) break;
             raw_flux_cell(c, e, gn, ks, vf, nlev, lev, Y, fe);
+            double fmax = 0.0;
+            for (int j = 0; j <= c->N; ++j)
+                if (fabs(fe[j]) > fmax) fmax = fabs(fe[j]);
             double B = INFINITY;
             for (int j = 0; j < c->N; ++j) {
                 double d = fe[j + 1] - fe[j], gj = gn[j * (c->k + 1)];
-                if (d > 0.0 && gj > 0.0) {
+                if (d > 0.0 && d > floor * fmax && gj > 0.0) {
                     double b = (e[j + 1] - e[j]) * gj / d;
                     if (b < B) B = b;
                 }

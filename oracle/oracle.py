@@ -83,7 +83,8 @@ def _load():
                                   ctypes.c_double, ctypes.c_int]
         lib.oracle_rk.restype = ctypes.c_long
         lib.oracle_rk_adaptive.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp,
-                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_int, dp]
         lib.oracle_rk_adaptive.restype = ctypes.c_long
         lib.oracle_cfl_dt.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp]
         lib.oracle_cfl_dt.restype = ctypes.c_double
@@ -217,11 +218,12 @@ def rk(cfg: Config, g, dt: float, n_steps: int, kscale=None, vfrag=None):
 
 
 def rk_adaptive(cfg: Config, g, cfl: float, dt_max: float, t_end: float, n_sub: int, t=None,
-                kscale=None, vfrag=None):
+                kscale=None, vfrag=None, floor: float = 0.0):
     """n_sub sub-steps of SSP-RK3 with a per-cell step under the CFL bound (Eq. dt):
     dt_c = min(dt_max, t_end - t_c, cfl * B_c), B_c the bound over the bins losing
-    mass at the sub-step's start.  Returns (g, t, violations); t (per cell, default
-    zeros) is the time each cell has reached."""
+    mass at the sub-step's start (more than floor times the cell's largest edge
+    flux).  Returns (g, t, violations); t (per cell, default zeros) is the time each
+    cell has reached."""
     g, C, ks, vf = _cells(cfg, g, kscale, vfrag)
     g = g.copy()
     t = np.zeros(C) if t is None else np.ascontiguousarray(t, dtype=np.float64).copy()
@@ -229,7 +231,7 @@ def rk_adaptive(cfg: Config, g, cfl: float, dt_max: float, t_end: float, n_sub: 
     nl, lv = cfg._levels()
     c = cfg._c()
     v = _load().oracle_rk_adaptive(ctypes.byref(c), C, _dp(g), _dp(ks), _dp(vf), float(cfg.vfrag), nl, _dp(lv),
-                                   float(cfl), float(dt_max), float(t_end), int(n_sub), _dp(t))
+                                   float(cfl), float(dt_max), float(floor), float(t_end), int(n_sub), _dp(t))
     assert v >= 0
     return g, t, int(v)
 

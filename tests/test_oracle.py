@@ -639,3 +639,31 @@ def test_adaptive_steps_reach_the_closed_form(oracle):
     g1, t1, v = O.rk_adaptive(cfg, g0, 0.5, 0.05, 1.0, 100)
     assert v == 0 and t1[0] == 1.0
     assert O.error_c(cfg, g1, lambda x: O.g_const(x, 1.0)) < 0.05
+
+
+def test_adaptive_step_flux_floor(oracle):
+    """floor > 0 leaves out of the bound the bins whose net outflow is at most that
+    fraction of the cell's largest edge flux: the step is then the largest
+    forward-Euler step that keeps the remaining bins nonnegative, never shorter
+    than the printed bound's; a floor above every outflow gives dt_max."""
+    O = oracle
+    cfg = _lognormal_cfg(O)
+    g, _ = O.limit(cfg, O.project(cfg, _ln_g0))
+    _, _, Fe = O.rhs(cfg, g)
+    d = np.diff(Fe[0])
+    avg = g.reshape(cfg.N, cfg.k + 1)[:, 0]
+    _, L, _ = O.rhs(cfg, g)
+    L0 = L.reshape(cfg.N, cfg.k + 1)[:, 0]
+    _, t0, _ = O.rk_adaptive(cfg, g, 1.0, 1e30, 1e30, 1)
+    # a floor between the two largest outflows' ratios: the binding bin changes
+    out = np.sort(d[d > 0])
+    eta = 0.5 * (out[-1] + out[-2]) / np.abs(Fe[0]).max()
+    _, t1, _ = O.rk_adaptive(cfg, g, 1.0, 1e30, 1e30, 1, floor=eta)
+    keep = d > eta * np.abs(Fe[0]).max()
+    assert keep.sum() == 1 and t1[0] >= t0[0]
+    after = (avg + t1[0] * L0) / avg
+    assert after[keep].min() == pytest.approx(0.0, abs=1e-12)
+    dt = 10.0 * t0[0]
+    ga, ta, va = O.rk_adaptive(cfg, g, 1.0, dt, 1e30, 1, floor=2.0)
+    gf, vf = O.rk(cfg, g, dt, 1)
+    assert np.array_equal(ga, gf) and ta[0] == dt and va == vf

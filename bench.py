@@ -168,6 +168,34 @@ def cpu_baseline(w, params, seconds):
             "cpu_model": model, "host_cpus": os.cpu_count()}
 
 
+def adaptive_bench(plan, g0, ks, w, n=10):
+    """Per-cell steps under the CFL bound (gd_rk_advance, launches issued one by one)
+    on the same plan and inputs: ms per sub-step and the adaptive stage kernel's
+    average duration, beside the eager fixed step (graph off)."""
+    import torch
+    g = g0.clone()
+    t = torch.zeros(plan.n_cells, dtype=torch.float64, device=g.device)
+    kw = dict(kscale=ks, flux_floor=1e-4 if plan.precision == "mixed" else 0.0)
+    plan.rk_advance(g, t, 1e30, 0.1, w.dt, 2, **kw)   # warm-up (allocates the step array)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.rk_advance(g, t, 1e30, 0.1, w.dt, n, **kw)
+    torch.cuda.synchronize()
+    ms_adapt = (time.perf_counter() - t0) * 1e3 / n
+    plan.timing(True)
+    plan.rk_advance(g, t, 1e30, 0.1, w.dt, 4, **kw)
+    sms, sl = plan.stage_time()     # 12 adaptive stages and the start limiter
+    plan.timing(False)
+    plan.use_graph(False)
+    t0 = time.perf_counter()
+    plan.rk_step(g, w.dt, n, kscale=ks)
+    torch.cuda.synchronize()
+    ms_eager = (time.perf_counter() - t0) * 1e3 / n
+    plan.use_graph(True)
+    return {"ms_per_substep": ms_adapt, "eager_fixed_step_ms": ms_eager, "stage_kernel_ms": sms / max(1, sl),
+            "cell_evals_per_s": 3.0 * plan.n_cells / (ms_adapt * 1e-3), "cfl": 0.1, "flux_floor": kw["flux_floor"]}
+
+
 def measured_traffic(variant):
     """HBM bytes of one split-FP16 contraction launch in the given work-item variant,
     from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE measurement scaled by the
@@ -330,6 +358,9 @@ def main():
                 drift = max(drift, float(((gm.sum(1) - g0m.sum(1)).abs() / g0m.sum(1)).max()))
             voff += n * P
         res[prec]["mass_drift"] = drift
+        res[prec]["adaptive"] = adaptive_bench(plan, g0, ks, w)
+        print(f"# {prec} per-cell steps: {res[prec]['adaptive']['ms_per_substep']:.3f} ms/sub-step "
+              f"(eager fixed step {res[prec]['adaptive']['eager_fixed_step_ms']:.3f})", file=sys.stderr, flush=True)
 
     # accuracy of the split contraction against the FP64 contraction on the full batch
     acc = {}
@@ -387,6 +418,7 @@ def main():
         "tensor_init_s": t_init,
         "mass_drift_mixed": mixed["mass_drift"],
         "accuracy_vs_fp64_gpu": acc,
+        "per_cell_steps": mixed["adaptive"],
     }
     if "fp64" in res:
         f = res["fp64"]
@@ -395,7 +427,8 @@ def main():
                            "step_ms_single_replays": f["step_ms_dist"],
                            "achieved_tflops": flops_launch / (f["kernel_ms"] * 1e-3) / 1e12,
                            "variant": f["variant"],
-                           "peak_tflops": PEAK_F64_TFLOPS, "mass_drift": f["mass_drift"]}
+                           "peak_tflops": PEAK_F64_TFLOPS, "mass_drift": f["mass_drift"],
+                           "per_cell_steps": f["adaptive"]}
         out["speedup_mixed_vs_fp64"] = cell_evals / f_evals
     if not args.no_adjoint:
         out["adjoint"] = adjoint_bench()

@@ -189,6 +189,42 @@ int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, doubl
 int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_steps, long long* violations);
 
 /*
+ * gd_rk_advance -- per-cell time steps under the CFL bound of Eq. dt (Sec. 3.2):
+ * n_substeps sub-steps of SSP-RK3 (Eq. RK3, the limiter on the start state and
+ * after every stage, as gd_rk_step), every cell with its own step, toward the
+ * common end time t_end.  In each sub-step a cell c with t[c] < t_end takes
+ *     dt_c = min(dt_max, t_end - t[c], cfl * B_c),
+ *     B_c  = min over bins j with F(e_{j+1}) - F(e_j) > flux_floor * max_i |F(e_i)|
+ *            and g_j^0 > 0 of h_j g_j^0 / (F(e_{j+1}) - F(e_j)),
+ * with the fluxes of its state at the start of the sub-step (only a bin that loses
+ * mass can turn negative in a forward-Euler stage; a bin with zero average cannot
+ * be helped by any step).  flux_floor = 0 is the bound as printed; a positive floor
+ * leaves out near-empty bins whose outflow is below that fraction of the cell's
+ * largest edge flux (their positivity is left to the limiter).  With split-FP16
+ * plans the fluxes carry an absolute error of ~1e-7 of the largest one, so such
+ * outflows are rounding noise there: use a floor well above it (e.g. 1e-4).
+ * Then t[c] = t_end if dt_c = t_end - t[c], else
+ * t[c] + dt_c.  A cell with t[c] >= t_end (or a zero bound) keeps its state bit for
+ * bit during the call (the start limiter aside).  The bound covers the first stage
+ * of a sub-step: cfl well below 1 keeps the later stages positive too (the
+ * violation count reports when it does not).
+ *  g          : device, state layout, in place.
+ *  kscale     : device [n_cells] or NULL.
+ *  t          : device [n_cells] (caller's cell order, groups concatenated), the
+ *               time each cell has reached: in/out.
+ *  t_end      : finite end time; cfl > 0, dt_max > 0 and flux_floor >= 0 finite
+ *               (else GD_EINVAL).
+ *  violations : host pointer or NULL, as in gd_rk_step.
+ *  unfinished : host pointer or NULL; if non-NULL, the number of cells with
+ *               t[c] < t_end after the call.
+ * Either host pointer makes the call synchronise the stream.  The launches are
+ * issued one by one (no graph).  The first call on a plan allocates a per-cell step
+ * array (synchronous).
+ */
+int gd_rk_advance(gd_plan* plan, double* g, const double* kscale, double* t, double t_end, double cfl,
+                  double dt_max, double flux_floor, int n_substeps, long long* violations, long long* unfinished);
+
+/*
  * Reverse mode (the adjoint of gd_rk_step), FP64 whatever the plan's precision.
  *
  * gd_rk_forward -- gd_rk_step (same steps, limiter placement and results) that also

@@ -569,6 +569,8 @@ struct gd_plan {
     double* y1 = nullptr;
     double* y2 = nullptr;
     unsigned long long* viol = nullptr;
+    double* dtc = nullptr;                  // per-cell steps of an adaptive sub-step (first adaptive call)
+    unsigned long long* below = nullptr;    // count of cells short of the end time
     long long n_bins = 0;                   // sum over groups of cells * bins
     std::vector<GroupDev> gdev;             // host copy of groups_dev
     // reverse mode, set up by the first adjoint call
@@ -930,10 +932,26 @@ static int timer_begin(gd_plan* pl, KernelTimer& T, hipStream_t s, hipEvent_t* e
     return GD_OK;
 }
 
+// per-cell steps of an adaptive sub-step (see StageArgs)
+struct AdaptArgs {
+    double cfl, t_end, floor;
+    double* t;
+    double* dtc;
+};
+
 static int stage(gd_plan* pl, hipStream_t s, int mode, int limit, int split, const double* kscale,
-                 const double* gn, const double* gs, double* out, double dt, double* raw, double* gamma = nullptr)
+                 const double* gn, const double* gs, double* out, double dt, double* raw, double* gamma = nullptr,
+                 const AdaptArgs* ad = nullptr)
 {
     StageArgs a{};
+    if (ad) {
+        a.adapt = 1;
+        a.cfl = ad->cfl;
+        a.t_end = ad->t_end;
+        a.floor = ad->floor;
+        a.tcell = ad->t;
+        a.dtc = ad->dtc;
+    }
     a.gamma = gamma;
     a.groups = pl->groups_dev;
     a.n_groups = int(pl->groups.size());
@@ -1045,6 +1063,51 @@ extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double d
         HIP_TRY(hipMemcpyAsync(&v, pl->viol, sizeof(v), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         *violations = (long long)v;
+    }
+    return GD_OK;
+}
+
+// Per-cell steps under the CFL bound (Eq. dt): n_sub sub-steps of SSP-RK3, each cell
+// with its own step, in the same six launches per sub-step as gd_rk_step (issued one
+// by one: the steps live on the device).
+extern "C" int gd_rk_advance(gd_plan* pl, double* g, const double* kscale, double* t, double t_end, double cfl,
+                             double dt_max, double flux_floor, int n_substeps, long long* violations,
+                             long long* unfinished)
+{
+    if (!pl || !g || !t || n_substeps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!std::isfinite(t_end)) return fail(GD_EINVAL, "t_end must be finite");
+    if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(GD_EINVAL, "cfl must be positive and finite");
+    if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return fail(GD_EINVAL, "dt_max must be positive and finite");
+    if (!(flux_floor >= 0.0) || !std::isfinite(flux_floor)) return fail(GD_EINVAL, "flux_floor must be >= 0 and finite");
+    int rc;
+    hipStream_t s = pl->stream;
+    if (!pl->dtc) {
+        if ((rc = dalloc(pl, &pl->dtc, size_t(pl->n_cells)))) return rc;
+        if ((rc = dalloc(pl, &pl->below, 1))) return rc;
+    }
+    const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
+    if ((rc = launch_fill_u64(pl->viol, 1, s))) return rc;
+    if ((rc = stage(pl, s, -1, 1, split, kscale, nullptr, g, nullptr, dt_max, nullptr))) return rc;
+    const AdaptArgs ad{cfl, t_end, flux_floor, t, pl->dtc};
+    for (int n = 0; n < n_substeps; ++n) {
+        if ((rc = contract(pl, s, g))) return rc;
+        if ((rc = stage(pl, s, 1, 1, split, kscale, g, g, pl->y1, dt_max, nullptr, nullptr, &ad))) return rc;
+        if ((rc = contract(pl, s, pl->y1))) return rc;
+        if ((rc = stage(pl, s, 2, 1, split, kscale, g, pl->y1, pl->y2, dt_max, nullptr, nullptr, &ad))) return rc;
+        if ((rc = contract(pl, s, pl->y2))) return rc;
+        if ((rc = stage(pl, s, 3, 1, split, kscale, g, pl->y2, g, dt_max, nullptr, nullptr, &ad))) return rc;
+    }
+    if (unfinished) {
+        if ((rc = launch_fill_u64(pl->below, 1, s))) return rc;
+        if ((rc = launch_count_below(t, pl->n_cells, t_end, pl->below, s))) return rc;
+    }
+    if (violations || unfinished) {
+        unsigned long long v[2] = {0, 0};
+        HIP_TRY(hipMemcpyAsync(&v[0], pl->viol, sizeof(v[0]), hipMemcpyDeviceToHost, s));
+        if (unfinished) HIP_TRY(hipMemcpyAsync(&v[1], pl->below, sizeof(v[1]), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (violations) *violations = (long long)v[0];
+        if (unfinished) *unfinished = (long long)v[1];
     }
     return GD_OK;
 }

@@ -163,7 +163,15 @@ struct StageArgs {
     double* out;               // new state (or L); mode -1 with limit: gs itself
     double* raw;               // optional FP64 raw output [cells][n_out]
     unsigned long long* viol;
-    double dt;
+    double dt;                 // the step; with adapt set, the largest step dt_max
+    // per-cell steps under the CFL bound (adapt = 1): mode 1 sets dtc[cell] =
+    // min(dt, t_end - tcell[cell], cfl * bound), modes 2 and 3 read it, mode 3
+    // advances tcell; a cell with dtc = 0 keeps its state (cells in caller order over
+    // all groups, GroupDev::cell0 + cell)
+    int adapt;
+    double cfl, t_end, floor;  // floor: outflows <= floor * (largest edge flux) do not bound
+    double* tcell;
+    double* dtc;
 };
 
 // Kernels of the reverse step (see adjoint.hip).
@@ -198,6 +206,7 @@ struct AdjStageArgs {
 
 // ------------------------------------------------------------------ launchers
 int launch_stage(const StageArgs& a, hipStream_t s);
+int launch_count_below(const double* t, long long n, double t_end, unsigned long long* count, hipStream_t s);
 int launch_fill_u64(unsigned long long* p, int n, hipStream_t s);
 int launch_project(const double* samples, const double* wP, double* coef, int C, int N, int k, hipStream_t s);
 // ksmax: largest KS of the plan; waves: 4 or 8 per workgroup

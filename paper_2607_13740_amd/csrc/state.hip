@@ -77,10 +77,20 @@ __global__ __launch_bounds__(256) void k_project(const double* samples, const do
 // exponent of every slot, so that the FP16 fragments and FP32 weights are written
 // coalesced in phase 2.  Small workgroups with LDS sized to the plan's largest P keep
 // most tiles of a launch resident at once.
+// With ADAPT the stage also takes each cell's own step under the CFL bound of Eq. dt:
+// before the RK combination of the first stage, the workgroup forms per slot the
+// minimum of h_j g_j^0 / (F(e_{j+1}) - F(e_j)) over the bins that lose mass and hold
+// a positive average (only those can be driven negative by a forward-Euler stage,
+// and none can be helped by a step when the average is zero), then
+// dt = min(dt_max, t_end - t, cfl * bound).  With a positive flux floor, a first
+// pass takes the slot's largest edge flux and bins whose net outflow is at most
+// floor times it are left out (with split-FP16 fluxes such outflows can be rounding
+// noise).  A cell with dt = 0 (done, or stuck at a zero bound) keeps its state bit
+// for bit: no combination, no limiter.
 constexpr int kStageMaxP = 192;
 constexpr int kStageThreads = 256;
 
-template <int PMAX>
+template <int PMAX, bool ADAPT>
 __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
 {
     __shared__ double st[32 * (PMAX + 1)];
@@ -117,6 +127,85 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
         if (a.split) smax[tid] = INT_MIN;
     }
     __syncthreads();
+
+    // per-slot step of this sub-step (ADAPT), or the common dt
+    __shared__ double sdt[32];
+    if constexpr (ADAPT) {
+        const int nthr = blockDim.x;
+        if (a.mode == 1) {
+            // nonnegative doubles order as their bit patterns
+            __shared__ unsigned long long sbnd[32], sfmax[32];
+            if (tid < 32) {
+                sbnd[tid] = 0x7ff0000000000000ull;   // +infinity
+                sfmax[tid] = 0ull;
+            }
+            __syncthreads();
+            auto edges = [&](int t, int& sl, int& j, int& c, double& Fl, double& Fr) {
+                sl = t / N;
+                j = t - sl * N;
+                c = scell[sl];
+                if (c < 0) return;
+                const int s = tile * 32 + sl;
+                auto flux = [&](int q) -> double {
+                    if (Yf) return (double)Yf[(size_t)s * ystride + q] * rowscale[q] * sfac[sl];
+                    return Yd[(size_t)s * ystride + q] * sfac[sl];
+                };
+                Fl = (j == 0) ? 0.0 : flux(j * K1 - 1);
+                Fr = (j + 1 < N || !conservative) ? flux((j + 1) * K1 - 1) : 0.0;
+            };
+            if (a.floor > 0.0) {
+                for (int t = tid; t < 32 * N; t += nthr) {
+                    int sl, j, c;
+                    double Fl = 0.0, Fr = 0.0;
+                    edges(t, sl, j, c, Fl, Fr);
+                    if (c < 0) continue;
+                    const double m = fmax(fabs(Fl), fabs(Fr));
+                    if (m > 0.0) atomicMax(&sfmax[sl], (unsigned long long)__double_as_longlong(m));
+                }
+                __syncthreads();
+            }
+            for (int t = tid; t < 32 * N; t += nthr) {
+                int sl, j, c;
+                double Fl = 0.0, Fr = 0.0;
+                edges(t, sl, j, c, Fl, Fr);
+                if (c < 0) continue;
+                const double d = Fr - Fl, gj = gs[(size_t)c * P + j * K1];
+                const double fl = a.floor * __longlong_as_double((long long)sfmax[sl]);
+                if (d > 0.0 && d > fl && gj > 0.0) {
+                    const double b = h[j] * gj / d;
+                    if (b == b) atomicMin(&sbnd[sl], (unsigned long long)__double_as_longlong(b));
+                }
+            }
+            __syncthreads();
+            if (tid < 32) {
+                const int c = scell[tid];
+                double dt = 0.0;
+                if (c >= 0) {
+                    const double rem = a.t_end - a.tcell[G->cell0 + c];
+                    if (rem > 0.0) {
+                        dt = a.dt < rem ? a.dt : rem;
+                        const double cb = a.cfl * __longlong_as_double((long long)sbnd[tid]);
+                        if (cb < dt) dt = cb;
+                        if (!(dt > 0.0)) dt = 0.0;
+                    }
+                    a.dtc[G->cell0 + c] = dt;
+                }
+                sdt[tid] = dt;
+            }
+        } else if (tid < 32) {
+            const int c = scell[tid];
+            sdt[tid] = (c >= 0) ? a.dtc[G->cell0 + c] : 0.0;
+        }
+        __syncthreads();
+        if (a.mode == 3 && tid < 32) {
+            const int c = scell[tid];
+            const double dt = sdt[tid];
+            if (c >= 0 && dt > 0.0) {
+                const double tc = a.tcell[G->cell0 + c], rem = a.t_end - tc;
+                a.tcell[G->cell0 + c] = (dt == rem) ? a.t_end : tc + dt;
+            }
+        }
+    }
 
     // 16-byte moves need an even order + 1 and 16-byte aligned bin starts
     auto al16 = [](const void* p) { return p == nullptr || ((uintptr_t)p & 15) == 0; };
@@ -167,6 +256,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                 double xs[kMaxOrder + 1] = {}, xn[kMaxOrder + 1] = {};
                 if (a.mode >= 1) load(gs, xs);
                 if (a.mode >= 2) load(gn, xn);
+                const double dt = ADAPT ? sdt[sl] : a.dt;
                 for (int i = 0; i < K1; ++i) {
                     const double V = (i == 0) ? 0.0 : pos(j * K1 + i - 1);
                     if (raw && i > 0) raw[(size_t)c * n_out + vbase + j * k + i - 1] = V;
@@ -174,13 +264,15 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                     const double L = (2.0 * i + 1.0) * ihj * (V - Fr + sgn * Fl);
                     switch (a.mode) {
                     case 0: v[i] = L; break;
-                    case 1: v[i] = xs[i] + a.dt * L; break;
-                    case 2: v[i] = 0.75 * xn[i] + 0.25 * (xs[i] + a.dt * L); break;
-                    default: v[i] = (1.0 / 3.0) * xn[i] + (2.0 / 3.0) * (xs[i] + a.dt * L); break;
+                    case 1: v[i] = xs[i] + dt * L; break;
+                    case 2: v[i] = 0.75 * xn[i] + 0.25 * (xs[i] + dt * L); break;
+                    default: v[i] = (1.0 / 3.0) * xn[i] + (2.0 / 3.0) * (xs[i] + dt * L); break;
                     }
                 }
+                if (ADAPT && !(dt > 0.0))
+                    for (int i = 0; i < K1; ++i) v[i] = (a.mode >= 2) ? xn[i] : xs[i];
             }
-            if (a.limit) {
+            if (a.limit && !(ADAPT && a.mode >= 1 && !(sdt[sl] > 0.0))) {
                 double gam;
                 viol += limit_bin(k, v, gam);
                 if (a.gamma) a.gamma[G->gam0 + (size_t)c * N + j] = gam;
@@ -252,8 +344,32 @@ int launch_stage(const StageArgs& a, hipStream_t s)
     if (a.n_tiles == 0) return GD_OK;
     if (a.max_p > kStageMaxP) return fail(GD_EUNSUPPORTED, "P too large for the stage kernel");
     // LDS sized to the plan's largest P (more resident workgroups for small P)
-    if (a.max_p <= 96) hipLaunchKernelGGL(k_stage<96>, dim3(a.n_tiles), dim3(kStageThreads), 0, s, a);
-    else hipLaunchKernelGGL(k_stage<kStageMaxP>, dim3(a.n_tiles), dim3(kStageThreads), 0, s, a);
+    const dim3 grid(a.n_tiles), block(kStageThreads);
+    if (a.adapt) {
+        if (a.mode < 1 || !a.tcell || !a.dtc) return fail(GD_EINVAL, "adaptive stage needs an RK mode and time arrays");
+        if (a.max_p <= 96) hipLaunchKernelGGL((k_stage<96, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_stage<kStageMaxP, true>), grid, block, 0, s, a);
+    } else {
+        if (a.max_p <= 96) hipLaunchKernelGGL((k_stage<96, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_stage<kStageMaxP, false>), grid, block, 0, s, a);
+    }
+    HIP_TRY(hipGetLastError());
+    return GD_OK;
+}
+
+// number of entries below t_end (the cells an adaptive call has not brought there)
+__global__ void k_count_below(const double* t, long long n, double t_end, unsigned long long* count)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool below = i < n && !(t[i] >= t_end);
+    const unsigned long long m = __ballot(below);
+    if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, (unsigned long long)__popcll(m));
+}
+
+int launch_count_below(const double* t, long long n, double t_end, unsigned long long* count, hipStream_t s)
+{
+    if (n <= 0) return GD_OK;
+    hipLaunchKernelGGL(k_count_below, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t, n, t_end, count);
     HIP_TRY(hipGetLastError());
     return GD_OK;
 }

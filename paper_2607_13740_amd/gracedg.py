@@ -83,6 +83,9 @@ def lib():
             "gd_collision_rhs": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
             "gd_rk_step": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+            "gd_rk_advance": ([_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_longlong),
+                               ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_projection_points": ([_VP, _DP], ctypes.c_int),
             "gd_project": ([_VP, ctypes.c_int, _VP, _VP, _VP], ctypes.c_int),
             "gd_plan_timing": ([_VP, ctypes.c_int], ctypes.c_int),
@@ -203,6 +206,7 @@ class Plan:
             tensors, cells = [tensors], [cells]
         self.tensors = list(tensors)
         self.cells = [int(c) for c in cells]
+        self.precision = precision
         arr_t = (_VP * len(self.tensors))(*[t.h for t in self.tensors])
         arr_c = (ctypes.c_int * len(self.cells))(*self.cells)
         if stream is None:
@@ -249,6 +253,21 @@ class Plan:
         _check(lib().gd_rk_step(self.h, _ptr(g), _ptr(kscale), float(dt), int(n_steps),
                                 ctypes.byref(v) if count_violations else None))
         return v.value if count_violations else None
+
+    def rk_advance(self, g, t, t_end, cfl, dt_max, n_substeps, kscale=None, flux_floor=0.0, count=False):
+        """Per-cell steps under the CFL bound (gd_rk_advance) on g and the cell
+        times t in place; with count, returns (violations, unfinished cells)."""
+        _dev64(g, self.n_values, "g")
+        if t is None:
+            raise TypeError("t must be a float64 device tensor")
+        _dev64(t, self.n_cells, "t")
+        _dev64(kscale, self.n_cells, "kscale")
+        v = ctypes.c_longlong(0)
+        u = ctypes.c_longlong(0)
+        _check(lib().gd_rk_advance(self.h, _ptr(g), _ptr(kscale), _ptr(t), float(t_end), float(cfl), float(dt_max),
+                                   float(flux_floor), int(n_substeps), ctypes.byref(v) if count else None,
+                                   ctypes.byref(u) if count else None))
+        return (v.value, u.value) if count else None
 
     def timing(self, enable=True):
         _check(lib().gd_plan_timing(self.h, int(bool(enable))))

@@ -39,6 +39,7 @@ def test_invalid_arguments_are_rejected():
         G.Tensor(8, 1, 1e-3, 1e3, kernel="maxwell", v0=0.5, v_bounce=-0.1, frag="general", levels=(1.0,))
     with pytest.raises(G.GDError, match="alpha"):
         G.Tensor(8, 1, 1e-3, 1e3, frag="general", alpha=-2.0, levels=(1.0,))
+    assert L.gd_rk_advance(None, None, None, None, 1.0, 0.1, 1.0, 0.0, 1, None, None) == G.GD_EINVAL
     f9 = G._Frag(9, -11 / 6, 1, lv.ctypes.data_as(G._DP))
     assert L.gd_init_tensor(ctypes.byref(k), ctypes.byref(f9), 8, 1, ctypes.byref(g), ctypes.byref(h)) == G.GD_EINVAL
 

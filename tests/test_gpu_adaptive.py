@@ -1,0 +1,241 @@
+"""Per-cell time steps under the CFL bound (Eq. dt) on the GPU: gd_rk_advance
+against the oracle's sub-stepping (oracle.rk_adaptive), cell by cell.
+
+Each sub-step a cell takes dt_c = min(dt_max, t_end - t_c, cfl B_c), B_c the
+Eq. dt bound of its start state over the bins losing mass.  The binding bin is
+often a near-empty tail bin whose outflow is a difference of fluxes far below the
+cell's largest.  The FP64 tensor contraction sums the same products as the
+oracle's nested quadrature in another order; on such tiny fluxes that shows as up
+to ~1e-8 relative in the chosen steps (well inside the 1e-6 bound used here), and
+the states agree to the 1e-11 bound of the fixed steps.
+
+The split-FP16 fluxes carry an absolute error of up to 1e-6 of the cell's largest
+flux, so tail outflows below that are noise there and the flux floor leaves them
+out (on both sides).  Its chosen steps are compared with the oracle's on the first
+sub-step, with a per-cell bound derived from that error: 2e-6 max|Y| over the
+outflow of each bin that could bind.  Beyond one sub-step the split and FP64
+sides flatten different tail bins, so longer split runs are checked by their
+invariants (clocks, mass, held cells) and by the bit-exact reduction to fixed
+steps below the bound.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2607_13740_amd import gracedg as G  # noqa: E402
+from paper_2607_13740_amd import workloads as W  # noqa: E402
+
+from test_gpu_parity import DEV, _pair, _states  # noqa: E402
+
+CFL = 0.1
+
+
+def _normwise(gg, go, h):
+    return np.max(np.abs((gg - go) * h), axis=1) / np.max(np.abs(go * h), axis=1)
+
+
+def _case(O, name, C, seed):
+    t, cfg = _pair(O, name)
+    g, p = _states(O, cfg, C, seed=seed)
+    g, _ = O.limit(cfg, g)
+    ks = p["kscale"]
+    # an end time that about half of the cells reach within 8 sub-steps
+    B = np.array([O.cfl_dt(cfg, g[c:c + 1], kscale=ks[c:c + 1]) for c in range(C)])
+    t_end = 8.0 * CFL * float(np.median(B))
+    return t, cfg, g, ks, t_end
+
+
+@pytest.mark.parametrize("name", ["ball_k2", "ball_k3", "ball_k4"])
+def test_rk_advance_matches_oracle(oracle, name):
+    """FP64 plans, the bound as printed (no floor): 8 sub-steps, about half of the
+    cells reach t_end."""
+    O = oracle
+    C, n_sub = 40, 8
+    t, cfg, g, ks, t_end = _case(O, name, C, seed=13)
+    go, to, vo = O.rk_adaptive(cfg, g, CFL, 1e30, t_end, n_sub, kscale=ks)
+    assert vo == 0 and 0 < np.count_nonzero(to < t_end) < C
+    plan = G.Plan(t, C, precision="fp64")
+    gd = torch.tensor(g, device=DEV).view(-1)
+    td = torch.zeros(C, dtype=torch.float64, device=DEV)
+    v, unfinished = plan.rk_advance(gd, td, t_end, CFL, 1e30, n_sub, kscale=torch.tensor(ks, device=DEV),
+                                    count=True)
+    gg = gd.cpu().numpy().reshape(C, -1)
+    tg = td.cpu().numpy()
+    h = np.tile(np.repeat(np.diff(O.edges(cfg)), cfg.k + 1), (C, 1))
+    assert np.max(np.abs(tg - to) / to) <= 1e-6
+    assert _normwise(gg, go, h).max() <= 1e-11, _normwise(gg, go, h).max()
+    assert v == 0 and unfinished == np.count_nonzero(tg < t_end) == np.count_nonzero(to < t_end)
+    m0 = (g * h)[:, ::cfg.k + 1].sum(axis=1)
+    m1 = (gg * h)[:, ::cfg.k + 1].sum(axis=1)
+    assert np.max(np.abs(m1 - m0) / m0) <= 1e-12
+
+
+@pytest.mark.parametrize("name", ["ball_k2", "ball_k3", "ball_k4"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk_advance_flux_floor_first_substep(oracle, prec, name):
+    """Flux floor 1e-4: the first sub-step's steps against the oracle's with the
+    same floor.  FP64: to round-off, and the same bins flattened.  Split FP16: each
+    cell within the bound its flux error allows (cells with a bin whose outflow lies
+    within that error of the floor are skipped: either side of the floor is right)."""
+    O = oracle
+    C, floor = 40, 1e-4
+    t, cfg, g, ks, _ = _case(O, name, C, seed=13)
+    go, to, vo = O.rk_adaptive(cfg, g, CFL, 1e30, 1e30, 1, kscale=ks, floor=floor)
+    plan = G.Plan(t, C, precision=prec)
+    gd = torch.tensor(g, device=DEV).view(-1)
+    td = torch.zeros(C, dtype=torch.float64, device=DEV)
+    v, _ = plan.rk_advance(gd, td, 1e30, CFL, 1e30, 1, kscale=torch.tensor(ks, device=DEV), flux_floor=floor,
+                           count=True)
+    tg = td.cpu().numpy()
+    if prec == "fp64":
+        assert np.max(np.abs(tg - to) / to) <= 1e-12
+        h = np.tile(np.repeat(np.diff(O.edges(cfg)), cfg.k + 1), (C, 1))
+        assert _normwise(gd.cpu().numpy().reshape(C, -1), go, h).max() <= 1e-11
+        assert v == vo
+        return
+    eps = 1e-6
+    Y, _, Fe = O.rhs(cfg, g, kscale=ks)
+    h = np.diff(O.edges(cfg))
+    d = np.diff(Fe, axis=1)
+    avg = g.reshape(C, cfg.N, -1)[:, :, 0]
+    err = 2.0 * eps * np.abs(Y).max(axis=1)
+    fl = floor * np.abs(Fe).max(axis=1)
+    checked = 0
+    for c in range(C):
+        if np.any(np.abs(d[c] - fl[c]) <= err[c] + eps * fl[c]):
+            continue
+        keep = (d[c] > fl[c]) & (avg[c] > 0)
+        b = np.where(keep, h * avg[c] / np.where(keep, d[c], 1.0), np.inf)
+        B = b.min()
+        near = keep & (b <= 2.0 * B)
+        tol = np.max(err[c] / d[c][near]) * 1.01 + 1e-14
+        assert abs(tg[c] - to[c]) <= tol * to[c], (c, tg[c], to[c], tol)
+        checked += 1
+    assert checked >= C // 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk_advance_reaches_end_time_and_holds(oracle, prec):
+    """Enough sub-steps bring every cell to t_end exactly; a further call leaves the
+    states as the start limiter alone leaves them, bit for bit, and the clocks as
+    they are; the conservative flux keeps every cell's mass.  FP64 (no floor) also
+    against the oracle."""
+    O = oracle
+    C = 40
+    floor = 0.0 if prec == "fp64" else 1e-4
+    t, cfg, g, ks, t_end = _case(O, "ball_k2", C, seed=14)
+    plan = G.Plan(t, C, precision=prec)
+    ksd = torch.tensor(ks, device=DEV)
+    gd = torch.tensor(g, device=DEV).view(-1)
+    td = torch.zeros(C, dtype=torch.float64, device=DEV)
+    v, unfinished = plan.rk_advance(gd, td, t_end, CFL, 1e30, 200, kscale=ksd, flux_floor=floor, count=True)
+    assert unfinished == 0 and torch.all(td == t_end).item()
+    ref = gd.clone()
+    plan.rk_step(ref, 1.0, 0, kscale=ksd)     # the start limiter only
+    v2, u2 = plan.rk_advance(gd, td, t_end, CFL, 1e30, 3, kscale=ksd, flux_floor=floor, count=True)
+    torch.cuda.synchronize()
+    assert u2 == 0 and (v2 == 0 or prec == "mixed")   # split: tail bins left to the limiter stay negative
+    assert torch.equal(gd, ref) and torch.all(td == t_end).item()
+    gg = gd.cpu().numpy().reshape(C, -1)
+    h = np.tile(np.repeat(np.diff(O.edges(cfg)), cfg.k + 1), (C, 1))
+    m0 = (g * h)[:, ::cfg.k + 1].sum(axis=1)
+    m1 = (gg * h)[:, ::cfg.k + 1].sum(axis=1)
+    assert np.max(np.abs(m1 - m0) / m0) <= 1e-12
+    if prec == "fp64":
+        go, to, _ = O.rk_adaptive(cfg, g, CFL, 1e30, t_end, 200, kscale=ks)
+        assert np.all(to == t_end)
+        assert _normwise(gg, go, h).max() <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk_advance_below_the_bound_is_rk_step(oracle, prec):
+    """With dt_max under every cell's bound the sub-steps are gd_rk_step steps of
+    dt_max, bit for bit, and every clock adds dt_max per sub-step."""
+    O = oracle
+    C, n = 40, 5
+    t, cfg, g, ks, _ = _case(O, "ball_k2", C, seed=15)
+    dt = 0.1 * min(O.cfl_dt(cfg, g[c:c + 1], kscale=ks[c:c + 1]) for c in range(C))
+    plan = G.Plan(t, C, precision=prec)
+    ksd = torch.tensor(ks, device=DEV)
+    ga = torch.tensor(g, device=DEV).view(-1)
+    gf = ga.clone()
+    td = torch.zeros(C, dtype=torch.float64, device=DEV)
+    plan.rk_advance(ga, td, 1e30, 1.0, dt, n, kscale=ksd)
+    plan.rk_step(gf, dt, n, kscale=ksd)
+    torch.cuda.synchronize()
+    assert torch.equal(ga, gf)
+    tt = 0.0
+    for _ in range(n):
+        tt += dt
+    assert torch.all(td == tt).item()
+
+
+def test_rk_advance_uneven_batch_and_thresholds(oracle):
+    """Two groups of different shape in one plan, and per-cell thresholds (cells
+    sorted into brackets inside the plan): the clocks and states stay in the
+    caller's cell order."""
+    O = oracle
+    t1, c1 = _pair(O, "ball_k2")
+    t2, c2 = _pair(O, "add_k1")
+    g1, p1 = _states(O, c1, 33, seed=16)
+    g2, p2 = _states(O, c2, 20, seed=17)
+    g1, _ = O.limit(c1, g1)
+    g2, _ = O.limit(c2, g2)
+    t_end = 6.0 * CFL * min(O.cfl_dt(c1, g1), O.cfl_dt(c2, g2))
+    t0 = np.concatenate([np.linspace(0.0, t_end, 33), np.zeros(20)])   # some cells start done
+    plan = G.Plan([t1, t2], [33, 20], precision="fp64")
+    gd = torch.tensor(np.concatenate([g1.reshape(-1), g2.reshape(-1)]), device=DEV)
+    td = torch.tensor(t0, device=DEV)
+    plan.rk_advance(gd, td, t_end, CFL, 1e30, 6)
+    o1, to1, _ = O.rk_adaptive(c1, g1, CFL, 1e30, t_end, 6, t=t0[:33])
+    o2, to2, _ = O.rk_adaptive(c2, g2, CFL, 1e30, t_end, 6, t=t0[33:])
+    r = gd.cpu().numpy()
+    tg = td.cpu().numpy()
+    tol = 1e-11
+    h1 = np.tile(np.repeat(np.diff(O.edges(c1)), c1.k + 1), (33, 1))
+    h2 = np.tile(np.repeat(np.diff(O.edges(c2)), c2.k + 1), (20, 1))
+    assert _normwise(r[:33 * c1.P].reshape(33, -1), o1, h1).max() <= tol
+    assert _normwise(r[33 * c1.P:].reshape(20, -1), o2, h2).max() <= tol
+    to = np.concatenate([to1, to2])
+    assert tg[32] == t_end and np.array_equal(tg[:33] == t_end, to1 == t_end)
+    assert np.max(np.abs(tg - to) / np.maximum(to, 1e-300)) <= 1e-6
+
+    # per-cell thresholds between tabulated levels (R13 blend), bracket-sorted slots
+    lv = W.VFRAG_LEVELS
+    N, k, C = 12, 2, 70
+    tt = G.Tensor(N, k, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=lv, conservative=True)
+    cfg = O.Config(N=N, k=k, xmin=1e-4, xmax=1e8, kernel="ballistic", frag="powerlaw", conservative=True,
+                   levels=lv)
+    rng = np.random.default_rng(23)
+    vf = rng.uniform(0.3, 1.0, C)
+    g = np.stack([O.project(cfg, lambda x, mu=mu: W.lognormal_density(x, mu, 1.0, 1.0))
+                  for mu in rng.uniform(np.log(30.0), np.log(3000.0), C)])
+    g, _ = O.limit(cfg, g)
+    ks = np.exp(0.5 * rng.standard_normal(C))
+    t_end = 5.0 * CFL * O.cfl_dt(cfg, g, kscale=ks, vfrag=vf)
+    go, to, _ = O.rk_adaptive(cfg, g, CFL, 1e30, t_end, 4, kscale=ks, vfrag=vf)
+    plan = G.Plan(tt, C, precision="fp64", vfrag=vf)
+    gd = torch.tensor(g, device=DEV).view(-1)
+    td = torch.zeros(C, dtype=torch.float64, device=DEV)
+    plan.rk_advance(gd, td, t_end, CFL, 1e30, 4, kscale=torch.tensor(ks, device=DEV))
+    h = np.tile(np.repeat(np.diff(O.edges(cfg)), k + 1), (C, 1))
+    assert _normwise(gd.cpu().numpy().reshape(C, -1), go, h).max() <= tol
+    assert np.max(np.abs(td.cpu().numpy() - to) / to) <= 1e-6
+
+
+def test_rk_advance_zero_substeps_counts_only(oracle):
+    O = oracle
+    t, cfg, g, ks, t_end = _case(O, "ball_k2", 10, seed=18)
+    plan = G.Plan(t, 10, precision="fp64")
+    gd = torch.tensor(g, device=DEV).view(-1)
+    td = torch.tensor(np.linspace(0.0, 2.0 * t_end, 10), device=DEV)
+    v, u = plan.rk_advance(gd, td, t_end, CFL, 1e30, 0, count=True)
+    assert v == 0 and u == int(np.count_nonzero(np.linspace(0.0, 2.0 * t_end, 10) < t_end))
+    with pytest.raises(G.GDError):
+        plan.rk_advance(gd, td, t_end, 0.0, 1e30, 1)
+    with pytest.raises(G.GDError):
+        plan.rk_advance(gd, td, t_end, CFL, 1e30, 1, flux_floor=-1.0)
+    with pytest.raises(G.GDError):
+        plan.rk_advance(gd, td, float("inf"), CFL, 1e30, 1)

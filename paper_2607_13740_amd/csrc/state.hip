@@ -140,35 +140,28 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                 sfmax[tid] = 0ull;
             }
             __syncthreads();
-            auto edges = [&](int t, int& sl, int& j, int& c, double& Fl, double& Fr) {
-                sl = t / N;
-                j = t - sl * N;
-                c = scell[sl];
-                if (c < 0) return;
-                const int s = tile * 32 + sl;
-                auto flux = [&](int q) -> double {
-                    if (Yf) return (double)Yf[(size_t)s * ystride + q] * rowscale[q] * sfac[sl];
-                    return Yd[(size_t)s * ystride + q] * sfac[sl];
-                };
-                Fl = (j == 0) ? 0.0 : flux(j * K1 - 1);
-                Fr = (j + 1 < N || !conservative) ? flux((j + 1) * K1 - 1) : 0.0;
+            // flux at raw position q of slot sl (edge fluxes sit at j(k+1)-1)
+            auto flux = [&](int sl, int q) -> double {
+                const size_t at = (size_t)(tile * 32 + sl) * ystride + q;
+                if (Yf) return (double)Yf[at] * rowscale[q] * sfac[sl];
+                return Yd[at] * sfac[sl];
             };
             if (a.floor > 0.0) {
                 for (int t = tid; t < 32 * N; t += nthr) {
-                    int sl, j, c;
-                    double Fl = 0.0, Fr = 0.0;
-                    edges(t, sl, j, c, Fl, Fr);
-                    if (c < 0) continue;
+                    const int sl = t / N, j = t - sl * N;
+                    if (scell[sl] < 0) continue;
+                    const double Fl = (j == 0) ? 0.0 : flux(sl, j * K1 - 1);
+                    const double Fr = (j + 1 < N || !conservative) ? flux(sl, (j + 1) * K1 - 1) : 0.0;
                     const double m = fmax(fabs(Fl), fabs(Fr));
                     if (m > 0.0) atomicMax(&sfmax[sl], (unsigned long long)__double_as_longlong(m));
                 }
                 __syncthreads();
             }
             for (int t = tid; t < 32 * N; t += nthr) {
-                int sl, j, c;
-                double Fl = 0.0, Fr = 0.0;
-                edges(t, sl, j, c, Fl, Fr);
+                const int sl = t / N, j = t - sl * N, c = scell[sl];
                 if (c < 0) continue;
+                const double Fl = (j == 0) ? 0.0 : flux(sl, j * K1 - 1);
+                const double Fr = (j + 1 < N || !conservative) ? flux(sl, (j + 1) * K1 - 1) : 0.0;
                 const double d = Fr - Fl, gj = gs[(size_t)c * P + j * K1];
                 const double fl = a.floor * __longlong_as_double((long long)sfmax[sl]);
                 if (d > 0.0 && d > fl && gj > 0.0) {
@@ -257,6 +250,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                 if (a.mode >= 1) load(gs, xs);
                 if (a.mode >= 2) load(gn, xn);
                 const double dt = ADAPT ? sdt[sl] : a.dt;
+                const bool hold = ADAPT && !(dt > 0.0);   // this cell takes no step
                 for (int i = 0; i < K1; ++i) {
                     const double V = (i == 0) ? 0.0 : pos(j * K1 + i - 1);
                     if (raw && i > 0) raw[(size_t)c * n_out + vbase + j * k + i - 1] = V;
@@ -264,13 +258,11 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                     const double L = (2.0 * i + 1.0) * ihj * (V - Fr + sgn * Fl);
                     switch (a.mode) {
                     case 0: v[i] = L; break;
-                    case 1: v[i] = xs[i] + dt * L; break;
-                    case 2: v[i] = 0.75 * xn[i] + 0.25 * (xs[i] + dt * L); break;
-                    default: v[i] = (1.0 / 3.0) * xn[i] + (2.0 / 3.0) * (xs[i] + dt * L); break;
+                    case 1: v[i] = hold ? xs[i] : xs[i] + dt * L; break;
+                    case 2: v[i] = hold ? xn[i] : 0.75 * xn[i] + 0.25 * (xs[i] + dt * L); break;
+                    default: v[i] = hold ? xn[i] : (1.0 / 3.0) * xn[i] + (2.0 / 3.0) * (xs[i] + dt * L); break;
                     }
                 }
-                if (ADAPT && !(dt > 0.0))
-                    for (int i = 0; i < K1; ++i) v[i] = (a.mode >= 2) ? xn[i] : xs[i];
             }
             if (a.limit && !(ADAPT && a.mode >= 1 && !(sdt[sl] > 0.0))) {
                 double gam;

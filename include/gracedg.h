@@ -129,7 +129,7 @@ typedef struct {
  * split at every bin edge.  T is built in FP64 on the host and uploaded in the
  * layouts of both contraction precisions.  Synchronous.  *out receives a handle
  * that the caller releases with gd_free_tensor.  Limits: 2 <= bins <= 256,
- * 0 <= order <= 4, P = bins*(order+1) <= 192; GD_EINVAL otherwise.
+ * 0 <= order <= 4, P = bins*(order+1) <= 208; GD_EINVAL otherwise.
  */
 int gd_init_tensor(const gd_kernel* kernel, const gd_frag_law* frag, int bins, int order,
                    const gd_grid* grid, gd_tensor** out);

@@ -155,8 +155,8 @@ struct AdjItem {
 template <int KSMAX, int W>
 __global__ __launch_bounds__(64 * W) void k_adjoint_fp64(ContractArgs a)
 {
-    __shared__ uint4 buf0[kFragBudget * 128];
-    __shared__ uint4 buf1[kFragBudget * 128];
+    __shared__ uint4 buf0[frag_budget(KSMAX) * 128];
+    __shared__ uint4 buf1[frag_budget(KSMAX) * 128];
     const int4 it = cptr(a.items)[blockIdx.x];
     if (it.x < 0) return;
     AdjItem<W> f{cptr(a.groups) + it.x, a.g, it.y, it.z & 0x3ff, (it.z >> 10) & 0x3ff, it.w, it.z >> 20, buf0, buf1};
@@ -176,6 +176,7 @@ int launch_adjoint_fp64(const ContractArgs& a, int ksomax, hipStream_t s)
 {
     if (ksomax <= 6) return launch_adj<6, kAdjWaves>(a, s);
     if (ksomax <= 12) return launch_adj<12, kAdjWaves>(a, s);
+    if (ksomax <= kMaxKS) return launch_adj<kMaxKS, kAdjWaves>(a, s);
     return fail(GD_EUNSUPPORTED, "too many output rows for the adjoint contraction");
 }
 
@@ -228,6 +229,7 @@ template <int PMAX>
 __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
 {
     constexpr int SUB = 32 / kAdjSlots;
+    constexpr int MAXNQB = (PMAX + 15) / 16, MAXNPS = (PMAX + kAdjPs - 1) / kAdjPs;   // q blocks, p ranges
     __shared__ double sl_lam[kAdjSlots * PMAX];
     __shared__ double red[kAdjSlots];
     const GD_CONST GroupDev* groups = cptr(a.groups);
@@ -266,21 +268,21 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
             // second-sum partials: the p ranges present in the block of q = p
             // (fixed trip counts, so that all partial loads are in flight together)
             const int qbp = p / 16, npr = cdiv_dev(min(P, qbp * 16 + 16), kAdjPs);
-            double g2[kAdjMaxNPS], g1[kAdjMaxNQB], g1d[kAdjMaxNQB];
+            double g2[MAXNPS], g1[MAXNQB], g1d[MAXNQB];
 #pragma unroll
-            for (int ps = 0; ps < kAdjMaxNPS; ++ps)
+            for (int ps = 0; ps < MAXNPS; ++ps)
                 g2[ps] = (ps < npr) ? G2[((size_t)ps * n_slots + s) * P + p] : 0.0;
 #pragma unroll
-            for (int qb = 0; qb < kAdjMaxNQB; ++qb) {
+            for (int qb = 0; qb < MAXNQB; ++qb) {
                 const bool in = qb >= qbp && qb < NQB;
                 g1[qb] = in ? G1p[((size_t)qb * n_slots + s) * P + p] : 0.0;
                 g1d[qb] = (in && blend) ? G1p[(((size_t)NQB + qb) * n_slots + s) * P + p] : 0.0;
             }
             double g = 0.0;
 #pragma unroll
-            for (int ps = 0; ps < kAdjMaxNPS; ++ps) g += g2[ps];
+            for (int ps = 0; ps < MAXNPS; ++ps) g += g2[ps];
 #pragma unroll
-            for (int qb = 0; qb < kAdjMaxNQB; ++qb) g += g1[qb] + g1d[qb];
+            for (int qb = 0; qb < MAXNQB; ++qb) g += g1[qb] + g1d[qb];
             const double sc = kscale ? kscale[c] : 1.0;
             v += sc * g;
             atomicAdd(&red[sl], 0.5 * ylin[(size_t)c * P + p] * g);
@@ -297,14 +299,14 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
                 if (a.dvfrag && blend) {
                     double d = 0.0;
 #pragma unroll
-                    for (int qb = 0; qb < kAdjMaxNQB; ++qb) {
+                    for (int qb = 0; qb < MAXNQB; ++qb) {
                         const int npr = cdiv_dev(min(P, qb * 16 + 16), kAdjPs);
-                        double dq[kAdjMaxNPS];
+                        double dq[MAXNPS];
 #pragma unroll
-                        for (int ps = 0; ps < kAdjMaxNPS; ++ps)
+                        for (int ps = 0; ps < MAXNPS; ++ps)
                             dq[ps] = (qb < NQB && ps < npr) ? G->Dth[((size_t)ps * NQB + qb) * n_slots + s] : 0.0;
 #pragma unroll
-                        for (int ps = 0; ps < kAdjMaxNPS; ++ps) d += dq[ps];
+                        for (int ps = 0; ps < MAXNPS; ++ps) d += dq[ps];
                     }
                     const double sc = kscale ? kscale[c] : 1.0;
                     a.dvfrag[G->cell0 + c] += sc * d * G->dthdv[s];
@@ -386,6 +388,8 @@ int launch_adj_boundary(const AdjStageArgs& a, hipStream_t s)
         hipLaunchKernelGGL(k_adj_boundary<96>, grid, dim3(kAdjThreads), 0, s, a);
     else if (a.max_p <= 192)
         hipLaunchKernelGGL(k_adj_boundary<192>, grid, dim3(kAdjThreads), 0, s, a);
+    else if (a.max_p <= kMaxP)
+        hipLaunchKernelGGL(k_adj_boundary<kMaxP>, grid, dim3(kAdjThreads), 0, s, a);
     else
         return fail(GD_EUNSUPPORTED, "P too large for the reverse stage kernel");
     HIP_TRY(hipGetLastError());

@@ -173,7 +173,7 @@ static void build_schedule(const gd_tensor* t, int RB, int KW, bool sort_by_lo, 
                     d.scale = sc;
                     d.frag = nfrag;
                     while (s0 < segs.size() && d.nseg < kSegMax &&
-                           (nfrag - d.frag) + (KSx - segs[s0].lo) <= kFragBudget) {
+                           (nfrag - d.frag) + (KSx - segs[s0].lo) <= frag_budget(KSx)) {
                         const int j = d.nseg++;
                         d.p[j] = segs[s0].p;
                         d.lo[j] = segs[s0].lo;
@@ -256,7 +256,7 @@ static int pack_adjoint(gd_tensor* t)
                     d.delta = delta;
                     d.frag = nfrag;
                     while (s0 < segs.size() && d.nseg < kSegMax &&
-                           (nfrag - d.frag) + (KSO - segs[s0].lo) <= kFragBudget) {
+                           (nfrag - d.frag) + (KSO - segs[s0].lo) <= frag_budget(KSO)) {
                         const int j = d.nseg++;
                         d.p[j] = segs[s0].p;
                         d.lo[j] = segs[s0].lo;
@@ -449,7 +449,7 @@ extern "C" int gd_init_tensor(const gd_kernel* kernel, const gd_frag_law* frag, 
     if (frag->kind != GD_FRAG_NONE && (frag->n_levels < 1 || frag->n_levels > 64 || !frag->levels))
         return fail(GD_EINVAL, "fragmentation needs 1..64 threshold levels");
     const int P = bins * (order + 1);
-    if (P > 192) return fail(GD_EINVAL, "P = bins*(order+1) must be <= 192");
+    if (P > kMaxP) return fail(GD_EINVAL, "P = bins*(order+1) must be <= 208");
     auto t = std::unique_ptr<gd_tensor>(new (std::nothrow) gd_tensor());
     if (!t) return fail(GD_ENOMEM, "host allocation");
     TensorSpec& sp = t->spec;

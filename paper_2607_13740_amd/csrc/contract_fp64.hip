@@ -119,8 +119,8 @@ struct F64Item {
 template <int KSMAX, int W>
 __global__ __launch_bounds__(64 * W) void k_contract_fp64(ContractArgs a)
 {
-    __shared__ uint4 buf0[kFragBudget * 128];
-    __shared__ uint4 buf1[kFragBudget * 128];
+    __shared__ uint4 buf0[frag_budget(KSMAX) * 128];
+    __shared__ uint4 buf1[frag_budget(KSMAX) * 128];
     const int4 it = cptr(a.items)[blockIdx.x];
     if (it.x < 0) return;   // padding of an XCD's range
     F64Item<W> f{cptr(a.groups) + it.x, a.g, it.y, it.z & 0x3ff, (it.z >> 10) & 0x3ff, it.w, it.z >> 20, buf0, buf1};
@@ -144,6 +144,7 @@ int launch_contract_fp64(const ContractArgs& a, int ksmax, int waves, hipStream_
     if (ksmax <= 6) return w4 ? launch<6, 4>(a, s) : launch<6, 8>(a, s);
     if (ksmax <= 8) return w4 ? launch<8, 4>(a, s) : launch<8, 8>(a, s);
     if (ksmax <= 12) return w4 ? launch<12, 4>(a, s) : launch<12, 8>(a, s);
+    if (ksmax <= kMaxKS) return w4 ? launch<kMaxKS, 4>(a, s) : launch<kMaxKS, 8>(a, s);
     return fail(GD_EUNSUPPORTED, "P too large for the FP64 contraction");
 }
 

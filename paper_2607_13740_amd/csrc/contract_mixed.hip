@@ -168,8 +168,8 @@ struct MixedItem {
 template <int KSMAX, int W, int T>
 __global__ __launch_bounds__(64 * W, T == 2 ? 2 : 1) void k_contract_mixed(ContractArgs a)
 {
-    __shared__ uint4 buf0[kFragBudget * 128];
-    __shared__ uint4 buf1[kFragBudget * 128];
+    __shared__ uint4 buf0[frag_budget(KSMAX) * 128];
+    __shared__ uint4 buf1[frag_budget(KSMAX) * 128];
     const int4 it = cptr(a.items)[blockIdx.x];
     if (it.x < 0) return;   // padding of an XCD's range
     MixedItem<W, T> f{cptr(a.groups) + it.x, it.y, it.z & 0x3ff, (it.z >> 10) & 0x3ff, it.w, it.z >> 20, buf0, buf1};
@@ -202,6 +202,7 @@ int launch_contract_mixed(const ContractArgs& a, int ksmax, int waves, int tpw, 
     if (ksmax <= 6) return launch_ks<6>(a, waves, tpw, s);
     if (ksmax <= 8) return launch_ks<8>(a, waves, tpw, s);
     if (ksmax <= 12) return launch_ks<12>(a, waves, tpw, s);
+    if (ksmax <= kMaxKS) return launch_ks<kMaxKS>(a, waves, tpw, s);
     return fail(GD_EUNSUPPORTED, "P too large for the mixed contraction");
 }
 

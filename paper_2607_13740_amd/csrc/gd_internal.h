@@ -51,7 +51,8 @@ __device__ __forceinline__ GD_GLOBAL T* gptr(T* p)
 // The contraction of one tensor level r and one row block ob is a list of
 // iterations.  An iteration carries up to kSegMax p values ("segments") of one part
 // (the level itself, or the difference of the next level and this one) whose
-// fragments together fit one LDS buffer of kFragBudget fragments of 2 KB.  Segment s
+// fragments together fit one LDS buffer of frag_budget(KS) fragments of 2 KB (12, or
+// KS when a single chain is longer).  Segment s
 // covers the K steps lo[s]..KS-1 (16 columns q each) of p[s]: blocks before lo are
 // structural zeros, zero blocks after it are stored as zero fragments.  Fragments
 // of an iteration are contiguous, segment by segment, K step ascending.  Every list
@@ -60,6 +61,9 @@ __device__ __forceinline__ GD_GLOBAL T* gptr(T* p)
 // iteration.
 constexpr int kSegMax = 4;
 constexpr int kFragBudget = 12;
+constexpr int kMaxKS = 13;            // K steps of 16: P = bins * (order + 1) <= 208
+constexpr int kMaxP = 16 * kMaxKS;
+constexpr int frag_budget(int ks) { return ks > kFragBudget ? ks : kFragBudget; }
 struct IterDesc {
     int ob;
     int delta;           // 1: level-difference part, weighted by the cell's blend factor
@@ -179,8 +183,6 @@ constexpr int kAdjThreads = 256;
 constexpr int kAdjSlots = 8;   // slots per workgroup of the per-slot reverse kernels (4 per tile)
 constexpr int kAdjPs = 32;     // values of p per list of the vector-Jacobian product
 constexpr int kAdjWaves = 4;   // waves per workgroup of the vector-Jacobian product
-constexpr int kAdjMaxNQB = 12; // q blocks of 16 for P <= 192
-constexpr int kAdjMaxNPS = 6;  // p ranges of kAdjPs for P <= 192
 struct AdjStageArgs {
     const GroupDev* groups;
     int n_groups;

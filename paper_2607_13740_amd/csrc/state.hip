@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void k_project(const double* samples, const do
 // floor times it are left out (with split-FP16 fluxes such outflows can be rounding
 // noise).  A cell with dt = 0 (done, or stuck at a zero bound) keeps its state bit
 // for bit: no combination, no limiter.
-constexpr int kStageMaxP = 192;
+constexpr int kStageMidP = 192;
 constexpr int kStageThreads = 256;
 
 template <int PMAX, bool ADAPT>
@@ -334,16 +334,18 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
 int launch_stage(const StageArgs& a, hipStream_t s)
 {
     if (a.n_tiles == 0) return GD_OK;
-    if (a.max_p > kStageMaxP) return fail(GD_EUNSUPPORTED, "P too large for the stage kernel");
+    if (a.max_p > kMaxP) return fail(GD_EUNSUPPORTED, "P too large for the stage kernel");
     // LDS sized to the plan's largest P (more resident workgroups for small P)
     const dim3 grid(a.n_tiles), block(kStageThreads);
     if (a.adapt) {
         if (a.mode < 1 || !a.tcell || !a.dtc) return fail(GD_EINVAL, "adaptive stage needs an RK mode and time arrays");
         if (a.max_p <= 96) hipLaunchKernelGGL((k_stage<96, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_stage<kStageMaxP, true>), grid, block, 0, s, a);
+        else if (a.max_p <= kStageMidP) hipLaunchKernelGGL((k_stage<kStageMidP, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_stage<kMaxP, true>), grid, block, 0, s, a);
     } else {
         if (a.max_p <= 96) hipLaunchKernelGGL((k_stage<96, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_stage<kStageMaxP, false>), grid, block, 0, s, a);
+        else if (a.max_p <= kStageMidP) hipLaunchKernelGGL((k_stage<kStageMidP, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_stage<kMaxP, false>), grid, block, 0, s, a);
     }
     HIP_TRY(hipGetLastError());
     return GD_OK;

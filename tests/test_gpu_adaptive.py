@@ -47,10 +47,12 @@ def _case(O, name, C, seed):
     return t, cfg, g, ks, t_end
 
 
-@pytest.mark.parametrize("name", ["ball_k2", "ball_k3", "ball_k4"])
+@pytest.mark.parametrize("name", ["ball_k2", "ball_k3", "ball_k4", "coupled_k2", "coupled_nc_k3"])
 def test_rk_advance_matches_oracle(oracle, name):
     """FP64 plans, the bound as printed (no floor): 8 sub-steps, about half of the
-    cells reach t_end."""
+    cells reach t_end.  Also the coupled model of Sec. 4.5 (general breakage,
+    Maxwellian outcomes), conservative and not (the outflow through x_max then
+    enters the last bin's bound)."""
     O = oracle
     C, n_sub = 40, 8
     t, cfg, g, ks, t_end = _case(O, name, C, seed=13)
@@ -67,9 +69,10 @@ def test_rk_advance_matches_oracle(oracle, name):
     assert np.max(np.abs(tg - to) / to) <= 1e-6
     assert _normwise(gg, go, h).max() <= 1e-11, _normwise(gg, go, h).max()
     assert v == 0 and unfinished == np.count_nonzero(tg < t_end) == np.count_nonzero(to < t_end)
-    m0 = (g * h)[:, ::cfg.k + 1].sum(axis=1)
-    m1 = (gg * h)[:, ::cfg.k + 1].sum(axis=1)
-    assert np.max(np.abs(m1 - m0) / m0) <= 1e-12
+    if cfg.conservative:
+        m0 = (g * h)[:, ::cfg.k + 1].sum(axis=1)
+        m1 = (gg * h)[:, ::cfg.k + 1].sum(axis=1)
+        assert np.max(np.abs(m1 - m0) / m0) <= 1e-12
 
 
 @pytest.mark.parametrize("name", ["ball_k2", "ball_k3", "ball_k4"])
@@ -239,3 +242,39 @@ def test_rk_advance_zero_substeps_counts_only(oracle):
         plan.rk_advance(gd, td, t_end, CFL, 1e30, 1, flux_floor=-1.0)
     with pytest.raises(G.GDError):
         plan.rk_advance(gd, td, float("inf"), CFL, 1e30, 1)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_constant_kernel_full_size(oracle, prec):
+    """The paper-size constant-kernel test (Sec. 4.2): N = 40, order 4 (P = 200) on
+    [1e-3, 1e15] from g0 = x e^{-x}, non-conservative flux, to tau = 3e12 under
+    per-cell CFL steps (cfl 1/2).  The printed findings hold on the GPU (mass off by
+    about 1e-6, both error norms below 1%), and the FP64 form follows the oracle's
+    sub-steps (about 130) to 1e-8 normwise; the split form (flux floor 1e-4) reaches
+    the same accuracy against the closed form."""
+    import json
+    import os
+    O = oracle
+    v = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.json")))
+    v = v["constant_kernel_full_size"]
+    N, k, tau = v["N"], 4, v["tau"]
+    t = G.Tensor(N, k, v["x_min"], v["x_max"], kernel="const", frag="none", conservative=False)
+    cfg = O.Config(N=N, k=k, xmin=v["x_min"], xmax=v["x_max"], kernel="const")
+    g0 = O.project(cfg, W.xexp_density)
+    plan = G.Plan(t, 1, precision=prec)
+    gd = torch.tensor(g0, device=DEV)
+    td = torch.zeros(1, dtype=torch.float64, device=DEV)
+    floor = 0.0 if prec == "fp64" else 1e-4
+    viol, unfinished = plan.rk_advance(gd, td, tau, 0.5, 1e30, 1000, flux_floor=floor, count=True)
+    assert unfinished == 0 and td.item() == tau
+    gg = gd.cpu().numpy()
+    h = np.diff(O.edges(cfg))
+    dm = abs(1.0 - (h * gg.reshape(N, -1)[:, 0]).sum())
+    assert 0.1 * v["mass_error_about"] < dm < 10.0 * v["mass_error_about"], dm
+    exact = (lambda x: O.g_const(x, tau))
+    assert max(O.error_c(cfg, gg, exact), O.error_d(cfg, gg, exact)) < v["error_below_at_k4"]
+    if prec == "fp64":
+        assert viol == 0
+        go, to, vo = O.rk_adaptive(cfg, g0, 0.5, 1e30, tau, 1000)
+        hh = np.repeat(h, k + 1)[None]
+        assert _normwise(gg.reshape(1, -1), go.reshape(1, -1), hh).max() <= 1e-8

@@ -40,10 +40,12 @@ def _dev(a):
     return torch.tensor(np.ascontiguousarray(a), device=DEV)
 
 
-@pytest.mark.parametrize("conservative", [True, False])
-def test_collision_vjp_matches_oracle_differences(oracle, conservative):
+@pytest.mark.parametrize("conservative,N,k,C", [(True, 8, 2, 12), (False, 8, 2, 12), (True, 52, 3, 4)])
+def test_collision_vjp_matches_oracle_differences(oracle, conservative, N, k, C):
+    """One right-hand-side product; the last case is the widest shape (P = 208, 13 K
+    steps of the transposed tensor)."""
     O = oracle
-    t, cfg, g, ks, vf, rng = _case(O, conservative=conservative)
+    t, cfg, g, ks, vf, rng = _case(O, N=N, k=k, C=C, conservative=conservative)
     C, P = g.shape
     plan = G.Plan(t, C, precision="fp64", vfrag=vf)
     mu = rng.standard_normal((C, P))

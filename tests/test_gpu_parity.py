@@ -38,6 +38,10 @@ CONFIGS = {
     # order 4 (P = 100 and 80)
     "ball_k4": (20, 4, 1e-4, 1e8, "ballistic", "powerlaw", True, 0.5),
     "const_nc_k4": (16, 4, 1e-3, 1e5, "const", "none", False, 1e300),
+    # the largest shapes (13 K steps): the paper-size constant-kernel test (Sec. 4.2,
+    # N = 40, order 4 on [1e-3, 1e15], P = 200) and P = 208
+    "const_nc_k4_n40": (40, 4, 1e-3, 1e15, "const", "none", False, 1e300),
+    "ball_k3_n52": (52, 3, 1e-4, 1e8, "ballistic", "powerlaw", True, 0.5),
 }
 
 

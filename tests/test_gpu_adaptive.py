@@ -278,3 +278,62 @@ def test_constant_kernel_full_size(oracle, prec):
         go, to, vo = O.rk_adaptive(cfg, g0, 0.5, 1e30, tau, 1000)
         hh = np.repeat(h, k + 1)[None]
         assert _normwise(gg.reshape(1, -1), go.reshape(1, -1), hh).max() <= 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk_advance_full_size_sampled(oracle, prec):
+    """The benchmark workload at full size (65536 cells, P = 96, per-cell kernel
+    scale and threshold) in the configuration bench.py times (cfl 0.1; FP64 without
+    floor, split FP16 with floor 1e-4): one sub-step toward an end time that part of
+    the cells reach.  Sampled cells against the oracle (FP64: steps to 1e-6 and
+    states to 1e-11; split: steps within the flux-error bound of the first-sub-step
+    test), clocks and masses checked on every cell."""
+    O = oracle
+    w = W.WORKLOADS["c3_batched"]
+    t = G.Tensor(w.bins, w.order, w.x_min, w.x_max, kernel=w.kernel, frag=w.frag, levels=w.levels,
+                 conservative=w.conservative)
+    p = W.lognormal_cells(w.cells, w.seed)
+    g0 = t.project(torch.tensor(W.samples(w, t.projection_points(), params=p), device=DEV)).reshape(-1)
+    ks = torch.tensor(p["kscale"], device=DEV)
+    plan = G.Plan(t, w.cells, precision=prec, vfrag=p["vfrag"])
+    floor = 0.0 if prec == "fp64" else 1e-4
+    cfg = O.Config(N=w.bins, k=w.order, xmin=w.x_min, xmax=w.x_max, kernel=w.kernel, frag=w.frag,
+                   conservative=w.conservative, levels=w.levels)
+    idx = np.random.default_rng(6).choice(w.cells, 16, replace=False)
+    idx[:2] = [0, w.cells - 1]
+    plan_limited = g0.clone()
+    plan.rk_step(plan_limited, w.dt, 0, kscale=ks)            # the start limiter, for the oracle's input
+    gs = plan_limited.view(w.cells, -1)[idx].cpu().numpy()
+    _, tb, _ = O.rk_adaptive(cfg, gs, CFL, 1e30, 1e30, 1, kscale=p["kscale"][idx], vfrag=p["vfrag"][idx],
+                             floor=floor)
+    t_end = float(np.median(tb))
+    go, to, _ = O.rk_adaptive(cfg, gs, CFL, 1e30, t_end, 1, kscale=p["kscale"][idx], vfrag=p["vfrag"][idx],
+                              floor=floor)
+    g = g0.clone()
+    td = torch.zeros(w.cells, dtype=torch.float64, device=DEV)
+    v, unfinished = plan.rk_advance(g, td, t_end, CFL, 1e30, 1, kscale=ks, flux_floor=floor, count=True)
+    assert 0 < unfinished < w.cells and bool(torch.all((td > 0) & (td <= t_end)))
+    tg = td[idx].cpu().numpy()
+    h = np.diff(t.edges())
+    if prec == "fp64":
+        assert np.max(np.abs(tg - to) / to) <= 1e-6
+        gg = g.view(w.cells, -1)[idx].cpu().numpy()
+        assert _normwise(gg, go, np.tile(np.repeat(h, w.order + 1), (len(idx), 1))).max() <= 1e-11
+    else:
+        Y, _, Fe = O.rhs(cfg, gs, kscale=p["kscale"][idx], vfrag=p["vfrag"][idx])
+        d = np.diff(Fe, axis=1)
+        avg = gs.reshape(len(idx), w.bins, -1)[:, :, 0]
+        err = 2e-6 * np.abs(Y).max(axis=1)
+        fl = floor * np.abs(Fe).max(axis=1)
+        for c in range(len(idx)):
+            if np.any(np.abs(d[c] - fl[c]) <= err[c] + 1e-6 * fl[c]):
+                continue
+            keep = (d[c] > fl[c]) & (avg[c] > 0)
+            b = np.where(keep, h * avg[c] / np.where(keep, d[c], 1.0), np.inf)
+            near = keep & (b <= 2.0 * b.min())
+            tol = np.max(err[c] / d[c][near]) * 1.01 + 1e-14
+            assert abs(tg[c] - to[c]) <= tol * to[c], (c, tg[c], to[c], tol)
+    hd = torch.tensor(h, device=DEV)
+    m0 = (g0.view(w.cells, w.bins, -1)[:, :, 0] * hd).sum(1)
+    m1 = (g.view(w.cells, w.bins, -1)[:, :, 0] * hd).sum(1)
+    assert float(((m1 - m0).abs() / m0).max()) <= 1e-12

@@ -178,7 +178,7 @@ int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, doubl
 /*
  * gd_rk_step -- n_steps of SSP-RK3 (Eq. RK3) in place on g, with the scaling
  * limiter applied to the start state and after every stage (Sec. 3.2):
- *     y1 = L(g) step, y2 = 3/4 g + 1/4 (y1 + dt L(y1)), g = 1/3 g + 2/3 (y2 + dt L(y2)).
+ *     y1 = g + dt L(g), y2 = 3/4 g + 1/4 (y1 + dt L(y1)), g = 1/3 g + 2/3 (y2 + dt L(y2)).
  *  kscale      : device [n_cells] or NULL.
  *  dt          : time step (no CFL check is made on the device).
  *  violations  : host pointer or NULL; if non-NULL the call synchronises the

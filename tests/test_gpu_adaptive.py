@@ -337,3 +337,31 @@ def test_rk_advance_full_size_sampled(oracle, prec):
     m0 = (g0.view(w.cells, w.bins, -1)[:, :, 0] * hd).sum(1)
     m1 = (g.view(w.cells, w.bins, -1)[:, :, 0] * hd).sum(1)
     assert float(((m1 - m0).abs() / m0).max()) <= 1e-12
+
+
+def test_rk_advance_wide_group_in_uneven_batch(oracle):
+    """A batch holding P = 96 and P = 192 groups (the stage kernel instantiated for
+    the largest P serves both): FP64 sub-steps against the oracle, group by group."""
+    O = oracle
+    t1, c1 = _pair(O, "ball_k3")
+    t2, c2 = _pair(O, "big_k3")
+    g1, p1 = _states(O, c1, 12, seed=31)
+    g2, p2 = _states(O, c2, 9, seed=32)
+    g1, _ = O.limit(c1, g1)
+    g2, _ = O.limit(c2, g2)
+    t_end = 4.0 * CFL * max(O.cfl_dt(c1, g1), O.cfl_dt(c2, g2))
+    plan = G.Plan([t1, t2], [12, 9], precision="fp64")
+    gd = torch.tensor(np.concatenate([g1.reshape(-1), g2.reshape(-1)]), device=DEV)
+    td = torch.zeros(21, dtype=torch.float64, device=DEV)
+    v, unfinished = plan.rk_advance(gd, td, t_end, CFL, 1e30, 3, count=True)
+    o1, to1, _ = O.rk_adaptive(c1, g1, CFL, 1e30, t_end, 3)
+    o2, to2, _ = O.rk_adaptive(c2, g2, CFL, 1e30, t_end, 3)
+    r = gd.cpu().numpy()
+    tg = td.cpu().numpy()
+    to = np.concatenate([to1, to2])
+    assert np.max(np.abs(tg - to) / to) <= 1e-6
+    assert unfinished == np.count_nonzero(to < t_end) and v == 0
+    h1 = np.tile(np.repeat(np.diff(O.edges(c1)), c1.k + 1), (12, 1))
+    h2 = np.tile(np.repeat(np.diff(O.edges(c2)), c2.k + 1), (9, 1))
+    assert _normwise(r[:12 * c1.P].reshape(12, -1), o1, h1).max() <= 1e-11
+    assert _normwise(r[12 * c1.P:].reshape(9, -1), o2, h2).max() <= 1e-11

@@ -44,7 +44,10 @@
  *    ends);
  *  - the limiter with a non-positive cell average flattens the bin (gamma=0);
  *    a negative average is counted as a positivity violation.  The limiter is
- *    applied to the initial state and after every RK stage.
+ *    applied to the initial state and after every RK stage;
+ *  - the CFL bound of Eq. dt runs over the bins that lose mass (only those can
+ *    turn negative in a forward-Euler stage) and hold a positive average; the
+ *    per-cell steps take it at the start state of every sub-step.
  */
 #include <math.h>
 #include <omp.h>

@@ -199,31 +199,36 @@ def cpu_blas_reference(t, g0, ks, vf, w, cells=2048):
                  "matmul over g x g, unfolded tensor), not the oracle", "cells": m, "seconds": dt}
 
 
-def adaptive_bench(plan, g0, ks, w, n=10):
-    """Per-cell steps under the CFL bound (gd_rk_advance, launches issued one by one)
-    on the same plan and inputs: ms per sub-step and the adaptive stage kernel's
-    average duration, beside the eager fixed step (graph off)."""
+def adaptive_bench(plan, g0, ks, w, n=20, warm=20):
+    """Per-cell steps under the CFL bound (gd_rk_advance) on the same plan and inputs:
+    ms per sub-step with one sub-step captured as a HIP graph and with the launches
+    issued one by one, the adaptive stage kernel's average duration, and the fixed
+    step issued one by one beside them (each timed after its own warm-up)."""
     import torch
     g = g0.clone()
     t = torch.zeros(plan.n_cells, dtype=torch.float64, device=g.device)
     kw = dict(kscale=ks, flux_floor=1e-4 if plan.precision == "mixed" else 0.0)
-    plan.rk_advance(g, t, 1e30, 0.1, w.dt, 2, **kw)   # warm-up (allocates the step array)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    plan.rk_advance(g, t, 1e30, 0.1, w.dt, n, **kw)
-    torch.cuda.synchronize()
-    ms_adapt = (time.perf_counter() - t0) * 1e3 / n
+
+    def timed(fn):
+        fn(warm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn(n)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / n
+
+    advance = lambda m: plan.rk_advance(g, t, 1e30, 0.1, w.dt, m, **kw)
+    plan.use_graph(False)
+    ms_eager = timed(lambda m: plan.rk_step(g, w.dt, m, kscale=ks))
+    ms_adapt_eager = timed(advance)
+    plan.use_graph(True)
+    ms_adapt = timed(advance)
     plan.timing(True)
-    plan.rk_advance(g, t, 1e30, 0.1, w.dt, 4, **kw)
+    advance(4)
     sms, sl = plan.stage_time()     # 12 adaptive stages and the start limiter
     plan.timing(False)
-    plan.use_graph(False)
-    t0 = time.perf_counter()
-    plan.rk_step(g, w.dt, n, kscale=ks)
-    torch.cuda.synchronize()
-    ms_eager = (time.perf_counter() - t0) * 1e3 / n
-    plan.use_graph(True)
-    return {"ms_per_substep": ms_adapt, "eager_fixed_step_ms": ms_eager, "stage_kernel_ms": sms / max(1, sl),
+    return {"ms_per_substep": ms_adapt, "ms_per_substep_eager": ms_adapt_eager,
+            "eager_fixed_step_ms": ms_eager, "stage_kernel_ms": sms / max(1, sl),
             "cell_evals_per_s": 3.0 * plan.n_cells / (ms_adapt * 1e-3), "cfl": 0.1, "flux_floor": kw["flux_floor"]}
 
 

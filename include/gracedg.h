@@ -217,9 +217,12 @@ int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_
  *  violations : host pointer or NULL, as in gd_rk_step.
  *  unfinished : host pointer or NULL; if non-NULL, the number of cells with
  *               t[c] < t_end after the call.
- * Either host pointer makes the call synchronise the stream.  The launches are
- * issued one by one (no graph).  The first call on a plan allocates a per-cell step
- * array (synchronous).
+ * Either host pointer makes the call synchronise the stream.  With graphs on
+ * (gd_plan_use_graph) one sub-step (three contractions and three stage kernels) is
+ * captured into a HIP graph and replayed n_substeps times; it is captured again when
+ * g, kscale, t, t_end, cfl, dt_max, flux_floor or the variant change.  Off, or while
+ * timing, the launches are issued one by one.  The first call on a plan allocates a
+ * per-cell step array (synchronous).
  */
 int gd_rk_advance(gd_plan* plan, double* g, const double* kscale, double* t, double t_end, double cfl,
                   double dt_max, double flux_floor, int n_substeps, long long* violations, long long* unfinished);

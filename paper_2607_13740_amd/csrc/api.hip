@@ -550,6 +550,15 @@ struct StepGraph {
     double dt = 0.0;
 };
 
+// one captured sub-step of gd_rk_advance and the arguments it was captured with
+struct SubstepGraph {
+    hipGraphExec_t exec = nullptr;
+    const double* g = nullptr;
+    const double* kscale = nullptr;
+    const double* t = nullptr;
+    double t_end = 0.0, cfl = 0.0, dt_max = 0.0, floor = 0.0;
+};
+
 struct gd_plan {
     std::vector<Group> groups;
     int prec = GD_PREC_FP64;
@@ -566,6 +575,7 @@ struct gd_plan {
     double exec_flops = 0.0;                // MFMA flops one contraction launch executes
     bool use_graph = true;
     StepGraph graph;
+    SubstepGraph sgraph;
     double* y1 = nullptr;
     double* y2 = nullptr;
     unsigned long long* viol = nullptr;
@@ -585,6 +595,8 @@ struct gd_plan {
     {
         if (graph.exec) (void)hipGraphExecDestroy(graph.exec);
         graph = StepGraph{};
+        if (sgraph.exec) (void)hipGraphExecDestroy(sgraph.exec);
+        sgraph = SubstepGraph{};
     }
     ~gd_plan()
     {
@@ -1067,9 +1079,46 @@ extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double d
     return GD_OK;
 }
 
+// the six launches of one sub-step with per-cell steps
+static int substep_launches(gd_plan* pl, hipStream_t s, double* g, const double* kscale, double dt_max,
+                            const AdaptArgs& ad)
+{
+    const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
+    int rc;
+    if ((rc = contract(pl, s, g))) return rc;
+    if ((rc = stage(pl, s, 1, 1, split, kscale, g, g, pl->y1, dt_max, nullptr, nullptr, &ad))) return rc;
+    if ((rc = contract(pl, s, pl->y1))) return rc;
+    if ((rc = stage(pl, s, 2, 1, split, kscale, g, pl->y1, pl->y2, dt_max, nullptr, nullptr, &ad))) return rc;
+    if ((rc = contract(pl, s, pl->y2))) return rc;
+    return stage(pl, s, 3, 1, split, kscale, g, pl->y2, g, dt_max, nullptr, nullptr, &ad);
+}
+
+// capture one sub-step on the plan's private stream (nothing runs while capturing)
+static int capture_substep(gd_plan* pl, double* g, const double* kscale, double dt_max, const AdaptArgs& ad)
+{
+    if (pl->sgraph.exec) (void)hipGraphExecDestroy(pl->sgraph.exec);
+    pl->sgraph = SubstepGraph{};
+    HIP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
+    int rc = substep_launches(pl, pl->cap, g, kscale, dt_max, ad);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(pl->cap, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(GD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(GD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    pl->sgraph = SubstepGraph{exec, g, kscale, ad.t, ad.t_end, ad.cfl, dt_max, ad.floor};
+    return GD_OK;
+}
+
 // Per-cell steps under the CFL bound (Eq. dt): n_sub sub-steps of SSP-RK3, each cell
-// with its own step, in the same six launches per sub-step as gd_rk_step (issued one
-// by one: the steps live on the device).
+// with its own step, in the same six launches per sub-step as gd_rk_step (the steps
+// live on the device); with graphs on, one sub-step is captured once per set of
+// arguments and replayed.
 extern "C" int gd_rk_advance(gd_plan* pl, double* g, const double* kscale, double* t, double t_end, double cfl,
                              double dt_max, double flux_floor, int n_substeps, long long* violations,
                              long long* unfinished)
@@ -1089,13 +1138,14 @@ extern "C" int gd_rk_advance(gd_plan* pl, double* g, const double* kscale, doubl
     if ((rc = launch_fill_u64(pl->viol, 1, s))) return rc;
     if ((rc = stage(pl, s, -1, 1, split, kscale, nullptr, g, nullptr, dt_max, nullptr))) return rc;
     const AdaptArgs ad{cfl, t_end, flux_floor, t, pl->dtc};
+    const bool graph = pl->use_graph && !pl->timing && n_substeps > 0;
+    const SubstepGraph& G = pl->sgraph;
+    if (graph && !(G.exec && G.g == g && G.kscale == kscale && G.t == t && G.t_end == t_end && G.cfl == cfl &&
+                   G.dt_max == dt_max && G.floor == flux_floor))
+        if ((rc = capture_substep(pl, g, kscale, dt_max, ad))) return rc;
     for (int n = 0; n < n_substeps; ++n) {
-        if ((rc = contract(pl, s, g))) return rc;
-        if ((rc = stage(pl, s, 1, 1, split, kscale, g, g, pl->y1, dt_max, nullptr, nullptr, &ad))) return rc;
-        if ((rc = contract(pl, s, pl->y1))) return rc;
-        if ((rc = stage(pl, s, 2, 1, split, kscale, g, pl->y1, pl->y2, dt_max, nullptr, nullptr, &ad))) return rc;
-        if ((rc = contract(pl, s, pl->y2))) return rc;
-        if ((rc = stage(pl, s, 3, 1, split, kscale, g, pl->y2, g, dt_max, nullptr, nullptr, &ad))) return rc;
+        if (graph) HIP_TRY(hipGraphLaunch(pl->sgraph.exec, s));
+        else if ((rc = substep_launches(pl, s, g, kscale, dt_max, ad))) return rc;
     }
     if (unfinished) {
         if ((rc = launch_fill_u64(pl->below, 1, s))) return rc;

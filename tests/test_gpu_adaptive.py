@@ -401,3 +401,30 @@ def test_constant_kernel_eoc_at_paper_size(oracle):
     for k in range(1, 5):
         assert eoc[k] > k + plus - 0.5, (k, eoc)
         assert ec[(k, 40)] < ec[(k - 1, 40)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk_advance_graph_replays_match_eager(oracle, prec):
+    """The captured sub-step (graphs on) against the launches issued one by one
+    (graphs off), bit for bit, over several calls: replays of one capture with eager
+    work and synchronisations between them, then a new end time (a new capture)."""
+    O = oracle
+    C = 40
+    t, cfg, g, ks, t_end = _case(O, "ball_k2", C, seed=19)
+    floor = 0.0 if prec == "fp64" else 1e-4
+    ksd = torch.tensor(ks, device=DEV)
+    runs = {}
+    for graph in (True, False):
+        plan = G.Plan(t, C, precision=prec)
+        plan.use_graph(graph)
+        gd = torch.tensor(g, device=DEV).view(-1)
+        td = torch.zeros(C, dtype=torch.float64, device=DEV)
+        out = []
+        for call, te in enumerate((t_end, t_end, t_end, 2.0 * t_end)):
+            plan.rk_advance(gd, td, te, CFL, 1e30, 2, kscale=ksd, flux_floor=floor)
+            scratch = plan.collision_rhs(gd, kscale=ksd)     # eager work between replays
+            torch.cuda.synchronize()
+            out.append((gd.clone(), td.clone(), scratch.clone()))
+        runs[graph] = out
+    for (ga, ta, sa), (gb, tb, sb) in zip(runs[True], runs[False]):
+        assert torch.equal(ga, gb) and torch.equal(ta, tb) and torch.equal(sa, sb)

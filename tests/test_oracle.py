@@ -288,6 +288,95 @@ def test_truncated_flux_brute_force(oracle, kernel, frag, conservative, vfrag):
         assert errs[1] < 2e-3 and errs[1] < 0.2 * errs[0] + 1e-12, (x, errs, ex)
 
 
+# ------------------------------------------------ sharp collision outcome by brute force
+def _ballistic_speed(u, v):
+    return u ** (-1 / 6) + v ** (-1 / 6)
+
+
+def _brute_flux_sharp(cfg, coeffs, x, vfrag, reverse=False):
+    """Eqs. Fcoagtrun + Ffragtrun for the ballistic kernel with the sharp outcome: a
+    pair fragments iff dv(u,v) = u^-1/6 + v^-1/6 > v_frag (coagulates otherwise), with
+    the destructive power law written out here (b = A w^alpha on [x_min, u+v]).
+    Adaptive quadrature split at bin edges and at the curve dv = v_frag, where
+    v = (v_frag - u^-1/6)^-6.  reverse=True swaps the outcome (a planted mistake)."""
+    e = np.array([cfg.xmin * (cfg.xmax / cfg.xmin) ** (j / cfg.N) for j in range(cfg.N + 1)])
+    co = coeffs.reshape(cfg.N, cfg.k + 1)
+
+    def g(y):
+        j = min(max(int(np.searchsorted(e, y, side="right")) - 1, 0), cfg.N - 1)
+        return float(npleg.legval(2.0 * (y - 0.5 * (e[j] + e[j + 1])) / (e[j + 1] - e[j]), co[j]))
+
+    K = lambda u, v: (u ** (1 / 3) + v ** (1 / 3)) ** 2 * _ballistic_speed(u, v)
+    be = 2.0 + cfg.alpha
+    D = lambda S: S ** be - cfg.xmin ** be
+    above = lambda u, v: (u + v) * ((u + v) ** be - x ** be) / D(u + v) if x < u + v else 0.0
+    below = lambda u, v: (u + v) * (min(x, u + v) ** be - cfg.xmin ** be) / D(u + v)
+    frag = (lambda u, v: _ballistic_speed(u, v) < vfrag) if reverse else (lambda u, v: _ballistic_speed(u, v) > vfrag)
+    vmax = (lambda u: cfg.xmax - u + cfg.xmin) if cfg.conservative else (lambda u: cfg.xmax)
+
+    def curve(u):
+        a = vfrag - u ** (-1 / 6)
+        return a ** -6.0 if a > 0 else np.inf
+
+    def inner(u, lo, f):
+        hi = vmax(u)
+        if hi <= lo:
+            return 0.0
+        pts = sorted(p for p in list(e) + [curve(u)] if lo < p < hi)
+        return integrate.quad(f, lo, hi, points=pts or None, epsabs=0, epsrel=1e-11, limit=400)[0]
+
+    pos = lambda u: inner(u, x - u + cfg.xmin, lambda v: g(v) * K(u, v) * (
+        above(u, v) / (v * (u + v)) if frag(u, v) else 1.0 / v))
+    neg = lambda u: inner(u, cfg.xmin, lambda v: g(v) * K(u, v) * below(u, v) / (v * (u + v)) if frag(u, v) else 0.0)
+    pts = [p for p in e if cfg.xmin < p < x] + [x + cfg.xmin - p for p in e if cfg.xmin < x + cfg.xmin - p < x]
+    F = integrate.quad(lambda u: g(u) * pos(u), cfg.xmin, x, points=sorted(set(pts)) or None,
+                       epsabs=0, epsrel=1e-10, limit=400)[0]
+    pts = [p for p in e if x < p < cfg.xmax]
+    if cfg.conservative:
+        pts += [cfg.xmax + cfg.xmin - p for p in e if x < cfg.xmax + cfg.xmin - p < cfg.xmax]
+    F -= integrate.quad(lambda u: g(u) * neg(u), x, cfg.xmax, points=sorted(set(pts)) or None,
+                        epsabs=0, epsrel=1e-10, limit=400)[0]
+    return F
+
+
+@pytest.mark.parametrize("x", [0.35, 1.7, 6.0])
+def test_sharp_threshold_brute_force(oracle, x):
+    """The sharp outcome split at an intermediate threshold: on [0.1, 10] the relative
+    speed u^-1/6 + v^-1/6 runs from 1.36 to 2.94, so v_frag = 2 puts the curve
+    dv = v_frag through the middle of the domain (through (1, 1)) and every flux
+    mixes coagulating and fragmenting pairs.  The nested Gauss sums with the
+    pointwise outcome converge (algebraically: the integrand jumps across the curve
+    inside Gauss pieces) to the brute-force double integral, while the swapped outcome
+    gives an O(1) different flux."""
+    O = oracle
+    rng = np.random.default_rng(7)
+    base = dict(N=3, k=2, xmin=0.1, xmax=10.0, kernel="ballistic", frag="powerlaw", conservative=True, vfrag=2.0)
+    coeffs = rng.uniform(0.2, 1.0, size=9) * np.array([1, 0.5, 0.2] * 3)
+    coeffs = O.limit(_cfg(O, **base), coeffs)[0].reshape(-1)
+    cfg = _cfg(O, **base)
+    ex = _brute_flux_sharp(cfg, coeffs, x, 2.0)
+    swapped = _brute_flux_sharp(cfg, coeffs, x, 2.0, reverse=True)
+    errs = [abs(O.flux_points(_cfg(O, Q=Q, **base), coeffs, [x])[0] - ex) / abs(ex) for Q in (6, 48)]
+    assert errs[1] < 5e-3 and errs[1] < 0.5 * errs[0], (x, errs)
+    F48 = O.flux_points(_cfg(O, Q=48, **base), coeffs, [x])[0]
+    assert abs(F48 - swapped) > 0.2 * abs(ex), (x, F48, swapped)
+
+
+def test_sharp_threshold_tie_coagulates(oracle):
+    """A pair fragments only when its relative speed strictly exceeds the threshold: at
+    v_frag equal to the pair's own speed it coagulates, one ulp below it fragments."""
+    import math
+    O = oracle
+    cfg = _cfg(O, N=4, k=1, xmin=0.1, xmax=10.0, kernel="ballistic", frag="powerlaw", conservative=True)
+    for u, v in [(0.3, 0.7), (1.0, 1.0), (2.5, 0.11)]:
+        dv = 1.0 * (math.pow(u, -1.0 / 6.0) + math.pow(v, -1.0 / 6.0))
+        K = (u ** (1 / 3) + v ** (1 / 3)) ** 2 * dv
+        kc, kf, _ = O.rates(cfg, u, v, vfrag=dv)
+        assert kc == pytest.approx(K, rel=1e-14) and kf == 0.0
+        kc, kf, _ = O.rates(cfg, u, v, vfrag=np.nextafter(dv, 0.0))
+        assert kc == 0.0 and kf == pytest.approx(K, rel=1e-14)
+
+
 # --------------------------------------------------------------- structural identities
 def _lognormal_cfg(O, **kw):
     base = dict(N=12, k=2, xmin=1e-4, xmax=1e8, kernel="ballistic", frag="powerlaw", conservative=True,

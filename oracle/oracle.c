@@ -37,8 +37,10 @@
  *    fragments with these weights (no sharp split);
  *  - the general breakage law (Eq. break with Eq. mfrag): a remnant at or below
  *    x_min is outside the domain and contributes to neither inner integral; the
- *    volume moments use the same node rule as every other law (F at the Gauss
- *    nodes of the bin);
+ *    fragmentation part of its volume moments takes the reordered x-integral of
+ *    App. B with one Delta x in both parts of the flux and the positive part's
+ *    lower v-limit carried over to x (x <= u + v - x_min); the coagulation part
+ *    and every other law use F at the Gauss nodes of the bin;
  *  - per-cell v_frag between tabulated levels: the raw flux vector is the
  *    linear blend of the two neighbouring level evaluations (clamped at the
  *    ends);
@@ -279,7 +281,7 @@ static int composite(const ocfg* c, const double* e, double a, double b,
  *            [Kc/v + Kf Pw/(v(u+v))]
  *      - sum_{u in G[x,xmax]} wu g(u) sum_{v in G[xmin, Vmax(u)]} wv g(v) Kf Nw/(v(u+v))
  * with Vmax(u) = xmax - u + xmin (conservative) or xmax.                          */
-static double flux_at(const ocfg* c, const ocell* p, const double* e, const double* g, double x,
+static double flux_at(const ocfg* c, const ocell* p, const double* e, const double* g, double x, int with_frag,
                       double* ux, double* uw, int* ub, double* vx, double* vw, int* vb)
 {
     double F = 0.0;
@@ -295,13 +297,14 @@ static double flux_at(const ocfg* c, const ocell* p, const double* e, const doub
             double v = vx[b];
             double kc, kf;
             kernel_split(c, p, u, v, &kc, &kf);
+            if (!with_frag) kf = 0.0;
             double integrand = kc / v;
             if (kf != 0.0) integrand += kf * Pw(c, x, u, v) / (v * (u + v));
             inner += vw[b] * g_at(c, e, g, vb[b], v) * integrand;
         }
         F += uw[a] * gu * inner;
     }
-    if (c->frag == OF_NONE) return F;
+    if (c->frag == OF_NONE || !with_frag) return F;
     /* negative part: u > x */
     nu = composite(c, e, x, c->xmax, ux, uw, ub);
     for (int a = 0; a < nu; ++a) {
@@ -322,6 +325,87 @@ static double flux_at(const ocfg* c, const ocell* p, const double* e, const doub
     return F;
 }
 
+/* ------------------------------- reordered volume integral of App. B (general law)
+ * With the remnant delta(w - m_left) of Eq. break the fragmentation flux jumps in x
+ * wherever x crosses a remnant mass, so the volume moment int_{I_j} F dphi_i/dx dx is
+ * not taken at Gauss nodes in x.  Exchanging the order (App. B) puts x innermost:
+ * for every node pair (u,v) of the outer sums -- u over the whole domain, v over
+ * [x_min, Vmax(u)] -- the x-integrals over I_j cut to the ranges where each term of
+ * the inner integrals (Eqs. inte1/inte2) is active run with their own Q-point rule:
+ *   positive flux (u < x, and x - u + x_min <= v, i.e. x <= u + v - x_min):
+ *     T1  + int_{I_j ^ [u, min(m_frag, u+v-x_min)]}  A/(2+a) (m_frag^(2+a) - x^(2+a))
+ *     T4  + int_{I_j ^ [u, min(m_left, u+v-x_min)]}  m_left
+ *   negative flux (x < u):
+ *     T2  - int_{I_j ^ [x_min, u]}                  A/(2+a) (x^(2+a) - x_min^(2+a))
+ *     T3  + int_{I_j ^ [m_frag, u]}                 A/(2+a) (x^(2+a) - m_frag^(2+a))
+ *     T5  - int_{I_j ^ [m_left, u]}                 m_left   (a remnant above x_min)
+ * each times dphi_i/dx and K_frag g(u) g(v) / (v (u+v)).  The v-limits are those of
+ * Eq. Ffragtrun with the same Delta x in both parts (the printed reordered formula
+ * mixes x_max and x_max - u + x_min), and the cap x <= u + v - x_min carries the
+ * lower v-limit of the positive part over to x.  A fragment mass at or below x_min
+ * puts the whole fragment mass below every x: T1 and T3 vanish and T2 becomes
+ * - int_{I_j ^ [x_min, u]} m_frag.  Only the fragmentation part is reordered; the
+ * coagulation part of the volume moments keeps the node rule of Sec. 3.3.          */
+enum { APPB_T1, APPB_T2, APPB_T2_ALL, APPB_T3, APPB_T4, APPB_T5 };
+
+static void appb_piece(const ocfg* c, const double* e, int j, double a, double b, int term, double mf,
+                       double ml, double coef, double* V)
+{
+    double lo = (a > e[j]) ? a : e[j];
+    double hi = (b < e[j + 1]) ? b : e[j + 1];
+    if (!(hi > lo)) return;
+    double h = e[j + 1] - e[j], mid = 0.5 * (e[j] + e[j + 1]);
+    double cen = 0.5 * (lo + hi), half = 0.5 * (hi - lo);
+    double be = 2.0 + c->alpha, An = (mf > c->xmin) ? general_norm(c, mf) : 0.0;
+    for (int q = 0; q < c->Q; ++q) {
+        double x = cen + half * c->s[q], f;
+        switch (term) {
+        case APPB_T1: f = An * (pow(mf, be) - pow(x, be)); break;
+        case APPB_T2: f = -An * (pow(x, be) - pow(c->xmin, be)); break;
+        case APPB_T2_ALL: f = -mf; break;
+        case APPB_T3: f = An * (pow(x, be) - pow(mf, be)); break;
+        case APPB_T4: f = ml; break;
+        default: f = -ml; break;
+        }
+        double xi = 2.0 * (x - mid) / h, wf = coef * half * c->w[q] * f * 2.0 / h;
+        for (int i = 1; i <= c->k; ++i) V[j * c->k + (i - 1)] += wf * legendre_d(i, xi);
+    }
+}
+
+/* adds the fragmentation part of V_{j,i} (j < N, 1 <= i <= k) to V [N*k] */
+static void vol_frag_reordered(const ocfg* c, const ocell* p, const double* e, const double* g, double* V,
+                               double* ux, double* uw, int* ub, double* vx, double* vw, int* vb)
+{
+    int nu = composite(c, e, c->xmin, c->xmax, ux, uw, ub);
+    for (int a = 0; a < nu; ++a) {
+        double u = ux[a];
+        double gu = g_at(c, e, g, ub[a], u);
+        double vmax = c->conservative ? (c->xmax - u + c->xmin) : c->xmax;
+        int nv = composite(c, e, c->xmin, vmax, vx, vw, vb);
+        for (int b = 0; b < nv; ++b) {
+            double v = vx[b];
+            double kc, kf;
+            kernel_split(c, p, u, v, &kc, &kf);
+            if (kf == 0.0) continue;
+            double coef = uw[a] * vw[b] * gu * g_at(c, e, g, vb[b], v) * kf / (v * (u + v));
+            double mf = mfrag_general(u, v), ml = (u + v) - mf, top = u + v - c->xmin;
+            for (int j = 0; j < c->N; ++j) {
+                if (mf > c->xmin) {
+                    appb_piece(c, e, j, u, (mf < top) ? mf : top, APPB_T1, mf, ml, coef, V);
+                    appb_piece(c, e, j, c->xmin, u, APPB_T2, mf, ml, coef, V);
+                    appb_piece(c, e, j, mf, u, APPB_T3, mf, ml, coef, V);
+                } else {
+                    appb_piece(c, e, j, c->xmin, u, APPB_T2_ALL, mf, ml, coef, V);
+                }
+                if (ml > c->xmin) {
+                    appb_piece(c, e, j, u, (ml < top) ? ml : top, APPB_T4, mf, ml, coef, V);
+                    appb_piece(c, e, j, ml, u, APPB_T5, mf, ml, coef, V);
+                }
+            }
+        }
+    }
+}
+
 /* -------------------------------------------- raw flux vector of one cell (O7)
  * Y = [F(e_1) .. F(e_{N-1}), (F(e_N) if non-conservative),
  *      V_{0,1..k}, V_{1,1..k}, ..., V_{N-1,1..k}]
@@ -339,21 +423,26 @@ static void raw_flux(const ocfg* c, const ocell* p, const double* e, const doubl
     int* ub = malloc(sizeof(int) * maxn);
     int* vb = malloc(sizeof(int) * maxn);
 
-    for (int j = 0; j <= c->N; ++j) Fe[j] = flux_at(c, p, e, g, e[j], ux, uw, ub, vx, vw, vb);
+    for (int j = 0; j <= c->N; ++j) Fe[j] = flux_at(c, p, e, g, e[j], 1, ux, uw, ub, vx, vw, vb);
     int o = 0;
     for (int j = 1; j < c->N; ++j) Y[o++] = Fe[j];
     if (!c->conservative) Y[o++] = Fe[c->N];
+    /* the general law's fragmentation part of the volume moments follows App. B */
+    const int reorder = (c->frag == OF_GENERAL);
+    double* Vr = calloc((size_t)c->N * (c->k > 0 ? c->k : 1), sizeof(double));
+    if (reorder && c->k > 0) vol_frag_reordered(c, p, e, g, Vr, ux, uw, ub, vx, vw, vb);
     for (int j = 0; j < c->N; ++j) {
         double h = e[j + 1] - e[j], mid = 0.5 * (e[j] + e[j + 1]);
         double Fn[64];
         for (int t = 0; t < c->Q; ++t)
-            Fn[t] = flux_at(c, p, e, g, mid + 0.5 * h * c->s[t], ux, uw, ub, vx, vw, vb);
+            Fn[t] = flux_at(c, p, e, g, mid + 0.5 * h * c->s[t], !reorder, ux, uw, ub, vx, vw, vb);
         for (int i = 1; i <= c->k; ++i) {
             double V = 0.0;
             for (int t = 0; t < c->Q; ++t) V += c->w[t] * legendre_d(i, c->s[t]) * Fn[t];
-            Y[o++] = V;
+            Y[o++] = V + Vr[j * c->k + (i - 1)];
         }
     }
+    free(Vr);
     free(ux); free(uw); free(vx); free(vw); free(ub); free(vb);
 }
 
@@ -546,7 +635,7 @@ int oracle_flux_points(const ocfg* c, const double* g, double kscale, double vfr
     int* ub = malloc(sizeof(int) * maxn);
     int* vb = malloc(sizeof(int) * maxn);
     ocell p = { vfrag, kscale };
-    for (int t = 0; t < npts; ++t) F[t] = flux_at(c, &p, e, g, xs[t], ux, uw, ub, vx, vw, vb);
+    for (int t = 0; t < npts; ++t) F[t] = flux_at(c, &p, e, g, xs[t], 1, ux, uw, ub, vx, vw, vb);
     free(ux); free(uw); free(vx); free(vw); free(ub); free(vb); free(e);
     return 0;
 }

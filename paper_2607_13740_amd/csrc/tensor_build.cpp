@@ -219,13 +219,15 @@ double mass_below(const Ctx& c, double x, double u, double v)
 }
 
 // Quadratic form of F(x) for every threshold level: B[r][p][q] with F = sum B g_p g_q.
-void flux_form(const Ctx& c, double x, std::vector<double>& B, std::vector<Node>& un,
+// with_frag = false keeps the coagulation part only (the general law's volume
+// moments take their fragmentation part from the reordered integral below).
+void flux_form(const Ctx& c, double x, bool with_frag, std::vector<double>& B, std::vector<Node>& un,
                std::vector<Node>& vn, std::vector<double>& acc)
 {
     const TensorSpec& sp = *c.sp;
     const int N = sp.bins, K1 = sp.order + 1, P = N * K1;
     const int R = std::max(1, int(sp.levels.size()));
-    const bool frag = sp.frag != GD_FRAG_NONE;
+    const bool frag = sp.frag != GD_FRAG_NONE && with_frag;
     const bool maxwell = sp.kernel == GD_KERNEL_MAXWELL;
     std::fill(B.begin(), B.end(), 0.0);
     double Pu[16], Pv[16];
@@ -256,6 +258,7 @@ void flux_form(const Ctx& c, double x, std::vector<double>& B, std::vector<Node>
             double h = c.e[v.bin + 1] - c.e[v.bin];
             legendre_all(sp.order, 2.0 * (v.x - 0.5 * (c.e[v.bin] + c.e[v.bin + 1])) / h, Pv, nullptr);
             const double above = frag ? mass_above(c, x, u.x, v.x) / (v.x * (u.x + v.x)) : 0.0;
+            const bool split = sp.frag != GD_FRAG_NONE;   // sharp outcome decided per pair
             double coag, fr = 0.0, dv = 0.0;
             if (maxwell) {
                 const double K = maxwell_rate(sp, u.x, v.x);
@@ -265,12 +268,12 @@ void flux_form(const Ctx& c, double x, std::vector<double>& B, std::vector<Node>
                 const double K = kernel_value(sp, u.x, v.x);
                 coag = K / v.x;
                 fr = K * above;
-                if (frag) dv = rel_speed(sp, u.x, v.x);
+                if (split) dv = rel_speed(sp, u.x, v.x);
             }
             for (int r = 0; r < R; ++r) {
                 double val;
                 if (maxwell) val = coag + (frag ? fr * c.p_frag[r] : 0.0);
-                else val = (!frag || dv <= sp.levels[r]) ? coag : fr;
+                else val = (!split || dv <= sp.levels[r]) ? coag : fr;
                 if (val == 0.0) continue;
                 double* ar = &acc[size_t(r) * P + v.bin * K1];
                 for (int b = 0; b < K1; ++b) ar[b] += v.w * Pv[b] * val;
@@ -302,6 +305,115 @@ void flux_form(const Ctx& c, double x, std::vector<double>& B, std::vector<Node>
         }
         close_u(u);
     }
+}
+
+// ---------------------------------------------------------------------------
+// General law (Eq. break with Eq. mfrag): the fragmentation part of the volume
+// moments int_{I_j} F dphi_i/dx dx with the order of integration exchanged (App. B).
+// The remnant makes F jump in x, so instead of F at Gauss nodes in x, every node pair
+// (u, v) of the outer sums -- u over the whole domain, v over [x_min, Vmax(u)] with the
+// Delta x of the flux -- integrates the x-ranges on which each piece of the inner
+// integrals is active (Eqs. inte1/inte2), with a Q-point rule per range:
+//   u < x <= u + v - x_min (positive flux; the upper bound is the lower v-limit of
+//   Eq. Ffragtrun read for x):  power law above x while x < m_frag, remnant while x < m_left;
+//   x < u (negative flux): power law between x_min and min(x, m_frag), remnant once
+//   m_left (> x_min) lies below x.
+// A fragment mass at or below x_min leaves no power law inside the domain: the whole
+// fragment mass counts below every x.
+void general_x_integrals(const Ctx& c, double u, double v, std::vector<double>& X)
+{
+    const TensorSpec& sp = *c.sp;
+    const int N = sp.bins, k = sp.order, Q = int(c.s.size());
+    std::fill(X.begin(), X.end(), 0.0);
+    const double xm = sp.x_min, S = u + v, mf = general_frag_mass(u, v), rem = S - mf;
+    const double cap = S - xm;
+    const bool inside = mf > xm;
+    const double nrm = inside ? mf / (std::pow(mf, c.beta) - c.xmin_beta) : 0.0;   // A/(2+alpha)
+    const double mfb = inside ? std::pow(mf, c.beta) : 0.0;
+    double dP[16], Pv[16];
+    // add int_{[lo,hi] ^ I_j} f(x) dphi_i/dx dx for every bin the range meets
+    auto range = [&](double lo, double hi, auto f) {
+        if (!(hi > lo)) return;
+        int j = int(std::upper_bound(c.e.begin(), c.e.end(), lo) - c.e.begin()) - 1;
+        j = std::max(0, j);
+        for (; j < N && c.e[j] < hi; ++j) {
+            const double a = std::max(lo, c.e[j]), b = std::min(hi, c.e[j + 1]);
+            if (!(b > a)) continue;
+            const double h = c.e[j + 1] - c.e[j], mid = 0.5 * (c.e[j] + c.e[j + 1]);
+            const double cm = 0.5 * (a + b), hw = 0.5 * (b - a);
+            for (int t = 0; t < Q; ++t) {
+                const double x = cm + hw * c.s[t];
+                legendre_all(k, 2.0 * (x - mid) / h, Pv, dP);
+                const double wf = hw * c.w[t] * f(x) * (2.0 / h);
+                for (int i = 1; i <= k; ++i) X[size_t(j) * k + i - 1] += wf * dP[i];
+            }
+        }
+    };
+    if (inside) {
+        range(u, std::min(mf, cap), [&](double x) { return nrm * (mfb - std::pow(x, c.beta)); });
+        range(xm, u, [&](double x) { return -nrm * (std::pow(x, c.beta) - c.xmin_beta); });
+        range(mf, u, [&](double x) { return nrm * (std::pow(x, c.beta) - mfb); });
+    } else {
+        range(xm, u, [&](double) { return -mf; });
+    }
+    if (rem > xm) {
+        range(u, std::min(rem, cap), [&](double) { return rem; });
+        range(rem, u, [&](double) { return -rem; });
+    }
+}
+
+// Adds the reordered fragmentation part to the volume rows (vbase + j*k + i - 1) of
+// every level.  Threads own disjoint sets of u bins (the p = (l, a) index of T), so the
+// summation order of every entry is fixed.
+void general_volume(const Ctx& c, HostTensor& out, int vbase)
+{
+    const TensorSpec& sp = *c.sp;
+    const int N = sp.bins, k = sp.order, K1 = k + 1, P = N * K1, NO = out.n_out;
+    const int R = std::max(1, int(sp.levels.size()));
+    const bool maxwell = sp.kernel == GD_KERNEL_MAXWELL;
+    std::atomic<int> next{0};
+    auto worker = [&]() {
+        std::vector<Node> un, vn;
+        std::vector<double> X(size_t(N) * k);
+        double Pu[16], Pv[16];
+        for (int l = next++; l < N; l = next++) {
+            pieces(c, c.e[l], c.e[l + 1], un);
+            for (const Node& u : un) {
+                const double hu = c.e[u.bin + 1] - c.e[u.bin];
+                legendre_all(k, 2.0 * (u.x - 0.5 * (c.e[u.bin] + c.e[u.bin + 1])) / hu, Pu, nullptr);
+                const double vmax = sp.conservative ? sp.x_max - u.x + sp.x_min : sp.x_max;
+                pieces(c, sp.x_min, vmax, vn);
+                for (const Node& v : vn) {
+                    const double hv = c.e[v.bin + 1] - c.e[v.bin];
+                    legendre_all(k, 2.0 * (v.x - 0.5 * (c.e[v.bin] + c.e[v.bin + 1])) / hv, Pv, nullptr);
+                    general_x_integrals(c, u.x, v.x, X);
+                    const double K = maxwell ? maxwell_rate(sp, u.x, v.x) : kernel_value(sp, u.x, v.x);
+                    const double dv = maxwell ? 0.0 : rel_speed(sp, u.x, v.x);
+                    const double w = u.w * v.w * K / (v.x * (u.x + v.x));
+                    for (int r = 0; r < R; ++r) {
+                        const double pf = maxwell ? c.p_frag[r] : (dv > sp.levels[r] ? 1.0 : 0.0);
+                        if (pf == 0.0) continue;
+                        for (int o = 0; o < N * k; ++o) {
+                            const double val = w * pf * X[o];
+                            if (val == 0.0) continue;
+                            double* rowT = &out.T[(size_t(r) * NO + vbase + o) * P * P];
+                            for (int a = 0; a < K1; ++a) {
+                                double* dst = rowT + size_t(u.bin * K1 + a) * P + v.bin * K1;
+                                const double f = val * Pu[a];
+                                for (int b = 0; b < K1; ++b) dst[b] += f * Pv[b];
+                            }
+                        }
+                    }
+                }
+            }
+        }
+    };
+    unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    nth = std::min<unsigned>(nth, unsigned(N));
+    std::vector<std::thread> th;
+    for (unsigned i = 1; i < nth; ++i) th.emplace_back(worker);
+    worker();
+    for (auto& x : th) x.join();
 }
 
 } // namespace
@@ -347,7 +459,9 @@ void build_tensor(const TensorSpec& sp, HostTensor& out)
     out.edges = c.e;
     out.T.assign(size_t(R) * NO * P * P, 0.0);
 
-    // flux evaluation points and the rows they feed
+    // flux evaluation points and the rows they feed (edge fluxes with the whole flux;
+    // volume nodes without the general law's fragmentation part, which follows App. B)
+    const bool reorder = sp.frag == GD_FRAG_GENERAL && k > 0;
     struct Pt { double x; int row0; int nrow; double coef[16]; };
     std::vector<Pt> pts;
     int o = 0;
@@ -385,7 +499,7 @@ void build_tensor(const TensorSpec& sp, HostTensor& out)
         vn.reserve((N + 2) * Q);
         for (int gi = next++; gi < ngrp; gi = next++)
             for (int t = grp[gi]; t < grp[gi + 1]; ++t) {
-                flux_form(c, pts[t].x, B, un, vn, acc);
+                flux_form(c, pts[t].x, !(reorder && pts[t].row0 >= vbase), B, un, vn, acc);
                 for (int r = 0; r < R; ++r)
                     for (int i = 0; i < pts[t].nrow; ++i) {
                         const double cf = pts[t].coef[i];
@@ -401,6 +515,7 @@ void build_tensor(const TensorSpec& sp, HostTensor& out)
     for (unsigned i = 1; i < nth; ++i) th.emplace_back(worker);
     worker();
     for (auto& x : th) x.join();
+    if (reorder) general_volume(c, out, vbase);
 }
 
 } // namespace gd

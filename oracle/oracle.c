@@ -564,9 +564,17 @@ static double bin_min(int k, const double* gi)
     return m;
 }
 
-static long limit_cell(int N, int k, double* g)
+/* trace: NULL, or a running FNV-1a hash of the bins the limiter changes (gamma < 1),
+ * so that two runs can tell whether the limiter's active set differed */
+static void trace_mix(unsigned long long* h, unsigned long long v)
+{
+    *h = (*h ^ v) * 1099511628211ull;
+}
+
+static long limit_cell(int N, int k, double* g, unsigned long long* trace)
 {
     long viol = 0;
+    if (trace) trace_mix(trace, 0xFFFFFFFFull);   /* one mark per limiter call */
     for (int j = 0; j < N; ++j) {
         double* gi = g + j * (k + 1);
         double avg = gi[0];
@@ -581,6 +589,7 @@ static long limit_cell(int N, int k, double* g)
             gamma = (m < 0.0) ? avg / (avg - m) : 1.0;
             if (gamma > 1.0) gamma = 1.0;
         }
+        if (trace && gamma < 1.0) trace_mix(trace, (unsigned long long)j + 1ull);
         for (int i = 1; i <= k; ++i) gi[i] *= gamma;
     }
     return viol;
@@ -668,7 +677,7 @@ long oracle_limit(const ocfg* c, int C, double* g)
     if (check(c) || c->k > 4) return -1;
     int P = c->N * (c->k + 1);
     long viol = 0;
-    for (int cell = 0; cell < C; ++cell) viol += limit_cell(c->N, c->k, g + (size_t)cell * P);
+    for (int cell = 0; cell < C; ++cell) viol += limit_cell(c->N, c->k, g + (size_t)cell * P, NULL);
     return viol;
 }
 
@@ -676,31 +685,44 @@ long oracle_limit(const ocfg* c, int C, double* g)
  * every stage; returns the violations found.  Work arrays of P (y1, y2, L),
  * n_out (Y) and N+1 (fe) doubles. */
 static long rk3_cell(const ocfg* c, const double* e, double* gn, double ks, double vf, int nlev,
-                     const double* lev, double dt, double* y1, double* y2, double* L, double* Y, double* fe)
+                     const double* lev, double dt, double* y1, double* y2, double* L, double* Y, double* fe,
+                     unsigned long long* trace)
 {
     int P = c->N * (c->k + 1);
     long viol = 0;
     raw_flux_cell(c, e, gn, ks, vf, nlev, lev, Y, fe);
     assemble_L(c, e, Y, L);
     for (int t = 0; t < P; ++t) y1[t] = gn[t] + dt * L[t];
-    viol += limit_cell(c->N, c->k, y1);
+    viol += limit_cell(c->N, c->k, y1, trace);
 
     raw_flux_cell(c, e, y1, ks, vf, nlev, lev, Y, fe);
     assemble_L(c, e, Y, L);
     for (int t = 0; t < P; ++t) y2[t] = 0.75 * gn[t] + 0.25 * (y1[t] + dt * L[t]);
-    viol += limit_cell(c->N, c->k, y2);
+    viol += limit_cell(c->N, c->k, y2, trace);
 
     raw_flux_cell(c, e, y2, ks, vf, nlev, lev, Y, fe);
     assemble_L(c, e, Y, L);
     for (int t = 0; t < P; ++t) gn[t] = gn[t] / 3.0 + 2.0 / 3.0 * (y2[t] + dt * L[t]);
-    viol += limit_cell(c->N, c->k, gn);
+    viol += limit_cell(c->N, c->k, gn, trace);
     return viol;
 }
 
 /* n_steps of SSP-RK3 (Eq. RK3) with the limiter on the initial state and after
  * every stage.  g is [C][N(k+1)] in place. */
+long oracle_rk_trace(const ocfg* c, int C, double* g, const double* kscale, const double* vfrag,
+                     double vfrag_default, int nlev, const double* lev, double dt, int n_steps,
+                     unsigned long long* trace);
+
 long oracle_rk(const ocfg* c, int C, double* g, const double* kscale, const double* vfrag,
                double vfrag_default, int nlev, const double* lev, double dt, int n_steps)
+{
+    return oracle_rk_trace(c, C, g, kscale, vfrag, vfrag_default, nlev, lev, dt, n_steps, NULL);
+}
+
+/* oracle_rk that also hashes, per cell, every bin the limiter changes (trace [C], or NULL) */
+long oracle_rk_trace(const ocfg* c, int C, double* g, const double* kscale, const double* vfrag,
+                     double vfrag_default, int nlev, const double* lev, double dt, int n_steps,
+                     unsigned long long* trace)
 {
     if (check(c) || c->k > 4 || C < 0 || n_steps < 0) return -1;
     int P = c->N * (c->k + 1), no = n_out(c);
@@ -717,8 +739,10 @@ long oracle_rk(const ocfg* c, int C, double* g, const double* kscale, const doub
         double* fe = malloc(sizeof(double) * (c->N + 1));
         double ks = kscale ? kscale[cell] : 1.0;
         double vf = vfrag ? vfrag[cell] : vfrag_default;
-        viol += limit_cell(c->N, c->k, gn);
-        for (int n = 0; n < n_steps; ++n) viol += rk3_cell(c, e, gn, ks, vf, nlev, lev, dt, y1, y2, L, Y, fe);
+        unsigned long long* tr = trace ? trace + cell : NULL;
+        if (tr) *tr = 14695981039346656037ull;
+        viol += limit_cell(c->N, c->k, gn, tr);
+        for (int n = 0; n < n_steps; ++n) viol += rk3_cell(c, e, gn, ks, vf, nlev, lev, dt, y1, y2, L, Y, fe, tr);
         free(y1); free(y2); free(L); free(Y); free(fe);
     }
     free(e);
@@ -759,7 +783,7 @@ long oracle_rk_adaptive(const ocfg* c, int C, double* g, const double* kscale, c
         double* fe = malloc(sizeof(double) * (c->N + 1));
         double ks = kscale ? kscale[cell] : 1.0;
         double vf = vfrag ? vfrag[cell] : vfrag_default;
-        viol += limit_cell(c->N, c->k, gn);
+        viol += limit_cell(c->N, c->k, gn, NULL);
         for (int n = 0; n < n_sub; ++n) {
             double rem = t_end - t[cell];
             if (!(rem > 0.0)) break;
@@ -778,7 +802,7 @@ long oracle_rk_adaptive(const ocfg* c, int C, double* g, const double* kscale, c
             double dt = dt_max < rem ? dt_max : rem;
             if (cfl * B < dt) dt = cfl * B;
             if (!(dt > 0.0)) break;
-            viol += rk3_cell(c, e, gn, ks, vf, nlev, lev, dt, y1, y2, L, Y, fe);
+            viol += rk3_cell(c, e, gn, ks, vf, nlev, lev, dt, y1, y2, L, Y, fe, NULL);
             t[cell] = (dt == rem) ? t_end : t[cell] + dt;
         }
         free(y1); free(y2); free(L); free(Y); free(fe);

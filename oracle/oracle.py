@@ -56,12 +56,30 @@ class _Cfg(ctypes.Structure):
 _lib = None
 
 
-def _load():
+NATIVE_FLAGS = ["-O3", "-march=native", "-fopenmp"]
+
+
+def use_native() -> str:
+    """Compile the same source with -O3 -march=native for the host this runs on and use
+    that build from now on (the CPU-baseline timing; the tests keep the portable -O2
+    build).  Returns the compiler flags."""
+    global _lib
+    import tempfile
+    path = os.path.join(tempfile.gettempdir(), f"liboracle_native_{os.getpid()}.so")
+    subprocess.check_call(["gcc", *NATIVE_FLAGS, "-fPIC", "-shared", _SRC, "-o", path, "-lm"])
+    _lib = None
+    _load(path)
+    return " ".join(NATIVE_FLAGS)
+
+
+def _load(path=None):
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        lib = ctypes.CDLL(_LIB)
+        if path is None:
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+            path = _LIB
+        lib = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         cp = ctypes.POINTER(_Cfg)
         lib.oracle_set_threads.argtypes = [ctypes.c_int]
@@ -82,6 +100,9 @@ def _load():
         lib.oracle_rk.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp,
                                   ctypes.c_double, ctypes.c_int]
         lib.oracle_rk.restype = ctypes.c_long
+        lib.oracle_rk_trace.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp,
+                                        ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_ulonglong)]
+        lib.oracle_rk_trace.restype = ctypes.c_long
         lib.oracle_rk_adaptive.argtypes = [cp, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int, dp,
                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                            ctypes.c_int, dp]
@@ -215,6 +236,60 @@ def rk(cfg: Config, g, dt: float, n_steps: int, kscale=None, vfrag=None):
                           float(dt), int(n_steps))
     assert v >= 0
     return g, int(v)
+
+
+def advect(cfg: Config, g, vel, dt: float, dx: float, periodic: bool = True):
+    """Transport between the hydro cells of a row, the hydro half of operator splitting
+    (Sec. 5.2): every Legendre coefficient of bin j moves with the bin's velocity vel[j]
+    by first-order upwind finite volumes, Courant number c = vel[j] dt / dx (|c| <= 1):
+    g_c <- (1 - |c|) g_c + |c| g_up, up = c - 1 for vel >= 0 and c + 1 otherwise;
+    periodic wraps the row, otherwise nothing flows in at its ends."""
+    g = np.asarray(g, dtype=np.float64).reshape(-1, cfg.N, cfg.k + 1)
+    C = g.shape[0]
+    out = np.empty_like(g)
+    for c in range(C):
+        for j in range(cfg.N):
+            cj = vel[j] * dt / dx
+            a = abs(cj)
+            assert a <= 1.0
+            up = c - 1 if cj >= 0.0 else c + 1
+            if 0 <= up < C:
+                gu = g[up, j]
+            elif periodic:
+                gu = g[up % C, j]
+            else:
+                gu = np.zeros(cfg.k + 1)
+            out[c, j] = (1.0 - a) * g[c, j] + a * gu
+    return out.reshape(C, -1)
+
+
+def split_step(cfg: Config, g, vel, dx: float, dt: float, n_steps: int, kscale=None, vfrag=None,
+               periodic: bool = True):
+    """Strang splitting of transport and collisions: per step, transport over dt/2, one
+    SSP-RK3 step over dt (rk(): start limiter, limiter after every stage), transport over
+    dt/2.  Returns (g, violations)."""
+    g = np.asarray(g, dtype=np.float64).reshape(-1, cfg.P)
+    viol = 0
+    for _ in range(n_steps):
+        g = advect(cfg, g, vel, 0.5 * dt, dx, periodic)
+        g, v = rk(cfg, g, dt, 1, kscale=kscale, vfrag=vfrag)
+        viol += v
+        g = advect(cfg, g, vel, 0.5 * dt, dx, periodic)
+    return g, viol
+
+
+def rk_traced(cfg: Config, g, dt: float, n_steps: int, kscale=None, vfrag=None):
+    """rk() that also returns, per cell, a hash of every (limiter call, bin) where the
+    limiter changed the state: equal hashes mean the same active set."""
+    g, C, ks, vf = _cells(cfg, g, kscale, vfrag)
+    g = g.copy()
+    tr = np.zeros(C, dtype=np.uint64)
+    nl, lv = cfg._levels()
+    c = cfg._c()
+    v = _load().oracle_rk_trace(ctypes.byref(c), C, _dp(g), _dp(ks), _dp(vf), float(cfg.vfrag), nl, _dp(lv),
+                                float(dt), int(n_steps), tr.ctypes.data_as(ctypes.POINTER(ctypes.c_ulonglong)))
+    assert v >= 0
+    return g, int(v), tr
 
 
 def rk_adaptive(cfg: Config, g, cfl: float, dt_max: float, t_end: float, n_sub: int, t=None,

@@ -888,3 +888,63 @@ def test_constant_kernel_full_size_with_per_cell_steps(oracle):
         errs[k] = (O.error_c(cfg, g, exact), O.error_d(cfg, g, exact))
     assert errs[4][0] < errs[3][0] < errs[1][0] and errs[4][1] < errs[3][1] < errs[1][1], errs
     assert max(errs[4]) < v["error_below_at_k4"], errs
+
+
+# ------------------------------------------------------- operator splitting (Sec. 5.2)
+def _row(O, C=12, seed=4):
+    cfg = _cfg(O, N=6, k=2, xmin=1e-3, xmax=1e3, kernel="ballistic", frag="powerlaw", conservative=True, vfrag=0.5)
+    rng = np.random.default_rng(seed)
+    g = np.stack([O.project(cfg, lambda x, mu=mu: W.lognormal_density(x, mu, 1.0, 1.0))
+                  for mu in rng.uniform(-2.0, 2.0, C)])
+    return cfg, O.limit(cfg, g)[0]
+
+
+def test_transport_at_courant_one_shifts_the_row(oracle):
+    """Upwind transport with |vel| dt / dx = 1 moves every bin exactly one cell along the
+    row (downstream for a positive velocity, upstream for a negative one), periodically."""
+    O = oracle
+    cfg, g = _row(O)
+    vel = np.array([2.0, -2.0, 2.0, 2.0, -2.0, 2.0])
+    out = O.advect(cfg, g, vel, 0.5, 1.0).reshape(len(g), cfg.N, 3)
+    gg = g.reshape(len(g), cfg.N, 3)
+    for j in range(cfg.N):
+        assert np.array_equal(out[:, j], np.roll(gg[:, j], 1 if vel[j] > 0 else -1, axis=0))
+
+
+def test_transport_conserves_mass_and_positivity(oracle):
+    """A periodic row keeps the mass of every bin; a convex combination of nonnegative
+    bin polynomials stays nonnegative (the limiter has nothing to do afterwards); an open
+    row loses only what leaves through its downstream end."""
+    O = oracle
+    cfg, g = _row(O)
+    h = np.diff(O.edges(cfg))
+    vel = np.linspace(-3.0, 3.0, cfg.N)
+    out = O.advect(cfg, g, vel, 0.1, 0.5)
+    m = lambda a: (a.reshape(len(g), cfg.N, 3)[:, :, 0] * h).sum(axis=0)
+    assert np.allclose(m(out), m(g), rtol=1e-14, atol=0)
+    lim, viol = O.limit(cfg, out)
+    assert viol == 0 and np.max(np.abs(lim - out)) <= 1e-15 * np.abs(out).max()
+    op = O.advect(cfg, g, vel, 0.1, 0.5, periodic=False).reshape(len(g), cfg.N, 3)
+    gg = g.reshape(len(g), cfg.N, 3)
+    for j in range(cfg.N):
+        a = abs(vel[j] * 0.1 / 0.5)
+        last = gg[-1, j, 0] if vel[j] >= 0 else gg[0, j, 0]
+        tot = np.abs(gg[:, j, 0]).sum()
+        assert abs((op[:, j, 0].sum() - gg[:, j, 0].sum()) + a * last) <= 1e-14 * tot
+
+
+def test_split_step_reduces_to_each_half(oracle):
+    """Strang splitting: with no velocity it is the SSP-RK3 collision step; with the
+    collisions switched off (kernel scale 0) it is two transports over half the step."""
+    O = oracle
+    cfg, g = _row(O, C=6)
+    dt = 0.2 * O.cfl_dt(cfg, g)
+    a, _ = O.split_step(cfg, g, np.zeros(cfg.N), 1.0, dt, 2)
+    b, _ = O.rk(cfg, g, dt, 1)
+    b, _ = O.rk(cfg, b, dt, 1)
+    assert np.array_equal(a, b)
+    vel = np.full(cfg.N, 0.7 / dt)
+    a, _ = O.split_step(cfg, g, vel, 1.0, dt, 1, kscale=np.zeros(len(g)))
+    b = O.advect(cfg, O.advect(cfg, O.limit(cfg, O.advect(cfg, g, vel, 0.5 * dt, 1.0))[0], vel, 0.0, 1.0),
+                 vel, 0.5 * dt, 1.0)
+    assert np.allclose(a, b, rtol=0, atol=1e-15 * np.abs(b).max())

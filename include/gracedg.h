@@ -37,7 +37,13 @@ enum {
     GD_EINVAL = -1,   /* bad argument (shape, enum, null pointer)              */
     GD_EHIP = -2,     /* HIP runtime error                                      */
     GD_ENOMEM = -3,   /* device or host allocation failed                       */
-    GD_EUNSUPPORTED = -4 /* combination not built (e.g. P above the kernels' limit) */
+    GD_EUNSUPPORTED = -4, /* combination not built (e.g. P above the kernels' limit) */
+    GD_EPOSITIVITY = -5   /* returned after a step call that was given a violation counter
+                             completed: the state is advanced (every step taken), but the
+                             limiter found bins with a negative (or non-finite) average,
+                             which it flattened keeping their mass (Sec. 3.2, Eq. gamma);
+                             the counter holds how many.  A step beyond the CFL bound of
+                             Eq. dt is the usual cause.                                 */
 };
 
 /* Collision kernel K(u,v) (Secs. 4.2-4.5). */
@@ -138,6 +144,9 @@ int gd_tensor_info(const gd_tensor* t, gd_tensor_info_t* info);
 int gd_tensor_export(const gd_tensor* t, int level, double* host_out);
 /* Copy the bin edges (bins+1 doubles) to host memory. */
 int gd_tensor_edges(const gd_tensor* t, double* host_out);
+/* Upload the device layouts of both contraction precisions now (otherwise the first
+ * plan on the tensor does it).  Allocates device memory; synchronous; idempotent. */
+int gd_tensor_upload(gd_tensor* t);
 void gd_free_tensor(gd_tensor* t);
 
 /*
@@ -156,6 +165,17 @@ void gd_free_tensor(gd_tensor* t);
  */
 int gd_plan_create(const gd_tensor* const* tensors, const int* cells_per_group, int n_groups,
                    int precision, const double* vfrag, void* stream, gd_plan** out);
+/*
+ * gd_plan_set_vfrag -- new per-cell fragmentation thresholds for an existing plan (a
+ * hydro driver whose thresholds change from step to step keeps its plan): the cells
+ * are sorted into threshold brackets again and the blend weights recomputed exactly as
+ * gd_plan_create does with this vfrag (host [total cells], or NULL = levels[0]).  The
+ * plan's buffers were sized at creation for any bracketing, so nothing is allocated;
+ * the work items are rebuilt, captured graphs dropped.  Synchronous (waits for the
+ * plan's stream first).  A non-finite value returns GD_EINVAL and leaves the plan as
+ * it was.  Groups whose tensor has one level are unaffected.
+ */
+int gd_plan_set_vfrag(gd_plan* plan, const double* vfrag);
 /* total cells and total state doubles (sum over groups of cells * P) */
 int gd_plan_sizes(const gd_plan* plan, long long* n_cells, long long* n_values);
 /* total bins (sum over groups of cells * bins): the length of a limiter-factor array */
@@ -175,6 +195,7 @@ void gd_plan_destroy(gd_plan* plan);
  */
 int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, double* rhs, double* raw);
 
+
 /*
  * gd_rk_step -- n_steps of SSP-RK3 (Eq. RK3) in place on g, with the scaling
  * limiter applied to the start state and after every stage (Sec. 3.2):
@@ -184,9 +205,35 @@ int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, doubl
  *  violations  : host pointer or NULL; if non-NULL the call synchronises the
  *                stream and stores the number of bins found with a negative
  *                average by the limiter (such a bin is flattened, its mass kept),
- *                or with a non-finite coefficient.
+ *                or with a non-finite coefficient; a nonzero count makes the call
+ *                return GD_EPOSITIVITY (after completing every step).
  */
 int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_steps, long long* violations);
+
+/*
+ * Operator splitting with a hydro step (Sec. 5.2: the grain-growth step is split from
+ * the evolution of the hydrodynamics).  The cells of every group of the plan form
+ * one row of hydro cells of width dx, in the plan's cell order.
+ *
+ * gd_advect -- the transport step: every Legendre coefficient of mass bin j moves
+ *   between neighbouring cells with the bin's velocity vel[j] by first-order upwind
+ *   finite volumes, Courant number c_j = vel[j] dt / dx:
+ *       g_c <- (1 - |c_j|) g_c + |c_j| g_up,  up = c - 1 (vel >= 0) or c + 1 (vel < 0),
+ *   a convex combination of bin polynomials (positivity kept).  periodic = 1 wraps the
+ *   row (the mass of every bin is kept to round-off); 0: nothing flows in at the ends
+ *   and what leaves is lost.
+ *    vel : host [sum over groups of bins] (groups concatenated); |vel| dt / dx <= 1
+ *          for every bin, else GD_EINVAL before any launch.
+ *   Synchronises the plan's stream before copying the Courant numbers; the transport
+ *   itself is asynchronous.
+ * gd_split_step -- n_steps of Strang splitting: transport over dt/2, one SSP-RK3
+ *   collision step over dt (as gd_rk_step, start limiter included), transport over
+ *   dt/2.  |vel| dt / (2 dx) <= 1.  violations as in gd_rk_step (counted over all
+ *   collision steps; GD_EPOSITIVITY when given and nonzero).
+ */
+int gd_advect(gd_plan* plan, double* g, const double* vel, double dt, double dx, int periodic);
+int gd_split_step(gd_plan* plan, double* g, const double* kscale, const double* vel, double dx, int periodic,
+                  double dt, int n_steps, long long* violations);
 
 /*
  * gd_rk_advance -- per-cell time steps under the CFL bound of Eq. dt (Sec. 3.2):
@@ -217,6 +264,7 @@ int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_
  *  violations : host pointer or NULL, as in gd_rk_step.
  *  unfinished : host pointer or NULL; if non-NULL, the number of cells with
  *               t[c] < t_end after the call.
+ * Returns GD_EPOSITIVITY when violations is given and nonzero (the sub-steps are all taken).
  * Either host pointer makes the call synchronise the stream.  With graphs on
  * (gd_plan_use_graph) one sub-step (three contractions and three stage kernels) is
  * captured into a HIP graph and replayed n_substeps times; it is captured again when
@@ -238,7 +286,8 @@ int gd_rk_advance(gd_plan* plan, double* g, const double* kscale, double* t, dou
  *     gammas : device, (1 + 3 n_steps) arrays of n_bins doubles (n_bins = sum over
  *              groups of cells * bins, cell-major per group): the factor the limiter
  *              applied to each bin when it wrote the state of the same index.
- *   g is overwritten with the final state, as gd_rk_step does.
+ *   g is overwritten with the final state, as gd_rk_step does; violations as in
+ *   gd_rk_step (GD_EPOSITIVITY when given and nonzero, the record complete).
  * gd_adjoint -- the vector-Jacobian product of the whole gd_rk_forward call:
  *     lam      : device, state layout; in: dLoss/dg(final), out: dLoss/dg(input)
  *                (the caller's state before the start limiter);

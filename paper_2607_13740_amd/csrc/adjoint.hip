@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
     constexpr int SUB = 32 / kAdjSlots;
     constexpr int MAXNQB = (PMAX + 15) / 16, MAXNPS = (PMAX + kAdjPs - 1) / kAdjPs;   // q blocks, p ranges
     __shared__ double sl_lam[kAdjSlots * PMAX];
-    __shared__ double red[kAdjSlots];
+    __shared__ double red[kAdjSlots * PMAX];   // per-coefficient terms of the kernel-scale gradient
     const GD_CONST GroupDev* groups = cptr(a.groups);
     const int tile_all = (int)blockIdx.x / SUB, s0 = ((int)blockIdx.x % SUB) * kAdjSlots;
     int gi = 0;
@@ -253,8 +253,6 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
     GD_GLOBAL double* prev = a.prev ? gptr(a.prev) + G->val0 : nullptr;
 
     // ---- phase C: one thread per (slot, coefficient)
-    if (threadIdx.x < kAdjSlots) red[threadIdx.x] = 0.0;
-    if (a.combine) __syncthreads();
     const GD_GLOBAL double* G2 = gptr(G->G2);
     const GD_GLOBAL double* G1p = gptr(G->G1p);
     for (int t = threadIdx.x; t < kAdjSlots * P; t += blockDim.x) {
@@ -285,7 +283,7 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
             for (int qb = 0; qb < MAXNQB; ++qb) g += g1[qb] + g1d[qb];
             const double sc = kscale ? kscale[c] : 1.0;
             v += sc * g;
-            atomicAdd(&red[sl], 0.5 * ylin[(size_t)c * P + p] * g);
+            red[sl * P + p] = 0.5 * ylin[(size_t)c * P + p] * g;
         }
         sl_lam[sl * P + p] = v;
     }
@@ -295,7 +293,11 @@ __global__ __launch_bounds__(kAdjThreads) void k_adj_boundary(AdjStageArgs a)
         if (s < n_slots) {
             const int c = perm ? perm[s] : s;
             if (c >= 0) {
-                if (a.dkscale) a.dkscale[G->cell0 + c] += red[threadIdx.x];
+                // summed in coefficient order, so that the result does not depend on
+                // the order in which the waves ran
+                double rsum = 0.0;
+                for (int p = 0; p < P; ++p) rsum += red[threadIdx.x * P + p];
+                if (a.dkscale) a.dkscale[G->cell0 + c] += rsum;
                 if (a.dvfrag && blend) {
                     double d = 0.0;
 #pragma unroll

@@ -19,14 +19,6 @@ int fail(int code, const std::string& msg)
     return code;
 }
 
-struct DevBuf {
-    void* p = nullptr;
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
-    }
-};
-
 template <class T>
 static int upload(std::vector<std::unique_ptr<DevBuf>>& owner, const std::vector<T>& v, const T** out, size_t* bytes)
 {
@@ -47,32 +39,6 @@ using namespace gd;
 extern "C" const char* gd_last_error(void) { return g_err.c_str(); }
 
 // ============================================================================ tensors
-struct gd_tensor {
-    TensorSpec spec;
-    HostTensor host;
-    int N = 0, k = 0, P = 0, n_out = 0, R = 0;
-    int KS = 0, NOB = 0;       // split-FP16 path: K steps of 16, row blocks of 32
-    int KS4 = 0, NOB16 = 0;    // FP64 path: K steps of 4, row blocks of 16
-    long long nnz = 0;
-    std::vector<long long> nnz_level, nnz_delta;   // per level r: folded level, level r+1 minus r
-    size_t bytes = 0;
-    bool packed = false;       // device layouts uploaded (by the first plan)
-    std::vector<std::unique_ptr<DevBuf>> bufs;
-    const double* h = nullptr;
-    const double* colscale = nullptr;   // [P]
-    const double* rowscale = nullptr;   // [NOB*32]
-    Schedule mixed, f64;
-    Schedule adj;              // FP64 transposed layout of the vector-Jacobian product
-    // Rows of the forward schedules are ordered bin by bin (V_{0,1..k}, then F_j with
-    // V_{j,1..k} for j = 1..N-1, then F_N if non-conservative), so that a row block
-    // covers neighbouring masses and its nonzero (p, q) blocks are few: F_j sits at
-    // position j(k+1)-1 and V_{j,i} at j(k+1)+i-1 of the raw buffers (the stage kernel
-    // reads them there).  rowperm[position] = row o.
-    std::vector<int> rowperm;
-    bool adj_packed = false;
-    int KSO = 0;               // K steps of 16 output rows o (adjoint contraction)
-    int NPS = 0;               // ranges of p per q block (adjoint contraction)
-};
 
 // folded tensor of level r: Tf[o][p][q] = T[o][p][q] + T[o][q][p] (p < q), T[o][p][p]
 static inline double fold(const gd_tensor* t, int r, int o, int p, int q)
@@ -511,6 +477,12 @@ extern "C" int gd_tensor_edges(const gd_tensor* t, double* host_out)
     return GD_OK;
 }
 
+extern "C" int gd_tensor_upload(gd_tensor* t)
+{
+    if (!t) return fail(GD_EINVAL, "null tensor");
+    return pack_tensor(t);
+}
+
 extern "C" void gd_free_tensor(gd_tensor* t) { delete t; }
 
 // ============================================================================ plans
@@ -526,6 +498,7 @@ struct Group {
     int C = 0;
     long long cell0 = 0, val0 = 0, raw0 = 0;
     int n_slots = 0, tiles32 = 0, tiles16 = 0, tile_off = 0;
+    int slot_cap = 0;           // slots the buffers hold: every cell plus the largest bracket padding
     std::vector<Bracket> brackets;
     int* perm = nullptr;        // slot -> cell within the group (nullptr: identity)
     double* theta = nullptr;    // [n_slots]
@@ -581,11 +554,14 @@ struct gd_plan {
     unsigned long long* viol = nullptr;
     double* dtc = nullptr;                  // per-cell steps of an adaptive sub-step (first adaptive call)
     unsigned long long* below = nullptr;    // count of cells short of the end time
+    double* courant = nullptr;              // per-bin Courant numbers of the transport step (groups concatenated)
+    std::vector<int> bin_off;               // first bin of every group in courant
     long long n_bins = 0;                   // sum over groups of cells * bins
     std::vector<GroupDev> gdev;             // host copy of groups_dev
     // reverse mode, set up by the first adjoint call
     bool adj_ready = false;
     int4* adj_items = nullptr;
+    size_t adj_items_cap = 0;
     int n_adj_items = 0, ksomax = 1;
     double* adj_buf[2] = {nullptr, nullptr};
     bool timing = false;
@@ -739,6 +715,49 @@ static int build_items(gd_plan* pl)
     return GD_OK;
 }
 
+// Threshold brackets of one group (tensors with several levels): bracket r and blend
+// weight theta of every cell, levels[r] <= v < levels[r+1], theta = (v - levels[r]) /
+// (levels[r+1] - levels[r]) clamped to [0,1]; cells sorted by bracket, each bracket
+// padded to kSlotGranule slots.  vf: the group's thresholds, or nullptr (levels[0]).
+static int bracket_cells(Group& G, const double* vf, std::vector<int>& perm, std::vector<double>& theta)
+{
+    const gd_tensor* t = G.t;
+    const std::vector<double>& lv = t->spec.levels;
+    std::vector<std::vector<std::pair<int, double>>> br(t->R - 1);
+    std::vector<double> dth(G.C);
+    for (int c = 0; c < G.C; ++c) {
+        const double v = vf ? vf[c] : lv[0];
+        if (!std::isfinite(v)) return fail(GD_EINVAL, "non-finite fragmentation threshold");
+        int r = 0;
+        while (r < t->R - 2 && v >= lv[r + 1]) ++r;
+        double th = (v - lv[r]) / (lv[r + 1] - lv[r]);
+        // inside the table theta moves with v; outside it is clamped
+        dth[c] = (v >= lv[r] && v <= lv[r + 1]) ? 1.0 / (lv[r + 1] - lv[r]) : 0.0;
+        th = std::min(1.0, std::max(0.0, th));
+        br[r].push_back({c, th});
+    }
+    perm.clear();
+    theta.clear();
+    G.brackets.clear();
+    G.h_dthdv.clear();
+    for (int r = 0; r < t->R - 1; ++r) {
+        if (br[r].empty()) continue;
+        G.brackets.push_back({r, int(perm.size()), int(br[r].size())});
+        for (auto& ct : br[r]) {
+            perm.push_back(ct.first);
+            theta.push_back(ct.second);
+            G.h_dthdv.push_back(dth[ct.first]);
+        }
+        while (perm.size() % kSlotGranule) {
+            perm.push_back(-1);
+            theta.push_back(0.0);
+            G.h_dthdv.push_back(0.0);
+        }
+    }
+    G.n_slots = int(perm.size());
+    return GD_OK;
+}
+
 extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_per_group, int n_groups,
                               int precision, const double* vfrag, void* stream, gd_plan** out)
 {
@@ -771,59 +790,36 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
     for (Group& G : pl->groups) {
         const gd_tensor* t = G.t;
         if (t->R > 1) {
-            // bracket r and blend weight theta of every cell: levels[r] <= v < levels[r+1],
-            // theta = (v - levels[r]) / (levels[r+1] - levels[r]) clamped to [0,1]
-            const std::vector<double>& lv = t->spec.levels;
-            std::vector<std::vector<std::pair<int, double>>> br(t->R - 1);
-            std::vector<double> dth(G.C);
-            for (int c = 0; c < G.C; ++c) {
-                const double v = vfrag ? vfrag[G.cell0 + c] : lv[0];
-                if (!std::isfinite(v)) return fail(GD_EINVAL, "non-finite fragmentation threshold");
-                int r = 0;
-                while (r < t->R - 2 && v >= lv[r + 1]) ++r;
-                double th = (v - lv[r]) / (lv[r + 1] - lv[r]);
-                // inside the table theta moves with v; outside it is clamped
-                dth[c] = (v >= lv[r] && v <= lv[r + 1]) ? 1.0 / (lv[r + 1] - lv[r]) : 0.0;
-                th = std::min(1.0, std::max(0.0, th));
-                br[r].push_back({c, th});
-            }
             std::vector<int> perm;
             std::vector<double> theta;
-            for (int r = 0; r < t->R - 1; ++r) {
-                if (br[r].empty()) continue;
-                G.brackets.push_back({r, int(perm.size()), int(br[r].size())});
-                for (auto& ct : br[r]) {
-                    perm.push_back(ct.first);
-                    theta.push_back(ct.second);
-                    G.h_dthdv.push_back(dth[ct.first]);
-                }
-                while (perm.size() % kSlotGranule) {
-                    perm.push_back(-1);
-                    theta.push_back(0.0);
-                    G.h_dthdv.push_back(0.0);
-                }
-            }
-            G.n_slots = int(perm.size());
+            if ((rc = bracket_cells(G, vfrag ? vfrag + G.cell0 : nullptr, perm, theta))) return rc;
+            // room for any later bracketing (gd_plan_set_vfrag): every bracket padded
+            G.slot_cap = G.C + (t->R - 1) * (kSlotGranule - 1);
+            G.slot_cap = cdiv(G.slot_cap, kSlotGranule) * kSlotGranule;
+            perm.resize(G.slot_cap, -1);
+            theta.resize(G.slot_cap, 0.0);
             if ((rc = dcopy(pl.get(), &G.perm, perm))) return rc;
             if ((rc = dcopy(pl.get(), &G.theta, theta))) return rc;
         } else {
             G.n_slots = G.C;
+            G.slot_cap = G.C;
             if (G.C > 0) G.brackets.push_back({0, 0, G.C});
         }
         G.tiles32 = cdiv(G.n_slots, 32);
         G.tiles16 = cdiv(G.n_slots, 16);
         G.tile_off = pl->tiles32;
         pl->tiles32 += G.tiles32;
+        const int tiles_cap = cdiv(G.slot_cap, 32);
         const bool mixed = precision == GD_PREC_MIXED_F16X3;
         if (mixed) {
             G.ystride = t->NOB * 32;
-            if ((rc = dalloc(pl.get(), &G.mfrag, size_t(G.tiles32) * t->KS * 128))) return rc;
-            if ((rc = dalloc(pl.get(), &G.mt, size_t(G.tiles32) * 32 * t->P))) return rc;
-            if ((rc = dalloc(pl.get(), &G.eslot, size_t(G.n_slots)))) return rc;
-            if ((rc = dalloc(pl.get(), &G.Yf, size_t(G.n_slots) * G.ystride))) return rc;
+            if ((rc = dalloc(pl.get(), &G.mfrag, size_t(tiles_cap) * t->KS * 128))) return rc;
+            if ((rc = dalloc(pl.get(), &G.mt, size_t(tiles_cap) * 32 * t->P))) return rc;
+            if ((rc = dalloc(pl.get(), &G.eslot, size_t(G.slot_cap)))) return rc;
+            if ((rc = dalloc(pl.get(), &G.Yf, size_t(G.slot_cap) * G.ystride))) return rc;
         } else {
             G.ystride = t->NOB16 * 16;
-            if ((rc = dalloc(pl.get(), &G.Yd, size_t(G.n_slots) * G.ystride))) return rc;
+            if ((rc = dalloc(pl.get(), &G.Yd, size_t(G.slot_cap) * G.ystride))) return rc;
         }
         const Schedule& S = mixed ? t->mixed : t->f64;
         GroupDev d{};
@@ -868,6 +864,14 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
     if ((rc = dalloc(pl.get(), &pl->y2, pl->n_values))) return rc;
     if ((rc = dalloc(pl.get(), &pl->viol, 1))) return rc;
     HIP_TRY(hipMemset(pl->viol, 0, sizeof(unsigned long long)));
+    {
+        int nb = 0;
+        for (Group& G : pl->groups) {
+            pl->bin_off.push_back(nb);
+            nb += G.t->N;
+        }
+        if ((rc = dalloc(pl.get(), &pl->courant, size_t(nb)))) return rc;
+    }
     HIP_TRY(hipStreamCreateWithFlags(&pl->cap, hipStreamNonBlocking));
     if ((rc = build_items(pl.get()))) return rc;
     *out = pl.release();
@@ -1052,15 +1056,13 @@ static int capture_step(gd_plan* pl, double* g, const double* kscale, double dt)
     return GD_OK;
 }
 
-extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double dt, int n_steps,
-                          long long* violations)
+// n_steps of SSP-RK3 on g (the start limiter, then the captured or launched steps);
+// violations accumulate in pl->viol
+static int rk_steps(gd_plan* pl, double* g, const double* kscale, double dt, int n_steps)
 {
-    if (!pl || !g || n_steps < 0) return fail(GD_EINVAL, "bad argument");
-    if (!std::isfinite(dt)) return fail(GD_EINVAL, "dt must be finite");
     int rc;
     hipStream_t s = pl->stream;
     const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
-    if ((rc = launch_fill_u64(pl->viol, 1, s))) return rc;
     // limiter on the start state (and its split for the first contraction)
     if ((rc = stage(pl, s, -1, 1, split, kscale, nullptr, g, nullptr, dt, nullptr))) return rc;
     const bool graph = pl->use_graph && !pl->timing && n_steps > 0;
@@ -1070,13 +1072,85 @@ extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double d
         if (graph) HIP_TRY(hipGraphLaunch(pl->graph.exec, s));
         else if ((rc = step_launches(pl, s, g, kscale, dt))) return rc;
     }
-    if (violations) {
-        unsigned long long v = 0;
-        HIP_TRY(hipMemcpyAsync(&v, pl->viol, sizeof(v), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        *violations = (long long)v;
+    return GD_OK;
+}
+
+static int read_violations(gd_plan* pl, long long* violations)
+{
+    unsigned long long v = 0;
+    HIP_TRY(hipMemcpyAsync(&v, pl->viol, sizeof(v), hipMemcpyDeviceToHost, pl->stream));
+    HIP_TRY(hipStreamSynchronize(pl->stream));
+    *violations = (long long)v;
+    if (v) return fail(GD_EPOSITIVITY, "the limiter found bins with a negative or non-finite average");
+    return GD_OK;
+}
+
+extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double dt, int n_steps,
+                          long long* violations)
+{
+    if (!pl || !g || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!std::isfinite(dt)) return fail(GD_EINVAL, "dt must be finite");
+    int rc;
+    hipStream_t s = pl->stream;
+    if ((rc = launch_fill_u64(pl->viol, 1, s))) return rc;
+    if ((rc = rk_steps(pl, g, kscale, dt, n_steps))) return rc;
+    return violations ? read_violations(pl, violations) : GD_OK;
+}
+
+// Courant numbers vel_j * dt / dx of every bin (host values checked, then copied)
+static int set_courant(gd_plan* pl, const double* vel, double dt, double dx)
+{
+    if (!vel || !(dx > 0.0) || !std::isfinite(dx) || !std::isfinite(dt) || dt < 0.0)
+        return fail(GD_EINVAL, "transport needs velocities, dx > 0 and a finite dt >= 0");
+    const int nb = pl->bin_off.empty() ? 0 : pl->bin_off.back() + pl->groups.back().t->N;
+    std::vector<double> c(nb);
+    for (int b = 0; b < nb; ++b) {
+        c[b] = vel[b] * dt / dx;
+        if (!(std::fabs(c[b]) <= 1.0)) return fail(GD_EINVAL, "transport Courant number |vel dt/dx| above 1");
+    }
+    HIP_TRY(hipStreamSynchronize(pl->stream));
+    HIP_TRY(hipMemcpy(pl->courant, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice));
+    return GD_OK;
+}
+
+static int advect_launches(gd_plan* pl, double* g, int periodic)
+{
+    int rc;
+    hipStream_t s = pl->stream;
+    for (size_t gi = 0; gi < pl->groups.size(); ++gi) {
+        const Group& G = pl->groups[gi];
+        if (G.C == 0) continue;
+        if ((rc = launch_advect(g + G.val0, pl->y1 + G.val0, pl->courant + pl->bin_off[gi], G.C, G.t->N,
+                                G.t->k + 1, periodic, s)))
+            return rc;
+        HIP_TRY(hipMemcpyAsync(g + G.val0, pl->y1 + G.val0, size_t(G.C) * G.t->P * sizeof(double),
+                               hipMemcpyDeviceToDevice, s));
     }
     return GD_OK;
+}
+
+extern "C" int gd_advect(gd_plan* pl, double* g, const double* vel, double dt, double dx, int periodic)
+{
+    if (!pl || !g) return fail(GD_EINVAL, "null argument");
+    int rc = set_courant(pl, vel, dt, dx);
+    if (rc) return rc;
+    return advect_launches(pl, g, periodic ? 1 : 0);
+}
+
+extern "C" int gd_split_step(gd_plan* pl, double* g, const double* kscale, const double* vel, double dx,
+                             int periodic, double dt, int n_steps, long long* violations)
+{
+    if (!pl || !g || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!std::isfinite(dt)) return fail(GD_EINVAL, "dt must be finite");
+    int rc = set_courant(pl, vel, 0.5 * dt, dx);
+    if (rc) return rc;
+    if ((rc = launch_fill_u64(pl->viol, 1, pl->stream))) return rc;
+    for (int n = 0; n < n_steps; ++n) {
+        if ((rc = advect_launches(pl, g, periodic ? 1 : 0))) return rc;
+        if ((rc = rk_steps(pl, g, kscale, dt, 1))) return rc;
+        if ((rc = advect_launches(pl, g, periodic ? 1 : 0))) return rc;
+    }
+    return violations ? read_violations(pl, violations) : GD_OK;
 }
 
 // the six launches of one sub-step with per-cell steps
@@ -1158,6 +1232,7 @@ extern "C" int gd_rk_advance(gd_plan* pl, double* g, const double* kscale, doubl
         HIP_TRY(hipStreamSynchronize(s));
         if (violations) *violations = (long long)v[0];
         if (unfinished) *unfinished = (long long)v[1];
+        if (violations && v[0]) return fail(GD_EPOSITIVITY, "the limiter found bins with a negative or non-finite average");
     }
     return GD_OK;
 }
@@ -1181,7 +1256,7 @@ static int prepare_adjoint(gd_plan* pl)
         d.NQB = cdiv(t->P, 16);
         d.NPS = t->NPS;
         pl->ksomax = std::max(pl->ksomax, t->KSO);
-        const size_t ns = size_t(std::max(1, G.n_slots));
+        const size_t ns = size_t(std::max(1, G.slot_cap));
         double *nu, *g2, *g1, *dt_, *dv;
         if ((rc = dalloc(pl, &nu, ns * t->KSO * 16))) return rc;
         if ((rc = dalloc(pl, &g2, size_t(t->NPS) * ns * t->P))) return rc;
@@ -1201,10 +1276,59 @@ static int prepare_adjoint(gd_plan* pl)
         if ((rc = dalloc(pl, &b, pl->n_values))) return rc;
     std::vector<int4> h;
     if ((rc = make_items(pl, 1, kAdjWaves, 1, 1, h, nullptr))) return rc;
-    size_t cap = 0;
-    if ((rc = upload_items(h, &pl->adj_items, &cap))) return rc;
+    if ((rc = upload_items(h, &pl->adj_items, &pl->adj_items_cap))) return rc;
     pl->n_adj_items = int(h.size());
     pl->adj_ready = true;
+    return GD_OK;
+}
+
+extern "C" int gd_plan_set_vfrag(gd_plan* pl, const double* vfrag)
+{
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    int rc;
+    // validate first, so that a bad value leaves the plan as it was
+    if (vfrag)
+        for (long long c = 0; c < pl->n_cells; ++c)
+            if (!std::isfinite(vfrag[c])) return fail(GD_EINVAL, "non-finite fragmentation threshold");
+    HIP_TRY(hipStreamSynchronize(pl->stream));
+    int tiles = 0;
+    for (size_t gi = 0; gi < pl->groups.size(); ++gi) {
+        Group& G = pl->groups[gi];
+        GroupDev& d = pl->gdev[gi];
+        if (G.t->R > 1) {
+            std::vector<int> perm;
+            std::vector<double> theta;
+            if ((rc = bracket_cells(G, vfrag ? vfrag + G.cell0 : nullptr, perm, theta))) return rc;
+            if (G.n_slots > G.slot_cap) return fail(GD_EINVAL, "internal: brackets exceed the slot capacity");
+            perm.resize(G.slot_cap, -1);
+            theta.resize(G.slot_cap, 0.0);
+            HIP_TRY(hipMemcpy(G.perm, perm.data(), perm.size() * sizeof(int), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(G.theta, theta.data(), theta.size() * sizeof(double), hipMemcpyHostToDevice));
+            if (pl->adj_ready) {
+                std::vector<double> dthdv = G.h_dthdv;
+                dthdv.resize(G.slot_cap, 0.0);
+                HIP_TRY(hipMemcpy(const_cast<double*>(d.dthdv), dthdv.data(), dthdv.size() * sizeof(double),
+                                  hipMemcpyHostToDevice));
+            }
+        }
+        G.tiles32 = cdiv(G.n_slots, 32);
+        G.tiles16 = cdiv(G.n_slots, 16);
+        G.tile_off = tiles;
+        tiles += G.tiles32;
+        d.n_slots = G.n_slots;
+        d.tiles32 = G.tiles32;
+        d.tiles16 = G.tiles16;
+        d.tile_off = G.tile_off;
+    }
+    pl->tiles32 = tiles;
+    HIP_TRY(hipMemcpy(pl->groups_dev, pl->gdev.data(), pl->gdev.size() * sizeof(GroupDev), hipMemcpyHostToDevice));
+    if ((rc = build_items(pl))) return rc;
+    if (pl->adj_ready) {
+        std::vector<int4> h;
+        if ((rc = make_items(pl, 1, kAdjWaves, 1, 1, h, nullptr))) return rc;
+        if ((rc = upload_items(h, &pl->adj_items, &pl->adj_items_cap))) return rc;
+        pl->n_adj_items = int(h.size());
+    }
     return GD_OK;
 }
 
@@ -1238,6 +1362,7 @@ extern "C" int gd_rk_forward(gd_plan* pl, double* g, const double* kscale, doubl
         HIP_TRY(hipMemcpyAsync(&v, pl->viol, sizeof(v), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         *violations = (long long)v;
+        if (v) return fail(GD_EPOSITIVITY, "the limiter found bins with a negative or non-finite average");
     }
     return GD_OK;
 }

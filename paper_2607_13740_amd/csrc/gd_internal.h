@@ -206,6 +206,48 @@ struct AdjStageArgs {
     double* dvfrag;
 };
 
+// ------------------------------------------------------------------ tensors
+// device buffer owned by a tensor
+struct DevBuf {
+    void* p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+} // namespace gd
+
+// The library's tensor handle (opaque in the C ABI).
+struct gd_tensor {
+    gd::TensorSpec spec;
+    gd::HostTensor host;
+    int N = 0, k = 0, P = 0, n_out = 0, R = 0;
+    int KS = 0, NOB = 0;       // split-FP16 path: K steps of 16, row blocks of 32
+    int KS4 = 0, NOB16 = 0;    // FP64 path: K steps of 4, row blocks of 16
+    long long nnz = 0;
+    std::vector<long long> nnz_level, nnz_delta;   // per level r: folded level, level r+1 minus r
+    size_t bytes = 0;
+    bool packed = false;       // device layouts uploaded (by the first plan)
+    std::vector<std::unique_ptr<gd::DevBuf>> bufs;
+    const double* h = nullptr;
+    const double* colscale = nullptr;   // [P]
+    const double* rowscale = nullptr;   // [NOB*32]
+    gd::Schedule mixed, f64;
+    gd::Schedule adj;              // FP64 transposed layout of the vector-Jacobian product
+    // Rows of the forward schedules are ordered bin by bin (V_{0,1..k}, then F_j with
+    // V_{j,1..k} for j = 1..N-1, then F_N if non-conservative), so that a row block
+    // covers neighbouring masses and its nonzero (p, q) blocks are few: F_j sits at
+    // position j(k+1)-1 and V_{j,i} at j(k+1)+i-1 of the raw buffers (the stage kernel
+    // reads them there).  rowperm[position] = row o.
+    std::vector<int> rowperm;
+    bool adj_packed = false;
+    int KSO = 0;               // K steps of 16 output rows o (adjoint contraction)
+    int NPS = 0;               // ranges of p per q block (adjoint contraction)
+};
+
+namespace gd {
+
 // ------------------------------------------------------------------ launchers
 int launch_stage(const StageArgs& a, hipStream_t s);
 int launch_count_below(const double* t, long long n, double t_end, unsigned long long* count, hipStream_t s);
@@ -217,5 +259,7 @@ int launch_contract_fp64(const ContractArgs& a, int ksmax, int waves, hipStream_
 int launch_adjoint_fp64(const ContractArgs& a, int ksomax, hipStream_t s);
 int launch_adj_boundary(const AdjStageArgs& a, hipStream_t s);
 int launch_fill_f64(double* p, long long n, double v, hipStream_t s);
+int launch_advect(const double* g, double* out, const double* courant, long long C, int N, int K1, int periodic,
+                  hipStream_t s);
 
 } // namespace gd

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgracedg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "gracedg.h")
 
-GD_OK, GD_EINVAL, GD_EHIP, GD_ENOMEM, GD_EUNSUPPORTED = 0, -1, -2, -3, -4
+GD_OK, GD_EINVAL, GD_EHIP, GD_ENOMEM, GD_EUNSUPPORTED, GD_EPOSITIVITY = 0, -1, -2, -3, -4, -5
 KERNELS = {"const": 0, "additive": 1, "multiplicative": 2, "ballistic": 3, "maxwell": 4}
 FRAGS = {"none": 0, "powerlaw": 1, "uniform_binary": 2, "remnant_only": 3, "general": 4}
 PREC = {"fp64": 0, "mixed": 1}
@@ -81,6 +81,11 @@ def lib():
                               ctypes.c_int),
             "gd_plan_destroy": ([_VP], None),
             "gd_collision_rhs": ([_VP, _VP, _VP, _VP, _VP], ctypes.c_int),
+            "gd_tensor_upload": ([_VP], ctypes.c_int),
+            "gd_plan_set_vfrag": ([_VP, _DP], ctypes.c_int),
+            "gd_advect": ([_VP, _VP, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+            "gd_split_step": ([_VP, _VP, _VP, _DP, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                               ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_rk_step": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_rk_advance": ([_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -111,8 +116,10 @@ def lib():
     return _lib
 
 
-def _check(rc):
-    if rc != GD_OK:
+def _check(rc, counted=False):
+    """Raise on a failed call.  counted: the call was given a violation counter, so
+    GD_EPOSITIVITY (completed, with limiter violations counted) is a result, not an error."""
+    if rc != GD_OK and not (counted and rc == GD_EPOSITIVITY):
         raise GDError(rc, lib().gd_last_error().decode())
 
 
@@ -187,6 +194,11 @@ class Tensor:
         _check(lib().gd_project(self.h, int(C), _ptr(samples), _ptr(out), ctypes.c_void_p(st)))
         return out
 
+    def upload(self):
+        """Device layouts of both contraction precisions now (gd_tensor_upload)."""
+        _check(lib().gd_tensor_upload(self.h))
+        return self
+
     def __del__(self):
         h = getattr(self, "h", None)
         if h is not None and _lib is not None:
@@ -213,6 +225,7 @@ class Plan:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         vf = None
+        self._vfrag = None
         if vfrag is not None:
             self._vfrag = np.ascontiguousarray(vfrag, dtype=np.float64)
             if self._vfrag.size != sum(self.cells):
@@ -229,6 +242,24 @@ class Plan:
         nb = ctypes.c_longlong()
         _check(lib().gd_plan_bins(self.h, ctypes.byref(nb)))
         self.n_bins = nb.value
+
+    def set_vfrag(self, vfrag):
+        """New per-cell fragmentation thresholds (host values, all cells in plan order;
+        None = the first level): brackets and blend weights rebuilt (gd_plan_set_vfrag)."""
+        if vfrag is None:
+            _check(lib().gd_plan_set_vfrag(self.h, None))
+            self._vfrag = None
+            return
+        v = np.ascontiguousarray(vfrag, dtype=np.float64).reshape(-1)
+        if v.size != self.n_cells:
+            raise ValueError("vfrag needs one value per cell")
+        _check(lib().gd_plan_set_vfrag(self.h, v.ctypes.data_as(_DP)))
+        self._vfrag = v
+
+    @property
+    def vfrag(self):
+        """The thresholds the plan's brackets were built from (None: the first level)."""
+        return self._vfrag
 
     def schedule_stats(self, group=0):
         fm, ff, ns = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
@@ -251,8 +282,32 @@ class Plan:
         _dev64(kscale, self.n_cells, "kscale")
         v = ctypes.c_longlong(0)
         _check(lib().gd_rk_step(self.h, _ptr(g), _ptr(kscale), float(dt), int(n_steps),
-                                ctypes.byref(v) if count_violations else None))
+                                ctypes.byref(v) if count_violations else None), counted=count_violations)
         return v.value if count_violations else None
+
+    def _vel(self, vel):
+        v = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1)
+        nb = sum(t.bins for t in self.tensors)
+        if v.size != nb:
+            raise ValueError(f"vel needs one velocity per bin of every group ({nb})")
+        return v
+
+    def advect(self, g, vel, dt, dx, periodic=True):
+        """Upwind transport of every coefficient between neighbouring cells (gd_advect)."""
+        _dev64(g, self.n_values, "g")
+        v = self._vel(vel)
+        _check(lib().gd_advect(self.h, _ptr(g), v.ctypes.data_as(_DP), float(dt), float(dx), int(bool(periodic))))
+
+    def split_step(self, g, vel, dx, dt, n_steps=1, kscale=None, periodic=True, count_violations=False):
+        """Strang splitting: transport dt/2, SSP-RK3 collision step dt, transport dt/2 (gd_split_step)."""
+        _dev64(g, self.n_values, "g")
+        _dev64(kscale, self.n_cells, "kscale")
+        v = self._vel(vel)
+        cnt = ctypes.c_longlong(0)
+        _check(lib().gd_split_step(self.h, _ptr(g), _ptr(kscale), v.ctypes.data_as(_DP), float(dx),
+                                   int(bool(periodic)), float(dt), int(n_steps),
+                                   ctypes.byref(cnt) if count_violations else None), counted=count_violations)
+        return cnt.value if count_violations else None
 
     def rk_advance(self, g, t, t_end, cfl, dt_max, n_substeps, kscale=None, flux_floor=0.0, count=False):
         """Per-cell steps under the CFL bound (gd_rk_advance) on g and the cell
@@ -266,7 +321,7 @@ class Plan:
         u = ctypes.c_longlong(0)
         _check(lib().gd_rk_advance(self.h, _ptr(g), _ptr(kscale), _ptr(t), float(t_end), float(cfl), float(dt_max),
                                    float(flux_floor), int(n_substeps), ctypes.byref(v) if count else None,
-                                   ctypes.byref(u) if count else None))
+                                   ctypes.byref(u) if count else None), counted=count)
         return (v.value, u.value) if count else None
 
     def timing(self, enable=True):
@@ -281,7 +336,7 @@ class Plan:
         gm = torch.empty((1 + 3 * n_steps) * self.n_bins, dtype=torch.float64, device=g.device)
         v = ctypes.c_longlong(0)
         _check(lib().gd_rk_forward(self.h, _ptr(g), _ptr(kscale), float(dt), int(n_steps), _ptr(st), _ptr(gm),
-                                   ctypes.byref(v) if count_violations else None))
+                                   ctypes.byref(v) if count_violations else None), counted=count_violations)
         return (st, gm, v.value) if count_violations else (st, gm)
 
     def adjoint(self, states, gammas, dt, n_steps, lam, kscale=None, want_kscale=True, want_vfrag=True):
@@ -376,12 +431,16 @@ def _rksolve_class():
         class RKSolve(torch.autograd.Function):
             """n_steps of SSP-RK3 with the limiter (gd_rk_forward) whose backward is the
             library's adjoint (gd_adjoint): gradients for the initial state, the per-cell
-            kernel scale and the per-cell fragmentation threshold.  The threshold tensor
-            only carries the gradient: its values must be the ones the plan was built
-            with (the plan fixes the threshold brackets)."""
+            kernel scale and the per-cell fragmentation threshold.  When the threshold
+            tensor's values differ from the plan's, the plan's brackets and blend weights
+            are rebuilt from them first (gd_plan_set_vfrag)."""
 
             @staticmethod
             def forward(ctx, g0, kscale, vfrag, plan, dt, n_steps):
+                if vfrag is not None:
+                    v = vfrag.detach().to("cpu", torch.float64).numpy().reshape(-1)
+                    if plan.vfrag is None or not np.array_equal(v, plan.vfrag):
+                        plan.set_vfrag(v)
                 g = g0.detach().clone().contiguous()
                 ks = None if kscale is None else kscale.detach().contiguous()
                 states, gammas = plan.rk_forward(g, dt, n_steps, kscale=ks)

@@ -249,3 +249,51 @@ def test_algorithmic_flops_count_each_cells_level():
     want2 = 2.0 * np.count_nonzero(fold(t2.export(0), P2, NO2, np.triu_indices(P2))) * 7
     both = G.Plan([t, t2], [C, 7], precision="fp64", vfrag=np.concatenate([vf, np.full(7, 0.5)]))
     assert both.algorithmic_flops() == want + want2
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_set_vfrag_rebrackets_in_place(oracle, prec):
+    """New per-cell thresholds on an existing plan (gd_plan_set_vfrag): the brackets and
+    blend weights are rebuilt in the plan's buffers, and the right-hand side and the
+    reverse pass equal those of a plan created with the new thresholds (same kernels,
+    same tiles: bit for bit), and the oracle at the new thresholds."""
+    O = oracle
+    t, cfg, g, ks, vf = _level_case(O)
+    C = len(g)
+    rng = np.random.default_rng(77)
+    vf2 = rng.uniform(0.25, 1.05, C)               # also outside the table (clamped)
+    vf2[:200] = 0.55                                # one crowded bracket
+    gd = torch.tensor(g, device=DEV).view(-1)
+    ksd = torch.tensor(ks, device=DEV)
+    plan = G.Plan(t, C, precision=prec, vfrag=vf)
+    print(f"set_vfrag {prec} C={C}", flush=True)
+    # reverse-mode workspace first, so that it is rebuilt too
+    st, gm = plan.rk_forward(gd.clone(), 1e-9, 1, kscale=ksd)
+    plan.adjoint(st, gm, 1e-9, 1, torch.ones_like(gd), kscale=ksd)
+    plan.set_vfrag(vf2)
+    fresh = G.Plan(t, C, precision=prec, vfrag=vf2)
+    r1, r2 = _raw(plan, gd, ksd), _raw(fresh, gd, ksd)
+    assert torch.equal(r1, r2)
+    idx = np.arange(0, C, 41)
+    Yo, _, _ = O.rhs(cfg, g[idx], kscale=ks[idx], vfrag=vf2[idx])
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert _eps(r1.view(C, -1)[idx].cpu().numpy(), Yo).max() <= tol
+    outs = []
+    for p in (plan, fresh):
+        gg = gd.clone()
+        st, gm = p.rk_forward(gg, 1e-9, 2, kscale=ksd)
+        lam = torch.ones_like(gd)
+        dks, dvf = p.adjoint(st, gm, 1e-9, 2, lam, kscale=ksd)
+        outs.append((gg, lam, dks, dvf))
+    for name, a, b in zip(("state", "dL/dg0", "dL/dkscale", "dL/dvfrag"), *outs):
+        d = float((a - b).abs().max())
+        print(f"  {name}: max |difference| {d:.3e} (scale {float(b.abs().max()):.3e})", flush=True)
+        assert torch.equal(a, b), name
+    # back to the original thresholds
+    plan.set_vfrag(vf)
+    assert torch.equal(_raw(plan, gd, ksd), _raw(G.Plan(t, C, precision=prec, vfrag=vf), gd, ksd))
+    with pytest.raises(G.GDError):
+        bad = vf.copy()
+        bad[3] = np.nan
+        plan.set_vfrag(bad)
+    assert torch.equal(_raw(plan, gd, ksd), _raw(G.Plan(t, C, precision=prec, vfrag=vf), gd, ksd))

@@ -195,19 +195,29 @@ def test_rk_matches_oracle_constant_kernel(oracle, prec):
 def test_rk_matches_oracle_fragmentation(oracle, prec, name):
     """Ballistic kernel with the power-law fragmentation, and the coupled model of
     Sec. 4.5 (Maxwellian outcomes, general breakage with remnants); conservative
-    flux, per-cell kernel scale; several cells.  The first runs 20 steps of half the
-    Eq. dt bound.  The second runs 10 steps of 0.05 (the oracle reports hundreds of
-    violations at half the bound, 0.78): its fragments pile up in the lowest bins,
-    which grow by ~10% per step of 0.2, and over longer horizons that growth
-    amplifies the contraction's rounding (one-step errors stay at 1e-7 split-FP16,
-    1e-15 FP64)."""
+    flux, per-cell kernel scale; several cells.  The first and third run 20 steps of
+    half the Eq. dt bound.  The coupled model runs to tau = 4 in 40 steps of 0.1 (at
+    half the Eq. dt bound, 0.78, the oracle reports hundreds of violations).
+
+    Its step is set by linear stability, not by Eq. dt: the fragments pile up in the
+    lowest bins of some cells, the spectral radius of the Jacobian of L there grows
+    from 1.6 to 17 by tau = 4, and with steps of 0.2 an eigenvalue (-16.6 + 2.5i)
+    leaves the stability region of SSP-RK3 (|R(dt lambda)| = 3.0 per step), so that
+    any rounding, FP64 or split, grows geometrically.  With steps of 0.1 every
+    |R| <= 1.003.  Bound of the split-FP16 state error at tau = 4: one right-hand side
+    carries at most 1e-6 of the cell's largest raw entry (test above); injecting
+    normwise noise of that kind into the oracle's raw vector on these 40 cells
+    (1e-7 of the largest entry, Gaussian per entry) moves the final bin masses by at
+    most 8.1e-7, i.e. an amplification of 8.1 along this trajectory, so 1e-6 per
+    evaluation bounds the state error by ~8e-6: tolerance 1e-5 (FP64: 1e-11)."""
     O = oracle
     t, cfg = _pair(O, name)
     C = 40
     g, p = _states(O, cfg, C, seed=9)
     ks = p["kscale"]
     g, _ = O.limit(cfg, g)
-    dt, n = (0.05, 10) if name == "coupled_k2" else (0.5 * O.cfl_dt(cfg, g, kscale=ks), 20)
+    dt, n = (0.1, 40) if name == "coupled_k2" else (0.5 * O.cfl_dt(cfg, g, kscale=ks), 20)
+    print(f"case {name} {prec} C={C} dt={dt:g} steps={n}", flush=True)
     go, vo = O.rk(cfg, g, dt, n, kscale=ks)
     plan = G.Plan(t, C, precision=prec)
     gd = torch.tensor(g, device=DEV).view(-1)
@@ -217,7 +227,9 @@ def test_rk_matches_oracle_fragmentation(oracle, prec, name):
     err = np.max(np.abs((gg - go) * h), axis=1) / np.max(np.abs(go * h), axis=1)
     assert vo == 0
     _check_tail_negativity(gg, h, cfg.k + 1, v, prec)
-    assert err.max() <= (1e-11 if prec == "fp64" else 1e-6), err.max()
+    tol = 1e-11 if prec == "fp64" else (1e-5 if name == "coupled_k2" else 1e-6)
+    print(f"  state error max {err.max():.2e} median {np.median(err):.2e} (tol {tol:.0e})", flush=True)
+    assert err.max() <= tol, err.max()
     # exact mass conservation of the conservative flux, in FP64 bookkeeping
     m0 = (g * h)[:, ::cfg.k + 1].sum(axis=1)
     m1 = (gg * h)[:, ::cfg.k + 1].sum(axis=1)
@@ -236,6 +248,15 @@ def test_violation_counter_fires_beyond_cfl(oracle):
     gd = torch.tensor(g, device=DEV).view(-1)
     v = plan.rk_step(gd, dt, 2, count_violations=True)
     assert vo > 0 and v > 0
+    # through the C ABI the call reports it in its return code (the steps are taken)
+    import ctypes
+    gd = torch.tensor(g, device=DEV).view(-1)
+    cnt = ctypes.c_longlong(-1)
+    assert G.lib().gd_rk_step(plan.h, G._ptr(gd), None, dt, 2, ctypes.byref(cnt)) == G.GD_EPOSITIVITY
+    assert cnt.value == v
+    cnt = ctypes.c_longlong(-1)
+    assert G.lib().gd_rk_step(plan.h, G._ptr(torch.tensor(g, device=DEV).view(-1)), None, 1e-12, 1,
+                              ctypes.byref(cnt)) == G.GD_OK and cnt.value == 0
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
@@ -363,3 +384,97 @@ def test_large_batch_sampled(oracle, prec):
     assert float(((m1 - m0).abs() / m0).max()) <= 1e-12
     del plan, raw, g0
     torch.cuda.empty_cache()
+
+
+def _golden(name):
+    import json
+    import os
+    return json.load(open(os.path.join(os.path.dirname(__file__), "golden", name)))
+
+
+def test_c2_single_cell_trajectory_both_precisions():
+    """The single-cell ballistic workload (32 bins of order 2 on [1e-4, 1e8], power-law
+    fragmentation above v_frag = 0.5, conservative flux, LN(0,1) unit-mass profile),
+    1000 SSP-RK3 steps of dt = 5e-7 in calls of 100, 200 and 700 steps, against the
+    oracle's states after each call (tests/golden/c2_trajectory.json, written by the
+    oracle alone).  Metric: max_i |h_j (g_gpu - g_oracle)_j^i| / max |h_j g_oracle| (bin
+    masses).  FP64: the contraction differs from the nested sums by ~1e-15 per
+    evaluation and the step is far inside the CFL bound (no violation on either side),
+    so the states stay within 1e-11.  Split FP16: ~1e-7 of the largest flux per
+    evaluation, bounded by 1e-6 on the states."""
+    gold = _golden("c2_trajectory.json")
+    c = gold["config"]
+    t = G.Tensor(c["N"], c["k"], c["xmin"], c["xmax"], kernel=c["kernel"], frag=c["frag"], levels=(c["vfrag"],),
+                 conservative=c["conservative"])
+    h = np.repeat(np.diff(t.edges()), c["k"] + 1)
+    assert gold["violations"] == 0
+    for prec, tol in (("fp64", 1e-11), ("mixed", 1e-6)):
+        plan = G.Plan(t, 1, precision=prec)
+        g = torch.tensor(gold["g0"], device=DEV)
+        n = 0
+        for m in (100, 200, 700):
+            v = plan.rk_step(g, gold["dt"], m, count_violations=True)
+            n += m
+            ref = np.asarray(gold["states"][str(n)])
+            err = np.max(np.abs((g.cpu().numpy() - ref) * h)) / np.max(np.abs(ref * h))
+            print(f"c2 {prec}: {n} steps, state error {err:.2e} (tol {tol:.0e}), violations {v}", flush=True)
+            assert err <= tol, (prec, n, err)
+            if prec == "fp64":
+                assert v == 0
+
+
+def test_transport_shifts_rows_exactly():
+    """gd_advect at Courant number 1 moves every bin one cell along its group's row
+    (downstream for a positive velocity, upstream for a negative one), bit for bit; the
+    row of each group is its own."""
+    t1 = G.Tensor(8, 2, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=(0.5,), conservative=True)
+    t2 = G.Tensor(6, 1, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=(0.5,), conservative=True)
+    plan = G.Plan([t1, t2], [11, 7], precision="fp64")
+    g = torch.rand(plan.n_values, dtype=torch.float64, device=DEV)
+    vel = np.concatenate([np.where(np.arange(8) % 2, -4.0, 4.0), np.full(6, -4.0)])
+    out = g.clone()
+    plan.advect(out, vel, 0.25, 1.0, periodic=True)
+    a = g[:11 * 24].view(11, 8, 3).cpu().numpy()
+    b = out[:11 * 24].view(11, 8, 3).cpu().numpy()
+    for j in range(8):
+        assert np.array_equal(b[:, j], np.roll(a[:, j], 1 if vel[j] > 0 else -1, axis=0))
+    a2 = g[11 * 24:].view(7, 6, 2).cpu().numpy()
+    b2 = out[11 * 24:].view(7, 6, 2).cpu().numpy()
+    assert np.array_equal(b2, np.roll(a2, -1, axis=0))
+    with pytest.raises(G.GDError):
+        plan.advect(out, vel * 1.01, 0.25, 1.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_split_step_matches_oracle(oracle, prec):
+    """Strang splitting of upwind transport between the cells of a row (each mass bin with
+    its own drift velocity, Courant number up to 0.8 per half step, periodic) and the
+    SSP-RK3 collision step, against the oracle's split step: three steps on 48 cells with
+    per-cell kernel scales.  FP64 within 1e-11 and split FP16 within 1e-6 normwise per
+    cell (bin masses), and the total mass of the row kept to 1e-12 (conservative flux,
+    periodic transport)."""
+    O = oracle
+    t, cfg = _pair(O, "add_k1")
+    C = 48
+    g, p = _states(O, cfg, C, seed=13)
+    ks = p["kscale"]
+    g, _ = O.limit(cfg, g)
+    dt = 0.5 * O.cfl_dt(cfg, g, kscale=ks)
+    e = O.edges(cfg)
+    xc = np.sqrt(e[:-1] * e[1:])
+    vel = np.where(np.arange(cfg.N) % 3 == 0, -1.0, 1.0) * (xc / xc.max()) ** (1 / 3)
+    dx = np.abs(vel).max() * 0.5 * dt / 0.8
+    print(f"case split {prec} C={C} dt={dt:.3e} steps=3", flush=True)
+    go, vo = O.split_step(cfg, g, vel, dx, dt, 3, kscale=ks)
+    plan = G.Plan(t, C, precision=prec)
+    gd = torch.tensor(g, device=DEV).view(-1)
+    v = plan.split_step(gd, vel, dx, dt, 3, kscale=torch.tensor(ks, device=DEV), count_violations=True)
+    gg = gd.cpu().numpy().reshape(C, -1)
+    h = np.tile(np.repeat(np.diff(e), cfg.k + 1), (C, 1))
+    err = np.max(np.abs((gg - go) * h), axis=1) / np.max(np.abs(go * h), axis=1)
+    assert vo == 0
+    _check_tail_negativity(gg, h, cfg.k + 1, v, prec)
+    assert err.max() <= (1e-11 if prec == "fp64" else 1e-6), err.max()
+    m0 = (g * h)[:, ::cfg.k + 1].sum()
+    m1 = (gg * h)[:, ::cfg.k + 1].sum()
+    assert abs(m1 - m0) / m0 <= 1e-12

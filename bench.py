@@ -112,6 +112,7 @@ def cpu_baseline(w, params, seconds):
     from paper_2607_13740_amd import workloads as W
 
     O.build(force=False)
+    flags = O.use_native()
     shapes = w.groups if w.groups else ((w.bins, w.order),)
     cfgs = [O.Config(N=N, k=k, xmin=w.x_min, xmax=w.x_max, kernel=w.kernel, frag=w.frag,
                      conservative=w.conservative, vfrag=w.levels[0],
@@ -155,17 +156,35 @@ def cpu_baseline(w, params, seconds):
     m1 = int(max(1, min(m, 0.1 * seconds / max(dt * cores / m, 1e-9))))
     dt1 = run(m1)
     O.set_threads(cores)
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
-    except OSError:
-        pass
     return {"value": m / dt, "unit": "cell-evals/s", "cores": cores, "kind": "oracle",
             "sample": f"first {m} cells of {w.name}, one right-hand-side evaluation each, FP64 nested "
-                      f"Gauss-Legendre sums in C (gcc -O2, OpenMP across cells), {dt:.1f} s",
+                      f"Gauss-Legendre sums in C (gcc {flags}, OpenMP across cells), {dt:.1f} s",
             "one_thread": {"value": m1 / dt1, "sample": f"first {m1} cells, {dt1:.1f} s"},
-            "cpu_model": model, "host_cpus": os.cpu_count()}
+            "cpu": host_cpu(), "host_cpus": os.cpu_count()}
+
+
+def host_cpu():
+    """What the host reports about its processor: the model string and family/model/
+    stepping of /proc/cpuinfo, the vector extensions the native build can use, and the
+    cores this process may run on."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ":" not in ln:
+                    if info:
+                        break
+                    continue
+                key, val = (x.strip() for x in ln.split(":", 1))
+                if key in ("vendor_id", "model name", "cpu family", "model", "stepping", "cpu MHz", "flags") \
+                        and key not in info:
+                    info[key] = val
+    except OSError:
+        pass
+    flags = set(info.pop("flags", "").split())
+    info["vector_ext"] = [f for f in ("avx2", "fma", "avx512f", "avx512_bf16", "avx512vl") if f in flags]
+    info["usable_cores"] = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return info
 
 
 def cpu_blas_reference(t, g0, ks, vf, w, cells=2048):

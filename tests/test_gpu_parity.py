@@ -410,7 +410,7 @@ def test_c2_single_cell_trajectory_both_precisions():
     assert gold["violations"] == 0
     for prec, tol in (("fp64", 1e-11), ("mixed", 1e-6)):
         plan = G.Plan(t, 1, precision=prec)
-        g = torch.tensor(gold["g0"], device=DEV)
+        g = torch.tensor(gold["g0"], dtype=torch.float64, device=DEV)
         n = 0
         for m in (100, 200, 700):
             v = plan.rk_step(g, gold["dt"], m, count_violations=True)

@@ -195,6 +195,29 @@ void gd_plan_destroy(gd_plan* plan);
  */
 int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, double* rhs, double* raw);
 
+/*
+ * gd_collision_rhs_noalloc -- gd_collision_rhs for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): L[g] (Eq. evo) of n_cells cells of tensor t, level 0 of its threshold
+ * table for every cell (theta = 0), with no plan.  It allocates nothing: its
+ * workspace (group descriptor, work items, split operands and weights, per-cell
+ * exponents, raw flux vector) lives in a 16 MiB static device array that each GPU the
+ * library runs on holds until the process ends.  The caller passes inputs and outputs:
+ *  t        : a tensor whose device layouts exist (gd_tensor_upload, or a plan on it);
+ *             GD_EINVAL otherwise.
+ *  precision: GD_PREC_FP64 or GD_PREC_MIXED_F16X3.
+ *  g, kscale, rhs, raw : device, as gd_collision_rhs with n_cells cells (raw may be NULL).
+ *  stream   : hipStream_t (NULL = the null stream); asynchronous.
+ * Limit: the workspace of n_cells must fit in the 16 MiB.  Per cell, split FP16:
+ * 64 KS + 4 P + 4 ystride + 4 bytes (KS = ceil(P/16), ystride = 32 ceil(n_out/32)),
+ * i.e. 1156 B at P = 96 (about 14,000 cells) and 2564 B at P = 208 (about 6,500);
+ * FP64: 8 ystride bytes (ystride = 16 ceil(n_out/16)), 768 B at P = 96.  Beyond it:
+ * GD_EINVAL, nothing launched.  Every call on a GPU shares that GPU's array
+ * and leaves its contents behind; calls that overlap on one GPU (several streams or
+ * threads) race and must be serialised by the caller.
+ */
+int gd_collision_rhs_noalloc(const gd_tensor* t, int precision, int n_cells, const double* g,
+                             const double* kscale, double* rhs, double* raw, void* stream);
 
 /*
  * gd_rk_step -- n_steps of SSP-RK3 (Eq. RK3) in place on g, with the scaling

@@ -26,7 +26,7 @@ HIP_FLAGS = [
 ]
 
 
-SOURCES_HIP = ["api.hip", "contract_mixed.hip", "contract_fp64.hip", "state.hip", "adjoint.hip", "hydro.hip"]
+SOURCES_HIP = ["api.hip", "contract_mixed.hip", "contract_fp64.hip", "state.hip", "adjoint.hip", "noalloc.hip", "hydro.hip"]
 
 
 def build(verbose: bool = False) -> str:

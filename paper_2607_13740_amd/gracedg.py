@@ -86,6 +86,7 @@ def lib():
             "gd_advect": ([_VP, _VP, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_int], ctypes.c_int),
             "gd_split_step": ([_VP, _VP, _VP, _DP, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+            "gd_collision_rhs_noalloc": ([_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
             "gd_rk_step": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_rk_advance": ([_VP, _VP, _VP, _VP, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -198,6 +199,25 @@ class Tensor:
         """Device layouts of both contraction precisions now (gd_tensor_upload)."""
         _check(lib().gd_tensor_upload(self.h))
         return self
+
+    def collision_rhs_noalloc(self, g, precision="mixed", kscale=None, rhs=None, raw=None, stream=None):
+        """L[g] of the cells in g ([C*P] float64 device) with level 0 of the threshold
+        table and no allocation in the library (gd_collision_rhs_noalloc); rhs (and raw,
+        [C*n_out]) are the caller's."""
+        import torch
+        C = g.numel() // self.P
+        if C * self.P != g.numel():
+            raise ValueError("g must hold whole cells")
+        if rhs is None:
+            rhs = torch.empty_like(g)
+        _dev64(g, C * self.P, "g")
+        _dev64(rhs, C * self.P, "rhs")
+        _dev64(kscale, C, "kscale")
+        _dev64(raw, C * self.n_out, "raw")
+        st = stream if stream is not None else torch.cuda.current_stream(g.device).cuda_stream
+        _check(lib().gd_collision_rhs_noalloc(self.h, PREC[precision], int(C), _ptr(g), _ptr(kscale), _ptr(rhs),
+                                              _ptr(raw), ctypes.c_void_p(st)))
+        return rhs
 
     def __del__(self):
         h = getattr(self, "h", None)

@@ -418,6 +418,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--variant", default=None,
                     help="waves,rows,xcd[,tiles_per_wave] of the contraction instead of the autotuner's choice")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes of the RK step (cell ranges stepped side by side; 0 = the library's choice by size)")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only copy a 512 MiB float64 buffer three times (the reference kernel that scales "
                          "rocprofv3's FETCH_SIZE/WRITE_SIZE counters to bytes) and exit")
@@ -461,12 +463,13 @@ def main():
             tune = {"waves": vv[0], "rows": vv[1], "xcd": vv[2], "tiles_per_wave": tp, "fixed": True}
         else:
             tune = plan.autotune(g, kscale=ks)
+        plan.set_lanes(args.lanes)
         ms, kms, launches, sms, dist = time_steps(plan, g, w, ks, args.steps, args.warmup)
         res[prec] = {"ms_per_step": ms, "kernel_ms": kms, "launches": launches, "plan": plan, "stage_ms": sms,
-                     "variant": plan.variant(), "tune": tune, "step_ms_dist": dist}
+                     "variant": plan.variant(), "tune": tune, "step_ms_dist": dist, "lanes": plan.lanes()}
         print(f"# {prec}: {ms:.3f} ms/step, contraction {kms:.4f} ms/launch over {launches} launches, "
               f"stage kernel {sms:.4f} ms/launch, "
-              f"variant {res[prec]['variant']}", file=sys.stderr, flush=True)
+              f"variant {res[prec]['variant']}, lanes {res[prec]['lanes']}", file=sys.stderr, flush=True)
         # mass drift over the run (FP64 bookkeeping of the bin masses), cell by cell
         drift, voff = 0.0, 0
         for t, n in zip(tensors, counts):
@@ -538,7 +541,10 @@ def main():
                    "P": [t.P for t in tensors] if len(tensors) > 1 else tensors[0].P,
                    "precision": "split FP16 (hi+lo, 3 MFMA products) with FP32 MFMA accumulation, FP64 p-sum, "
                                 "FP64 state/limiter/RK",
-                   "contraction_variant": mixed["variant"], "step": "one captured HIP graph per RK step"},
+                   "contraction_variant": mixed["variant"],
+                   "lanes": {"count": mixed["lanes"][0], "first_tiles": mixed["lanes"][1]},
+                   "step": "one captured HIP graph per RK step and lane; lanes (cell ranges of equal cost) "
+                           "step side by side on streams of their own and join at the end of the call"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_F16_TFLOPS,
                      "traffic": measured_traffic(mixed["variant"]) if w.name == "c3_batched" else None,
@@ -562,7 +568,7 @@ def main():
         out["fp64_gpu"] = {"value": f_evals, "ms_per_step": f["ms_per_step"], "kernel_ms": f["kernel_ms"],
                            "step_ms_single_replays": f["step_ms_dist"],
                            "achieved_tflops": flops_launch / (f["kernel_ms"] * 1e-3) / 1e12,
-                           "variant": f["variant"],
+                           "variant": f["variant"], "lanes": f["lanes"][0],
                            "peak_tflops": PEAK_F64_TFLOPS, "mass_drift": f["mass_drift"],
                            "per_cell_steps": f["adaptive"]}
         out["speedup_mixed_vs_fp64"] = cell_evals / f_evals

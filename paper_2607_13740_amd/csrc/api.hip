@@ -2,6 +2,7 @@
 // (groups of hydro cells, workspaces, threshold brackets) and the calls that run
 // the right-hand side and the SSP-RK3 step.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -532,6 +533,21 @@ struct SubstepGraph {
     double t_end = 0.0, cfl = 0.0, dt_max = 0.0, floor = 0.0;
 };
 
+// An execution lane of the fixed RK step: the cells of a contiguous range of 32-slot
+// tiles, with the contraction items of those tiles only.  Cells never interact, so
+// the lanes of a plan run their steps on streams of their own and meet only at the
+// end of the call: one lane's memory-bound stage kernel and the tail of its
+// contraction overlap the other lane's contraction.
+struct Lane {
+    int t0 = 0, t1 = 0;                     // 32-slot tiles [t0, t1) over all groups
+    int4* items = nullptr;
+    size_t items_cap = 0;
+    int n_items = 0;
+    hipStream_t stream = nullptr;           // lanes after the first: private stream (lane 0: the plan's)
+    hipEvent_t done = nullptr;
+    StepGraph graph;
+};
+
 struct gd_plan {
     std::vector<Group> groups;
     int prec = GD_PREC_FP64;
@@ -546,6 +562,9 @@ struct gd_plan {
     int n_items = 0;
     size_t items_cap = 0;
     double exec_flops = 0.0;                // MFMA flops one contraction launch executes
+    int lanes_req = 0;                      // requested lanes of the fixed step (0: by size)
+    std::vector<Lane> lanes;                // more than one: gd_rk_step runs them side by side
+    hipEvent_t fork = nullptr;
     bool use_graph = true;
     StepGraph graph;
     SubstepGraph sgraph;
@@ -567,10 +586,22 @@ struct gd_plan {
     bool timing = false;
     KernelTimer timer, stimer;              // contraction and stage launches
     std::vector<void*> allocs;
+    void release_lane(Lane& L)
+    {
+        if (L.graph.exec) (void)hipGraphExecDestroy(L.graph.exec);
+        if (L.items) (void)hipFree(L.items);
+        if (L.done) (void)hipEventDestroy(L.done);
+        if (L.stream && L.stream != stream) (void)hipStreamDestroy(L.stream);
+        L = Lane{};
+    }
     void drop_graph()
     {
         if (graph.exec) (void)hipGraphExecDestroy(graph.exec);
         graph = StepGraph{};
+        for (Lane& L : lanes) {
+            if (L.graph.exec) (void)hipGraphExecDestroy(L.graph.exec);
+            L.graph = StepGraph{};
+        }
         if (sgraph.exec) (void)hipGraphExecDestroy(sgraph.exec);
         sgraph = SubstepGraph{};
     }
@@ -578,6 +609,8 @@ struct gd_plan {
     {
         drop_graph();
         if (cap) (void)hipStreamDestroy(cap);
+        for (Lane& L : lanes) release_lane(L);
+        if (fork) (void)hipEventDestroy(fork);
         for (KernelTimer* T : {&timer, &stimer})
             for (auto& e : T->ev) {
                 (void)hipEventDestroy(e.first);
@@ -622,7 +655,8 @@ static constexpr int kSlotGranule = 32;
 // Item list of one contraction over every group of the plan: the lists of schedule
 // `which` (0: the plan's forward precision, 1: the FP64 vector-Jacobian product),
 // workgroups over W consecutive tiles of ts slots.
-static int make_items(const gd_plan* pl, int which, int W, int rows, int xcd, std::vector<int4>& h, double* flops)
+static int make_items(const gd_plan* pl, int which, int W, int rows, int xcd, std::vector<int4>& h, double* flops,
+                      int lt0 = 0, int lt1 = INT_MAX)
 {
     // item word z: first row block | end row block << 10 | valid tiles << 20
     const bool mixed = which == 0 && pl->prec == GD_PREC_MIXED_F16X3;
@@ -641,8 +675,12 @@ static int make_items(const gd_plan* pl, int which, int W, int rows, int xcd, st
         const int NOB = S.NOB;
         if (NOB > 1023 || W > 2047) return fail(GD_EUNSUPPORTED, "too many row blocks for the work-item encoding");
         const int nr = rows <= 0 ? NOB : std::min(NOB, rows);
+        // the lane's 32-slot tiles [lt0, lt1), in this group's tiles of ts slots
+        const int la = std::max(0, lt0 - G.tile_off) * (32 / ts);
+        const int lb = int(std::min<long long>((long long)lt1 - G.tile_off, G.tiles32)) * (32 / ts);
         for (const Bracket& b : G.brackets) {
-            const int t0 = b.s0 / ts, t1 = cdiv(b.s0 + b.n, ts);
+            const int t0 = std::max(b.s0 / ts, la), t1 = std::min(cdiv(b.s0 + b.n, ts), lb);
+            if (t0 >= t1) continue;
             for (int ob = 0; ob < NOB; ob += nr) {
                 const int ob1 = std::min(NOB, ob + nr);
                 if (!S.list_n.empty() && S.list_n[size_t(b.r) * NOB + ob] == 0) continue;   // empty list
@@ -702,6 +740,64 @@ static int upload_items(const std::vector<int4>& h, int4** dev, size_t* cap)
     return GD_OK;
 }
 
+// lanes of the fixed step when none are requested: two once the batch fills the
+// chip several times over (one workgroup of 8 tiles per item, two items per CU)
+static constexpr int kLaneMinTiles = 1024;
+static constexpr int kMaxLanes = 8;
+
+// Lane boundaries at equal contraction cost (every tile of a bracket costs the sum
+// of its row-block lists), the items of every lane, and the lanes' streams.
+static int build_lanes(gd_plan* pl)
+{
+    const int want = pl->lanes_req > 0 ? pl->lanes_req : (pl->tiles32 >= kLaneMinTiles ? 2 : 1);
+    const int n = std::max(1, std::min(want, pl->tiles32));
+    pl->drop_graph();
+    const size_t keep = n == 1 ? 0 : size_t(n);
+    for (size_t l = keep; l < pl->lanes.size(); ++l) pl->release_lane(pl->lanes[l]);
+    pl->lanes.resize(keep);
+    if (n == 1) return GD_OK;
+    const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
+    std::vector<long long> cost(size_t(pl->tiles32), 0);
+    for (const Group& G : pl->groups) {
+        const Schedule& S = mixed ? G.t->mixed : G.t->f64;
+        for (const Bracket& b : G.brackets) {
+            long long c = 0;
+            for (int ob = 0; ob < S.NOB; ++ob) c += S.list_cost[size_t(b.r) * S.NOB + ob];
+            for (int t = b.s0 / 32; t < cdiv(b.s0 + b.n, 32); ++t) cost[size_t(G.tile_off + t)] += c;
+        }
+    }
+    long long total = 0;
+    for (long long c : cost) total += c;
+    int t = 0;
+    long long pre = 0;
+    for (int l = 0; l < n; ++l) {
+        Lane& L = pl->lanes[size_t(l)];
+        L.t0 = t;
+        if (l == n - 1) {
+            t = pl->tiles32;
+        } else {
+            // at least one tile per lane, and one left for each later lane
+            const long long target = total * (l + 1) / n;
+            while (t < pl->tiles32 - (n - 1 - l) && (t == L.t0 || pre + cost[size_t(t)] / 2 < target))
+                pre += cost[size_t(t++)];
+        }
+        L.t1 = t;
+        std::vector<int4> h;
+        int rc = make_items(pl, 0, pl->waves * pl->tpw, pl->rows, pl->xcd, h, nullptr, L.t0, L.t1);
+        if (!rc) rc = upload_items(h, &L.items, &L.items_cap);
+        if (rc) return rc;
+        L.n_items = int(h.size());
+        if (l == 0) {
+            L.stream = pl->stream;
+        } else if (!L.stream) {
+            HIP_TRY(hipStreamCreateWithFlags(&L.stream, hipStreamNonBlocking));
+        }
+        if (!L.done) HIP_TRY(hipEventCreateWithFlags(&L.done, hipEventDisableTiming));
+    }
+    if (!pl->fork) HIP_TRY(hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming));
+    return GD_OK;
+}
+
 static int build_items(gd_plan* pl)
 {
     std::vector<int4> h;
@@ -712,7 +808,7 @@ static int build_items(gd_plan* pl)
     pl->n_items = int(h.size());
     pl->exec_flops = fl;
     pl->drop_graph();
-    return GD_OK;
+    return build_lanes(pl);
 }
 
 // Threshold brackets of one group (tensors with several levels): bracket r and blend
@@ -923,6 +1019,23 @@ extern "C" int gd_plan_variant(const gd_plan* pl, int* waves, int* tiles_per_wav
     return GD_OK;
 }
 
+extern "C" int gd_plan_set_lanes(gd_plan* pl, int lanes)
+{
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    if (lanes < 0 || lanes > kMaxLanes) return fail(GD_EINVAL, "lanes must be 0 (by size) .. 8");
+    pl->lanes_req = lanes;
+    return build_lanes(pl);
+}
+
+extern "C" int gd_plan_lanes(const gd_plan* pl, int* lanes, int* first_tiles)
+{
+    if (!pl || !lanes) return fail(GD_EINVAL, "null argument");
+    *lanes = pl->lanes.empty() ? 1 : int(pl->lanes.size());
+    if (first_tiles)
+        for (int l = 0; l < *lanes; ++l) first_tiles[l] = pl->lanes.empty() ? 0 : pl->lanes[size_t(l)].t0;
+    return GD_OK;
+}
+
 extern "C" int gd_plan_use_graph(gd_plan* pl, int enable)
 {
     if (!pl) return fail(GD_EINVAL, "null plan");
@@ -957,7 +1070,7 @@ struct AdaptArgs {
 
 static int stage(gd_plan* pl, hipStream_t s, int mode, int limit, int split, const double* kscale,
                  const double* gn, const double* gs, double* out, double dt, double* raw, double* gamma = nullptr,
-                 const AdaptArgs* ad = nullptr)
+                 const AdaptArgs* ad = nullptr, const Lane* lane = nullptr)
 {
     StageArgs a{};
     if (ad) {
@@ -971,7 +1084,8 @@ static int stage(gd_plan* pl, hipStream_t s, int mode, int limit, int split, con
     a.gamma = gamma;
     a.groups = pl->groups_dev;
     a.n_groups = int(pl->groups.size());
-    a.n_tiles = pl->tiles32;
+    a.tile0 = lane ? lane->t0 : 0;
+    a.n_tiles = lane ? lane->t1 - lane->t0 : pl->tiles32;
     a.max_p = pl->max_p;
     a.mode = mode;
     a.limit = limit;
@@ -993,12 +1107,12 @@ static int stage(gd_plan* pl, hipStream_t s, int mode, int limit, int split, con
 
 // one contraction launch over every group on stage state gs (the split path reads
 // the fragments the previous stage kernel wrote from gs)
-static int contract(gd_plan* pl, hipStream_t s, const double* gs)
+static int contract(gd_plan* pl, hipStream_t s, const double* gs, const Lane* lane = nullptr)
 {
     hipEvent_t ev_end;
     int rc = timer_begin(pl, pl->timer, s, &ev_end);
     if (rc) return rc;
-    ContractArgs a{pl->groups_dev, pl->items, gs, pl->n_items};
+    ContractArgs a{pl->groups_dev, lane ? lane->items : pl->items, gs, lane ? lane->n_items : pl->n_items};
     rc = (pl->prec == GD_PREC_MIXED_F16X3) ? launch_contract_mixed(a, pl->ksmax, pl->waves, pl->tpw, s)
                                                : launch_contract_fp64(a, pl->ksmax, pl->waves, s);
     if (rc) return rc;
@@ -1020,24 +1134,28 @@ extern "C" int gd_collision_rhs(gd_plan* pl, const double* g, const double* ksca
 
 // y1 = gn + dt L(gn); y2 = 3/4 gn + 1/4 (y1 + dt L(y1)); gn = 1/3 gn + 2/3 (y2 + dt L(y2)),
 // each stage limited (and split for the next contraction) as it is written
-static int step_launches(gd_plan* pl, hipStream_t s, double* g, const double* kscale, double dt)
+static int step_launches(gd_plan* pl, hipStream_t s, double* g, const double* kscale, double dt,
+                         const Lane* lane = nullptr)
 {
     const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
     int rc;
-    if ((rc = contract(pl, s, g))) return rc;
-    if ((rc = stage(pl, s, 1, 1, split, kscale, g, g, pl->y1, dt, nullptr))) return rc;
-    if ((rc = contract(pl, s, pl->y1))) return rc;
-    if ((rc = stage(pl, s, 2, 1, split, kscale, g, pl->y1, pl->y2, dt, nullptr))) return rc;
-    if ((rc = contract(pl, s, pl->y2))) return rc;
-    return stage(pl, s, 3, 1, split, kscale, g, pl->y2, g, dt, nullptr);
+    if ((rc = contract(pl, s, g, lane))) return rc;
+    if ((rc = stage(pl, s, 1, 1, split, kscale, g, g, pl->y1, dt, nullptr, nullptr, nullptr, lane))) return rc;
+    if ((rc = contract(pl, s, pl->y1, lane))) return rc;
+    if ((rc = stage(pl, s, 2, 1, split, kscale, g, pl->y1, pl->y2, dt, nullptr, nullptr, nullptr, lane))) return rc;
+    if ((rc = contract(pl, s, pl->y2, lane))) return rc;
+    return stage(pl, s, 3, 1, split, kscale, g, pl->y2, g, dt, nullptr, nullptr, nullptr, lane);
 }
 
-// capture one RK step on the plan's private stream (nothing runs while capturing)
-static int capture_step(gd_plan* pl, double* g, const double* kscale, double dt)
+// capture one RK step (of one lane, or of the whole plan) on the plan's private
+// stream (nothing runs while capturing)
+static int capture_step(gd_plan* pl, double* g, const double* kscale, double dt, Lane* lane = nullptr)
 {
-    pl->drop_graph();
+    StepGraph& G = lane ? lane->graph : pl->graph;
+    if (G.exec) (void)hipGraphExecDestroy(G.exec);
+    G = StepGraph{};
     HIP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-    int rc = step_launches(pl, pl->cap, g, kscale, dt);
+    int rc = step_launches(pl, pl->cap, g, kscale, dt, lane);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(pl->cap, &graph);
     if (rc) {
@@ -1049,10 +1167,10 @@ static int capture_step(gd_plan* pl, double* g, const double* kscale, double dt)
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(GD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    pl->graph.exec = exec;
-    pl->graph.g = g;
-    pl->graph.kscale = kscale;
-    pl->graph.dt = dt;
+    G.exec = exec;
+    G.g = g;
+    G.kscale = kscale;
+    G.dt = dt;
     return GD_OK;
 }
 
@@ -1066,8 +1184,28 @@ static int rk_steps(gd_plan* pl, double* g, const double* kscale, double dt, int
     // limiter on the start state (and its split for the first contraction)
     if ((rc = stage(pl, s, -1, 1, split, kscale, nullptr, g, nullptr, dt, nullptr))) return rc;
     const bool graph = pl->use_graph && !pl->timing && n_steps > 0;
-    if (graph && !(pl->graph.exec && pl->graph.g == g && pl->graph.kscale == kscale && pl->graph.dt == dt))
-        if ((rc = capture_step(pl, g, kscale, dt))) return rc;
+    auto current = [&](const StepGraph& G) { return G.exec && G.g == g && G.kscale == kscale && G.dt == dt; };
+    if (pl->lanes.size() > 1 && !pl->timing && n_steps > 0) {
+        // every lane takes all n_steps on its own stream, forked from and joined to s
+        if (graph)
+            for (Lane& L : pl->lanes)
+                if (!current(L.graph) && (rc = capture_step(pl, g, kscale, dt, &L))) return rc;
+        HIP_TRY(hipEventRecord(pl->fork, s));
+        for (size_t l = 1; l < pl->lanes.size(); ++l) HIP_TRY(hipStreamWaitEvent(pl->lanes[l].stream, pl->fork, 0));
+        for (int n = 0; n < n_steps; ++n)
+            for (size_t l = 0; l < pl->lanes.size(); ++l) {
+                Lane& L = pl->lanes[l];
+                hipStream_t ls = l == 0 ? s : L.stream;
+                if (graph) HIP_TRY(hipGraphLaunch(L.graph.exec, ls));
+                else if ((rc = step_launches(pl, ls, g, kscale, dt, &L))) return rc;
+            }
+        for (size_t l = 1; l < pl->lanes.size(); ++l) {
+            HIP_TRY(hipEventRecord(pl->lanes[l].done, pl->lanes[l].stream));
+            HIP_TRY(hipStreamWaitEvent(s, pl->lanes[l].done, 0));
+        }
+        return GD_OK;
+    }
+    if (graph && !current(pl->graph) && (rc = capture_step(pl, g, kscale, dt))) return rc;
     for (int n = 0; n < n_steps; ++n) {
         if (graph) HIP_TRY(hipGraphLaunch(pl->graph.exec, s));
         else if ((rc = step_launches(pl, s, g, kscale, dt))) return rc;

@@ -157,7 +157,7 @@ struct StageArgs {
     double* gamma;             // optional limiter factors [bins] (cell order per group)
     const GroupDev* groups;
     int n_groups;
-    int n_tiles;               // 32-slot tiles over all groups
+    int tile0, n_tiles;        // the launch covers 32-slot tiles [tile0, tile0 + n_tiles) over all groups
     int max_p;                 // largest P over the groups (sets the LDS size)
     int mode;                  // -1 none, 0: out = L, 1..3: RK stage into out
     int limit, split;

@@ -97,9 +97,10 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
     __shared__ int smax[32];
     const GD_CONST GroupDev* groups = cptr(a.groups);
     int gi = 0;
-    while (gi + 1 < a.n_groups && (int)blockIdx.x >= groups[gi + 1].tile_off) ++gi;
+    const int gtile = (int)blockIdx.x + a.tile0;
+    while (gi + 1 < a.n_groups && gtile >= groups[gi + 1].tile_off) ++gi;
     const GD_CONST GroupDev* G = groups + gi;
-    const int tile = (int)blockIdx.x - G->tile_off, tid = threadIdx.x;
+    const int tile = gtile - G->tile_off, tid = threadIdx.x;
     const int N = G->N, k = G->k, K1 = k + 1, P = G->P, LD = P + 1, n_out = G->n_out;
     const int n_slots = G->n_slots, ystride = G->ystride;
     const bool conservative = G->conservative != 0;

@@ -86,6 +86,8 @@ def lib():
             "gd_advect": ([_VP, _VP, _DP, ctypes.c_double, ctypes.c_double, ctypes.c_int], ctypes.c_int),
             "gd_split_step": ([_VP, _VP, _VP, _DP, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
+            "gd_plan_set_lanes": ([_VP, ctypes.c_int], ctypes.c_int),
+            "gd_plan_lanes": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_collision_rhs_noalloc": ([_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
             "gd_rk_step": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
@@ -415,6 +417,18 @@ class Plan:
         _check(lib().gd_plan_autotune(self.h, _ptr(g), _ptr(kscale), cp, ctypes.byref(w), ctypes.byref(t),
                                       ctypes.byref(r), ctypes.byref(x)))
         return {"waves": w.value, "tiles_per_wave": t.value, "rows": r.value, "xcd": x.value}
+
+    def set_lanes(self, lanes=0):
+        """Lanes of gd_rk_step (0 = by size): cell ranges stepped side by side on
+        streams of their own (gd_plan_set_lanes)."""
+        _check(lib().gd_plan_set_lanes(self.h, int(lanes)))
+
+    def lanes(self):
+        """(lanes in use, first 32-slot tile of each)."""
+        n = ctypes.c_int()
+        ft = (ctypes.c_int * 8)()
+        _check(lib().gd_plan_lanes(self.h, ctypes.byref(n), ft))
+        return n.value, list(ft[:n.value])
 
     def use_graph(self, enable=True):
         _check(lib().gd_plan_use_graph(self.h, int(bool(enable))))

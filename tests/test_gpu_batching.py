@@ -297,3 +297,54 @@ def test_set_vfrag_rebrackets_in_place(oracle, prec):
         bad[3] = np.nan
         plan.set_vfrag(bad)
     assert torch.equal(_raw(plan, gd, ksd), _raw(G.Plan(t, C, precision=prec, vfrag=vf), gd, ksd))
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_lanes_match_one_lane(oracle, prec):
+    """gd_rk_step with the cells split into lanes (stepped side by side on streams of
+    their own) against one lane, bit for bit: two groups (one with blended threshold
+    brackets, one single-level), lane boundaries inside brackets and between groups,
+    captured graphs and launches one by one, several calls with a change of dt."""
+    O = oracle
+    t1, cfg1, g1, ks1, vf1 = _level_case(O)
+    N2, k2, C2 = 16, 2, 500
+    t2 = G.Tensor(N2, k2, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=(0.5,), conservative=True)
+    cfg2 = O.Config(N=N2, k=k2, xmin=1e-4, xmax=1e8, kernel="ballistic", frag="powerlaw", conservative=True,
+                    levels=(0.5,))
+    rng = np.random.default_rng(41)
+    g2 = np.stack([O.project(cfg2, lambda x, mu=mu: W.lognormal_density(x, mu, 1.0, 1.0))
+                   for mu in rng.uniform(np.log(30.0), np.log(3000.0), C2)])
+    g1, _ = O.limit(cfg1, g1)
+    g2, _ = O.limit(cfg2, g2)
+    C1 = len(g1)
+    ks = np.concatenate([ks1, np.exp(0.5 * rng.standard_normal(C2))])
+    vf = np.concatenate([vf1, np.full(C2, 0.5)])
+    g0 = torch.tensor(np.concatenate([g1.reshape(-1), g2.reshape(-1)]), device=DEV)
+    ksd = torch.tensor(ks, device=DEV)
+    dt = 2e-6
+    ref_plan = G.Plan([t1, t2], [C1, C2], precision=prec, vfrag=vf)
+    assert ref_plan.lanes()[0] == 1            # small plans take one lane by default
+    ref = g0.clone()
+    for n, d in ((2, dt), (1, 0.5 * dt)):
+        ref_plan.rk_step(ref, d, n, kscale=ksd)
+    torch.cuda.synchronize()
+    for lanes in (2, 3, 5):
+        for graph in (True, False):
+            plan = G.Plan([t1, t2], [C1, C2], precision=prec, vfrag=vf)
+            plan.set_lanes(lanes)
+            plan.use_graph(graph)
+            n_l, first = plan.lanes()
+            assert n_l == lanes and first[0] == 0 and all(a < b for a, b in zip(first, first[1:])), first
+            g = g0.clone()
+            junk = torch.zeros(1 << 20, device=DEV)
+            for n, d in ((2, dt), (1, 0.5 * dt)):
+                v = plan.rk_step(g, d, n, kscale=ksd, count_violations=True)
+                junk += 1.0
+                assert v == 0
+            torch.cuda.synchronize()
+            assert torch.equal(g, ref), (lanes, graph, float((g - ref).abs().max()))
+    tiny = G.Plan(t2, 40, precision=prec)
+    tiny.set_lanes(8)
+    assert tiny.lanes()[0] == 2                # one lane per 32-slot tile at most
+    tiny.set_lanes(0)
+    assert tiny.lanes() == (1, [0])

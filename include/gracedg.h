@@ -391,7 +391,8 @@ int gd_plan_use_graph(gd_plan* plan, int enable);
  * Cells are independent (Eq. evo acts cell by cell), so the results are bit for bit
  * those of one lane.  lanes: 0 = by size (two once the plan has 1024 tiles of 32
  * slots or more, else one), 1..8.  Plans with fewer tiles than lanes take one lane
- * per tile.  Only gd_rk_step uses lanes; while timing it issues one lane.
+ * per tile.  Only gd_rk_step and gd_rk_advance use lanes; while timing they issue one
+ * lane.
  * Synchronous; drops the captured graphs.
  * gd_plan_lanes -- the lanes in use, and (first_tiles, if given, room for 8) the
  * first tile of each.

@@ -533,8 +533,8 @@ struct SubstepGraph {
     double t_end = 0.0, cfl = 0.0, dt_max = 0.0, floor = 0.0;
 };
 
-// An execution lane of the fixed RK step: the cells of a contiguous range of 32-slot
-// tiles, with the contraction items of those tiles only.  Cells never interact, so
+// An execution lane of the RK steps (fixed, or per-cell sub-steps): the cells of a
+// contiguous range of 32-slot tiles, with the contraction items of those tiles only.  Cells never interact, so
 // the lanes of a plan run their steps on streams of their own and meet only at the
 // end of the call: one lane's memory-bound stage kernel and the tail of its
 // contraction overlap the other lane's contraction.
@@ -546,6 +546,7 @@ struct Lane {
     hipStream_t stream = nullptr;           // lanes after the first: private stream (lane 0: the plan's)
     hipEvent_t done = nullptr;
     StepGraph graph;
+    SubstepGraph sgraph;
 };
 
 struct gd_plan {
@@ -589,6 +590,7 @@ struct gd_plan {
     void release_lane(Lane& L)
     {
         if (L.graph.exec) (void)hipGraphExecDestroy(L.graph.exec);
+        if (L.sgraph.exec) (void)hipGraphExecDestroy(L.sgraph.exec);
         if (L.items) (void)hipFree(L.items);
         if (L.done) (void)hipEventDestroy(L.done);
         if (L.stream && L.stream != stream) (void)hipStreamDestroy(L.stream);
@@ -601,6 +603,8 @@ struct gd_plan {
         for (Lane& L : lanes) {
             if (L.graph.exec) (void)hipGraphExecDestroy(L.graph.exec);
             L.graph = StepGraph{};
+            if (L.sgraph.exec) (void)hipGraphExecDestroy(L.sgraph.exec);
+            L.sgraph = SubstepGraph{};
         }
         if (sgraph.exec) (void)hipGraphExecDestroy(sgraph.exec);
         sgraph = SubstepGraph{};
@@ -1293,25 +1297,28 @@ extern "C" int gd_split_step(gd_plan* pl, double* g, const double* kscale, const
 
 // the six launches of one sub-step with per-cell steps
 static int substep_launches(gd_plan* pl, hipStream_t s, double* g, const double* kscale, double dt_max,
-                            const AdaptArgs& ad)
+                            const AdaptArgs& ad, const Lane* lane = nullptr)
 {
     const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
     int rc;
-    if ((rc = contract(pl, s, g))) return rc;
-    if ((rc = stage(pl, s, 1, 1, split, kscale, g, g, pl->y1, dt_max, nullptr, nullptr, &ad))) return rc;
-    if ((rc = contract(pl, s, pl->y1))) return rc;
-    if ((rc = stage(pl, s, 2, 1, split, kscale, g, pl->y1, pl->y2, dt_max, nullptr, nullptr, &ad))) return rc;
-    if ((rc = contract(pl, s, pl->y2))) return rc;
-    return stage(pl, s, 3, 1, split, kscale, g, pl->y2, g, dt_max, nullptr, nullptr, &ad);
+    if ((rc = contract(pl, s, g, lane))) return rc;
+    if ((rc = stage(pl, s, 1, 1, split, kscale, g, g, pl->y1, dt_max, nullptr, nullptr, &ad, lane))) return rc;
+    if ((rc = contract(pl, s, pl->y1, lane))) return rc;
+    if ((rc = stage(pl, s, 2, 1, split, kscale, g, pl->y1, pl->y2, dt_max, nullptr, nullptr, &ad, lane))) return rc;
+    if ((rc = contract(pl, s, pl->y2, lane))) return rc;
+    return stage(pl, s, 3, 1, split, kscale, g, pl->y2, g, dt_max, nullptr, nullptr, &ad, lane);
 }
 
-// capture one sub-step on the plan's private stream (nothing runs while capturing)
-static int capture_substep(gd_plan* pl, double* g, const double* kscale, double dt_max, const AdaptArgs& ad)
+// capture one sub-step (of one lane, or of the whole plan) on the plan's private
+// stream (nothing runs while capturing)
+static int capture_substep(gd_plan* pl, double* g, const double* kscale, double dt_max, const AdaptArgs& ad,
+                           Lane* lane = nullptr)
 {
-    if (pl->sgraph.exec) (void)hipGraphExecDestroy(pl->sgraph.exec);
-    pl->sgraph = SubstepGraph{};
+    SubstepGraph& SG = lane ? lane->sgraph : pl->sgraph;
+    if (SG.exec) (void)hipGraphExecDestroy(SG.exec);
+    SG = SubstepGraph{};
     HIP_TRY(hipStreamBeginCapture(pl->cap, hipStreamCaptureModeThreadLocal));
-    int rc = substep_launches(pl, pl->cap, g, kscale, dt_max, ad);
+    int rc = substep_launches(pl, pl->cap, g, kscale, dt_max, ad, lane);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(pl->cap, &graph);
     if (rc) {
@@ -1323,7 +1330,7 @@ static int capture_substep(gd_plan* pl, double* g, const double* kscale, double 
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(GD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    pl->sgraph = SubstepGraph{exec, g, kscale, ad.t, ad.t_end, ad.cfl, dt_max, ad.floor};
+    SG = SubstepGraph{exec, g, kscale, ad.t, ad.t_end, ad.cfl, dt_max, ad.floor};
     return GD_OK;
 }
 
@@ -1351,13 +1358,34 @@ extern "C" int gd_rk_advance(gd_plan* pl, double* g, const double* kscale, doubl
     if ((rc = stage(pl, s, -1, 1, split, kscale, nullptr, g, nullptr, dt_max, nullptr))) return rc;
     const AdaptArgs ad{cfl, t_end, flux_floor, t, pl->dtc};
     const bool graph = pl->use_graph && !pl->timing && n_substeps > 0;
-    const SubstepGraph& G = pl->sgraph;
-    if (graph && !(G.exec && G.g == g && G.kscale == kscale && G.t == t && G.t_end == t_end && G.cfl == cfl &&
-                   G.dt_max == dt_max && G.floor == flux_floor))
-        if ((rc = capture_substep(pl, g, kscale, dt_max, ad))) return rc;
-    for (int n = 0; n < n_substeps; ++n) {
-        if (graph) HIP_TRY(hipGraphLaunch(pl->sgraph.exec, s));
-        else if ((rc = substep_launches(pl, s, g, kscale, dt_max, ad))) return rc;
+    auto current = [&](const SubstepGraph& G) {
+        return G.exec && G.g == g && G.kscale == kscale && G.t == t && G.t_end == t_end && G.cfl == cfl &&
+               G.dt_max == dt_max && G.floor == flux_floor;
+    };
+    if (pl->lanes.size() > 1 && !pl->timing && n_substeps > 0) {
+        // every lane takes all sub-steps on its own stream, forked from and joined to s
+        if (graph)
+            for (Lane& L : pl->lanes)
+                if (!current(L.sgraph) && (rc = capture_substep(pl, g, kscale, dt_max, ad, &L))) return rc;
+        HIP_TRY(hipEventRecord(pl->fork, s));
+        for (size_t l = 1; l < pl->lanes.size(); ++l) HIP_TRY(hipStreamWaitEvent(pl->lanes[l].stream, pl->fork, 0));
+        for (int n = 0; n < n_substeps; ++n)
+            for (size_t l = 0; l < pl->lanes.size(); ++l) {
+                Lane& L = pl->lanes[l];
+                hipStream_t ls = l == 0 ? s : L.stream;
+                if (graph) HIP_TRY(hipGraphLaunch(L.sgraph.exec, ls));
+                else if ((rc = substep_launches(pl, ls, g, kscale, dt_max, ad, &L))) return rc;
+            }
+        for (size_t l = 1; l < pl->lanes.size(); ++l) {
+            HIP_TRY(hipEventRecord(pl->lanes[l].done, pl->lanes[l].stream));
+            HIP_TRY(hipStreamWaitEvent(s, pl->lanes[l].done, 0));
+        }
+    } else {
+        if (graph && !current(pl->sgraph) && (rc = capture_substep(pl, g, kscale, dt_max, ad))) return rc;
+        for (int n = 0; n < n_substeps; ++n) {
+            if (graph) HIP_TRY(hipGraphLaunch(pl->sgraph.exec, s));
+            else if ((rc = substep_launches(pl, s, g, kscale, dt_max, ad))) return rc;
+        }
     }
     if (unfinished) {
         if ((rc = launch_fill_u64(pl->below, 1, s))) return rc;

@@ -495,3 +495,51 @@ def test_fragmentation_test_at_paper_size():
     mass = (np.diff(O.edges(cfg)) * gg.reshape(N, -1)[:, 0]).sum()
     print(f"e_c {ec:.4f} e_d {ed:.4f} mass {mass:.9f}", flush=True)
     assert ec < 0.01 and ed < 0.01 and abs(mass - 1.0) < 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_rk_advance_lanes_match_one_lane(oracle, prec):
+    """gd_rk_advance with the cells split into lanes (sub-steps side by side on
+    streams of their own) against one lane, bit for bit: states, clocks, violation
+    and unfinished counts; two groups with per-cell thresholds, some cells starting
+    at the end time, graphs on and off, a second call with a new end time."""
+    O = oracle
+    lv = W.VFRAG_LEVELS
+    N, k, C1 = 12, 2, 130
+    tt = G.Tensor(N, k, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=lv, conservative=True)
+    cfg = O.Config(N=N, k=k, xmin=1e-4, xmax=1e8, kernel="ballistic", frag="powerlaw", conservative=True,
+                   levels=lv)
+    rng = np.random.default_rng(29)
+    vf = rng.uniform(0.3, 1.0, C1)
+    g1 = np.stack([O.project(cfg, lambda x, mu=mu: W.lognormal_density(x, mu, 1.0, 1.0))
+                   for mu in rng.uniform(np.log(30.0), np.log(3000.0), C1)])
+    g1, _ = O.limit(cfg, g1)
+    t2, c2 = _pair(O, "ball_k3")
+    C2 = 70
+    g2, _ = _states(O, c2, C2, seed=30)
+    g2, _ = O.limit(c2, g2)
+    ks = np.exp(0.5 * rng.standard_normal(C1 + C2))
+    t_end = 5.0 * CFL * min(O.cfl_dt(cfg, g1, kscale=ks[:C1], vfrag=vf), O.cfl_dt(c2, g2, kscale=ks[C1:]))
+    t0 = np.concatenate([np.zeros(C1 - 10), np.full(10, t_end), np.linspace(0.0, t_end, C2)])
+    g0 = np.concatenate([g1.reshape(-1), g2.reshape(-1)])
+    vfa = np.concatenate([vf, np.full(C2, lv[0])])
+    floor = 0.0 if prec == "fp64" else 1e-4
+    ksd = torch.tensor(ks, device=DEV)
+    runs = {}
+    for lanes, graph in ((1, True), (2, True), (3, False), (4, True)):
+        plan = G.Plan([tt, t2], [C1, C2], precision=prec, vfrag=vfa)
+        plan.set_lanes(lanes)
+        plan.use_graph(graph)
+        assert plan.lanes()[0] == lanes
+        gd = torch.tensor(g0, device=DEV)
+        td = torch.tensor(t0, device=DEV)
+        out = []
+        for te, n in ((t_end, 3), (2.0 * t_end, 4)):
+            v, u = plan.rk_advance(gd, td, te, CFL, 1e30, n, kscale=ksd, flux_floor=floor, count=True)
+            torch.cuda.synchronize()
+            out.append((gd.clone(), td.clone(), v, u))
+        runs[(lanes, graph)] = out
+    ref = runs[(1, True)]
+    for key, out in runs.items():
+        for (ga, ta, va, ua), (gb, tb, vb, ub) in zip(out, ref):
+            assert torch.equal(ga, gb) and torch.equal(ta, tb) and va == vb and ua == ub, key

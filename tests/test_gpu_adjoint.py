@@ -223,3 +223,79 @@ def test_adjoint_of_uneven_batch_matches_single_groups(oracle):
     assert torch.allclose(dks[9:], outs[1][1], rtol=1e-12, atol=1e-300)
     assert torch.allclose(dvf[:9], outs[0][2], rtol=1e-12, atol=1e-300)
     assert float(dvf[9:].abs().max()) == 0.0      # single-level group: no threshold dependence
+
+
+def _moment_weights(edges, k, R=32):
+    """W[p][j(k+1)+i] = int_{I_j} x^(p-1) P_i(xi(x)) dx, p = 0..3 (R-point Gauss per bin), so
+    that the moment M_p = W[p] . g (Sec. 4.1)."""
+    s, w = np.polynomial.legendre.leggauss(R)
+    N = len(edges) - 1
+    W = np.zeros((4, N * (k + 1)))
+    for j in range(N):
+        a, b = edges[j], edges[j + 1]
+        x = 0.5 * (a + b) + 0.5 * (b - a) * s
+        for i in range(k + 1):
+            Pi = np.polynomial.legendre.Legendre.basis(i)(s)
+            for p in range(4):
+                W[p, j * (k + 1) + i] = 0.5 * (b - a) * np.sum(w * x ** (p - 1) * Pi)
+    return W
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_c5_moment_loss_gradient_matches_oracle_finite_differences(prec):
+    """The adjoint workload's loss (Sec. 4.1 moments M_0..M_3 of the final state against
+    seeded targets) over 200 steps of dt = 2e-8 on four of its cells, per-cell kernel
+    scale and threshold blended between levels: the library's reverse pass against
+    central differences of the FP64 oracle (h = 1e-6; tests/golden/c5_fd.json, written
+    by the oracle alone) along 8 seeded directions d = g0 * zeta and per cell for the
+    kernel scale, and per cell for the threshold with step 1e-3 inside its bracket (the
+    threshold moves the loss by less than an ulp at 1e-6; its check allows the
+    quotient's rounding resolution).  Cases where the oracle's limiter changed a
+    different set of bins in the perturbed runs are reported and left out.  Bar
+    (relative to the largest derivative of each kind): 1e-7 for the FP64 forward, 1e-4
+    with the split-FP16 forward (its states carry ~1e-7 of rounding)."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c5_fd.json")))
+    w = W.WORKLOADS["c5_adjoint"]
+    C = len(gold["cells"])
+    t = G.Tensor(w.bins, w.order, w.x_min, w.x_max, kernel=w.kernel, frag=w.frag, levels=tuple(gold["levels"]),
+                 conservative=w.conservative)
+    g0 = np.asarray(gold["g0"])
+    ks, vf = np.asarray(gold["kscale"]), np.asarray(gold["vfrag"])
+    plan = G.Plan(t, C, precision=prec, vfrag=vf)
+    Wm = _moment_weights(t.edges(), w.order)
+    Mstar = np.asarray(gold["Mstar"])
+    g = torch.tensor(g0, device=DEV).view(-1).clone()
+    ksd = torch.tensor(ks, device=DEV)
+    st, gm = plan.rk_forward(g, gold["dt"], gold["steps"], kscale=ksd)
+    M = g.view(C, -1).cpu().numpy() @ Wm.T
+    loss = float((((M - Mstar) / Mstar) ** 2).sum())
+    print(f"c5 {prec}: loss {loss:.10e} (oracle {gold['loss']:.10e})", flush=True)
+    assert abs(loss - gold["loss"]) <= (1e-10 if prec == "fp64" else 1e-5) * abs(gold["loss"])
+    lam = torch.tensor(((2.0 * (M - Mstar) / Mstar ** 2) @ Wm).reshape(-1), device=DEV)
+    dks, dvf = plan.adjoint(st, gm, gold["dt"], gold["steps"], lam, kscale=ksd)
+    grad = lam.view(C, -1).cpu().numpy()
+    tol = 1e-7 if prec == "fp64" else 1e-4
+    zeta = np.random.default_rng(gold["dir_seed"]).standard_normal((gold["n_dirs"],) + g0.shape)
+    fd = np.asarray(gold["fd_dir"])
+    ad = np.array([np.sum(grad * g0 * zeta[i]) for i in range(len(fd))])
+    keep = np.asarray(gold["same_active_set_dir"])
+    rel = np.abs(ad - fd) / np.abs(fd).max()
+    print(f"  directions: max rel error {rel[keep].max():.2e}, left out (active set changed): {int((~keep).sum())}",
+          flush=True)
+    assert keep.sum() >= 4 and rel[keep].max() <= tol, rel
+    a, b = dks.cpu().numpy(), np.asarray(gold["fd_kscale"])
+    keep = np.asarray(gold["same_active_set_kscale"])
+    rel = np.abs(a - b) / np.abs(b).max()
+    print(f"  kscale: max rel error {rel[keep].max():.2e}, left out: {int((~keep).sum())}", flush=True)
+    assert keep.sum() >= 2 and rel[keep].max() <= tol, ("kscale", rel)
+    # the threshold moves each cell's loss term by ~1e-12 per unit over this horizon:
+    # the oracle's quotient (step hv) resolves it only to the rounding of the loss
+    # terms, taken here as 256 ulp of the larger of L_c(v +- hv) over 2 hv
+    a, b = dvf.cpu().numpy(), np.asarray(gold["fd_vfrag"])
+    keep = np.asarray(gold["same_active_set_vfrag"])
+    res = 256 * np.finfo(float).eps * np.abs(np.asarray(gold["loss_vfrag_pm"])).max(axis=1) / (2 * gold["hv"])
+    err = np.abs(a - b)
+    print(f"  vfrag: adjoint {a}, oracle quotient {b}, resolution {res}, left out: {int((~keep).sum())}", flush=True)
+    assert keep.sum() >= 2 and np.all(err[keep] <= tol * np.abs(b).max() + res[keep]), ("vfrag", err, res)

@@ -14,8 +14,10 @@ typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
 
 // Limiter of one bin in registers: g^i <- gamma g^i (i >= 1) with
 // gamma = min(1, avg / (avg - min)); a non-positive average flattens the bin and a
-// negative one is reported.
-__device__ __forceinline__ int limit_bin(int k, double* c, double& gamma)
+// negative one is reported.  K is the order, fixed at compile time: the minimum's
+// root finding then runs without loops or branches on the order.
+template <int K>
+__device__ __forceinline__ int limit_bin(double* c, double& gamma)
 {
     const double avg = c[0];
     int viol = 0;
@@ -26,17 +28,31 @@ __device__ __forceinline__ int limit_bin(int k, double* c, double& gamma)
     } else {
         // |P_i| <= 1 on [-1,1]: avg - sum |c_i| >= 0 proves the minimum nonnegative
         double lb = avg;
-        for (int i = 1; i <= k; ++i) lb -= fabs(c[i]);
+#pragma unroll
+        for (int i = 1; i <= K; ++i) lb -= fabs(c[i]);
         if (lb >= 0.0) {
             gamma = 1.0;
         } else {
-            const double m = bin_min(k, c);
+            const double m = bin_min<K>(c);
             viol = !(m > -INFINITY);   // a non-finite higher coefficient
             gamma = (m < 0.0) ? fmin(1.0, avg / (avg - m)) : 1.0;
         }
     }
-    for (int i = 1; i <= k; ++i) c[i] *= gamma;
+#pragma unroll
+    for (int i = 1; i <= K; ++i) c[i] *= gamma;
     return viol;
+}
+
+// the order of a group is the same for the whole workgroup: no divergence
+__device__ __forceinline__ int limit_bin(int k, double* c, double& gamma)
+{
+    switch (k) {
+    case 0: return limit_bin<0>(c, gamma);
+    case 1: return limit_bin<1>(c, gamma);
+    case 2: return limit_bin<2>(c, gamma);
+    case 3: return limit_bin<3>(c, gamma);
+    default: return limit_bin<4>(c, gamma);
+    }
 }
 
 __global__ void k_fill_u64(unsigned long long* p, int n)

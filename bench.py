@@ -267,8 +267,13 @@ def mfma_counters(variant):
     key = f"{variant['waves']},{variant['tiles_per_wave']},{variant['rows']},{variant['xcd']}"
     v = rec["variants"].get(key)
     if v is None:
-        return None
-    return dict(v, file="profiles/k_contract_mfma_counters_c3_batched.md")
+        # the XCD ordering changes the order of the work items, not the MFMA work
+        key = next((k for k in rec["variants"] if k.rsplit(",", 1)[0] == key.rsplit(",", 1)[0]), None)
+        if key is None:
+            return None
+        v = rec["variants"][key]
+    return dict(v, measured_variant=key, fp64_kernel=rec.get("fp64_kernel"),
+                file="profiles/k_contract_mfma_counters_c3_batched.md")
 
 
 def measured_traffic(variant):

@@ -744,6 +744,16 @@ static int upload_items(const std::vector<int4>& h, int4** dev, size_t* cap)
     return GD_OK;
 }
 
+// wait for the plan's work in flight (its graphs, item lists and lane streams are
+// about to be replaced)
+static int quiesce(gd_plan* pl)
+{
+    HIP_TRY(hipStreamSynchronize(pl->stream));
+    for (const Lane& L : pl->lanes)
+        if (L.stream) HIP_TRY(hipStreamSynchronize(L.stream));
+    return GD_OK;
+}
+
 // lanes of the fixed step when none are requested: two once the batch fills the
 // chip several times over (one workgroup of 8 tiles per item, two items per CU)
 static constexpr int kLaneMinTiles = 1024;
@@ -755,6 +765,7 @@ static int build_lanes(gd_plan* pl)
 {
     const int want = pl->lanes_req > 0 ? pl->lanes_req : (pl->tiles32 >= kLaneMinTiles ? 2 : 1);
     const int n = std::max(1, std::min(want, pl->tiles32));
+    if (int rc = quiesce(pl)) return rc;
     pl->drop_graph();
     const size_t keep = n == 1 ? 0 : size_t(n);
     for (size_t l = keep; l < pl->lanes.size(); ++l) pl->release_lane(pl->lanes[l]);
@@ -804,9 +815,11 @@ static int build_lanes(gd_plan* pl)
 
 static int build_items(gd_plan* pl)
 {
+    int rc = quiesce(pl);
+    if (rc) return rc;
     std::vector<int4> h;
     double fl = 0.0;
-    int rc = make_items(pl, 0, pl->waves * pl->tpw, pl->rows, pl->xcd, h, &fl);
+    rc = make_items(pl, 0, pl->waves * pl->tpw, pl->rows, pl->xcd, h, &fl);
     if (!rc) rc = upload_items(h, &pl->items, &pl->items_cap);
     if (rc) return rc;
     pl->n_items = int(h.size());

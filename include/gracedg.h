@@ -383,17 +383,17 @@ int gd_plan_autotune(gd_plan* plan, const double* g, const double* kscale, const
 int gd_plan_use_graph(gd_plan* plan, int enable);
 /*
  * gd_plan_set_lanes -- split the cells of the plan into `lanes` lanes (contiguous
- * ranges of 32-slot tiles of equal contraction cost) for gd_rk_step: every lane
- * takes all the call's steps on a stream of its own (lane 0 on the plan's stream,
- * the others on private streams forked from it and joined back to it before the
- * call returns), so that the kernels of one lane fill the tail of another lane's
- * contraction and its memory-bound stage kernels overlap the other's contractions.
- * Cells are independent (Eq. evo acts cell by cell), so the results are bit for bit
- * those of one lane.  lanes: 0 = by size (two once the plan has 1024 tiles of 32
- * slots or more, else one), 1..8.  Plans with fewer tiles than lanes take one lane
- * per tile.  Only gd_rk_step and gd_rk_advance use lanes; while timing they issue one
- * lane.
- * Synchronous; drops the captured graphs.
+ * ranges of 32-slot tiles of equal contraction cost) for gd_rk_step, gd_rk_advance
+ * and gd_collision_rhs: every lane takes all the call's steps or sub-steps (or its
+ * evaluation) on a stream of its own (lane 0 on the plan's stream, the others on
+ * private streams forked from it and joined back to it before the call returns), so
+ * that the kernels of one lane fill the tail of another lane's contraction and its
+ * memory-bound stage kernels overlap the other's contractions.  Cells are
+ * independent (Eq. evo acts cell by cell), so the results are bit for bit those of
+ * one lane.  lanes: 0 = by size (two once the plan has 1024 tiles of 32 slots or
+ * more, else one), 1..8.  Plans with fewer tiles than lanes take one lane per tile.
+ * The adjoint calls run one lane; while timing (gd_plan_timing) every call does.
+ * Synchronous (waits for the plan's work in flight); drops the captured graphs.
  * gd_plan_lanes -- the lanes in use, and (first_tiles, if given, room for 8) the
  * first tile of each.
  */

@@ -533,8 +533,9 @@ struct SubstepGraph {
     double t_end = 0.0, cfl = 0.0, dt_max = 0.0, floor = 0.0;
 };
 
-// An execution lane of the RK steps (fixed, or per-cell sub-steps): the cells of a
-// contiguous range of 32-slot tiles, with the contraction items of those tiles only.  Cells never interact, so
+// An execution lane of the RK steps (fixed, or per-cell sub-steps) and of a single
+// evaluation of L: the cells of a contiguous range of 32-slot tiles, with the
+// contraction items of those tiles only.  Cells never interact, so
 // the lanes of a plan run their steps on streams of their own and meet only at the
 // end of the call: one lane's memory-bound stage kernel and the tail of its
 // contraction overlap the other lane's contraction.
@@ -755,8 +756,8 @@ static int quiesce(gd_plan* pl)
 }
 
 // lanes of the RK steps when none are requested: two from 1024 tiles of 32 slots
-// (32,768 cells; measured faster at 65,536-262,144 cells and on a 100,000-cell
-// uneven batch), one below
+// (32,768 cells; measured faster at 32,768-262,144 cells and on a 100,000-cell
+// uneven batch, slower for the split path at 16,384), one below
 static constexpr int kLaneMinTiles = 1024;
 static constexpr int kMaxLanes = 8;
 
@@ -1144,10 +1145,25 @@ extern "C" int gd_collision_rhs(gd_plan* pl, const double* g, const double* ksca
     const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
     hipStream_t s = pl->stream;
     int rc;
-    // split of the input state (no limiting: the state is read only)
-    if (mixed && (rc = stage(pl, s, -1, 0, 1, kscale, nullptr, g, nullptr, 0.0, nullptr))) return rc;
-    if ((rc = contract(pl, s, g))) return rc;
-    return stage(pl, s, 0, 0, 0, kscale, nullptr, g, rhs, 0.0, raw);
+    // split of the input state (no limiting: the state is read only), contraction,
+    // assembly of L; lane by lane on the lanes' streams when the plan has lanes
+    auto launches = [&](hipStream_t ls, const Lane* L) -> int {
+        int r;
+        if (mixed && (r = stage(pl, ls, -1, 0, 1, kscale, nullptr, g, nullptr, 0.0, nullptr, nullptr, nullptr, L)))
+            return r;
+        if ((r = contract(pl, ls, g, L))) return r;
+        return stage(pl, ls, 0, 0, 0, kscale, nullptr, g, rhs, 0.0, raw, nullptr, nullptr, L);
+    };
+    if (pl->lanes.size() <= 1 || pl->timing) return launches(s, nullptr);
+    HIP_TRY(hipEventRecord(pl->fork, s));
+    for (size_t l = 1; l < pl->lanes.size(); ++l) HIP_TRY(hipStreamWaitEvent(pl->lanes[l].stream, pl->fork, 0));
+    for (size_t l = 0; l < pl->lanes.size(); ++l)
+        if ((rc = launches(l == 0 ? s : pl->lanes[l].stream, &pl->lanes[l]))) return rc;
+    for (size_t l = 1; l < pl->lanes.size(); ++l) {
+        HIP_TRY(hipEventRecord(pl->lanes[l].done, pl->lanes[l].stream));
+        HIP_TRY(hipStreamWaitEvent(s, pl->lanes[l].done, 0));
+    }
+    return GD_OK;
 }
 
 // y1 = gn + dt L(gn); y2 = 3/4 gn + 1/4 (y1 + dt L(y1)); gn = 1/3 gn + 2/3 (y2 + dt L(y2)),

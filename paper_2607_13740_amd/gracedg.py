@@ -419,8 +419,8 @@ class Plan:
         return {"waves": w.value, "tiles_per_wave": t.value, "rows": r.value, "xcd": x.value}
 
     def set_lanes(self, lanes=0):
-        """Lanes of gd_rk_step and gd_rk_advance (0 = by size): cell ranges stepped
-        side by side on streams of their own (gd_plan_set_lanes)."""
+        """Lanes of gd_rk_step, gd_rk_advance and gd_collision_rhs (0 = by size): cell
+        ranges stepped side by side on streams of their own (gd_plan_set_lanes)."""
         _check(lib().gd_plan_set_lanes(self.h, int(lanes)))
 
     def lanes(self):

@@ -301,8 +301,8 @@ def test_set_vfrag_rebrackets_in_place(oracle, prec):
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_lanes_match_one_lane(oracle, prec):
-    """gd_rk_step with the cells split into lanes (stepped side by side on streams of
-    their own) against one lane, bit for bit: two groups (one with blended threshold
+    """gd_rk_step and gd_collision_rhs with the cells split into lanes (run side by
+    side on streams of their own) against one lane, bit for bit: two groups (one with blended threshold
     brackets, one single-level), lane boundaries inside brackets and between groups,
     captured graphs and launches one by one, several calls with a change of dt."""
     O = oracle
@@ -324,6 +324,8 @@ def test_lanes_match_one_lane(oracle, prec):
     dt = 2e-6
     ref_plan = G.Plan([t1, t2], [C1, C2], precision=prec, vfrag=vf)
     assert ref_plan.lanes()[0] == 1            # small plans take one lane by default
+    raw_ref = torch.zeros(ref_plan.n_raw, dtype=torch.float64, device=DEV)
+    rhs_ref = ref_plan.collision_rhs(g0, kscale=ksd, raw=raw_ref)
     ref = g0.clone()
     for n, d in ((2, dt), (1, 0.5 * dt)):
         ref_plan.rk_step(ref, d, n, kscale=ksd)
@@ -335,6 +337,10 @@ def test_lanes_match_one_lane(oracle, prec):
             plan.use_graph(graph)
             n_l, first = plan.lanes()
             assert n_l == lanes and first[0] == 0 and all(a < b for a, b in zip(first, first[1:])), first
+            raw = torch.zeros(plan.n_raw, dtype=torch.float64, device=DEV)
+            rhs = plan.collision_rhs(g0, kscale=ksd, raw=raw)
+            torch.cuda.synchronize()
+            assert torch.equal(rhs, rhs_ref) and torch.equal(raw, raw_ref), (lanes, "collision_rhs")
             g = g0.clone()
             junk = torch.zeros(1 << 20, device=DEV)
             for n, d in ((2, dt), (1, 0.5 * dt)):

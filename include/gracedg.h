@@ -357,7 +357,8 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, const
  *   (every stored fragment, all products, for every tile of an item); any pointer
  *   may be NULL.
  * gd_plan_autotune -- time every variant on state g (device, state layout, read
- *   only; kscale as in gd_rk_step) and keep the fastest.  cache_path (or NULL)
+ *   only; kscale as in gd_rk_step) and keep the fastest (XCD-ordered items win ties
+ *   within 2%: they move less HBM traffic).  cache_path (or NULL)
  *   names a text file of "key waves tiles_per_wave rows xcd" lines: a plan of the same shape (precision,
  *   bins, order, levels, cells and brackets of every group) takes its stored
  *   choice without timing; a newly timed choice is appended.  Synchronous.

@@ -1785,6 +1785,10 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
         }
         float ms = 0.0f;
         (void)hipEventElapsedTime(&ms, e0, e1);
+        // XCD ordering reads the fragments of fewer lists per L2 (about 40% less HBM
+        // traffic at equal speed, which the other lane's stage kernels can use):
+        // it wins ties within 2%
+        if (c.x) ms *= 0.98f;
         if (ms < best) {
             best = ms;
             bw = c.w;

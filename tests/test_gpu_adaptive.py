@@ -434,11 +434,11 @@ def test_rk_advance_graph_replays_match_eager(oracle, prec):
 
 def test_constant_kernel_eoc_at_larger_n(oracle):
     """The convergence study of Sec. 4.2 continued to the sizes the kernels' P <= 208
-    allows: N = 50 -> 100 for orders 0 and 1 (P up to 200) and N = 100 -> 200 for order 0
-    (P = 200), on the paper's domain and horizon ([1e-3, 1e15], tau = 3e12, per-cell CFL
-    steps, FP64).  The error e_c falls at about the printed EOC = k + 1 (Eq. eoc), within
-    0.3 (k = 0 follows its rate closely already at N = 20), and order 1 stays below
-    order 0."""
+    allows: N = 50 -> 100 -> 200 for order 0, 50 -> 100 and 40 -> 80 for order 1,
+    40 -> 69 for order 2 (P = 207) and 40 -> 52 for order 3 (P = 208), on the paper's
+    domain and horizon ([1e-3, 1e15], tau = 3e12, per-cell CFL steps, FP64).  The error
+    e_c falls at about the printed EOC = k + 1 (Eq. eoc, with log(N2/N1) for the ratio
+    of the grids), within 0.3, and order 1 stays below order 0."""
     import json
     import os
     O = oracle
@@ -446,7 +446,8 @@ def test_constant_kernel_eoc_at_larger_n(oracle):
     v, plus = gv["constant_kernel_full_size"], gv["constant_kernel_eoc"]["eoc_equals_k_plus"]
     tau = v["tau"]
     ec = {}
-    for k, N in ((0, 50), (0, 100), (0, 200), (1, 50), (1, 100)):
+    for k, N in ((0, 50), (0, 100), (0, 200), (1, 50), (1, 100), (1, 40), (1, 80), (2, 40), (2, 69), (3, 40),
+                 (3, 52)):
         print(f"case eoc k={k} N={N}", flush=True)
         t = G.Tensor(N, k, v["x_min"], v["x_max"], kernel="const", frag="none", conservative=False)
         cfg = O.Config(N=N, k=k, xmin=v["x_min"], xmax=v["x_max"], kernel="const")
@@ -457,9 +458,8 @@ def test_constant_kernel_eoc_at_larger_n(oracle):
         viol, unfinished = plan.rk_advance(gd, td, tau, 0.5, 1e30, 5000, count=True)
         assert viol == 0 and unfinished == 0
         ec[(k, N)] = O.error_c(cfg, gd.cpu().numpy(), lambda x: O.g_const(x, tau))
-    eoc = {(0, 50): np.log(ec[(0, 50)] / ec[(0, 100)]) / np.log(2.0),
-           (0, 100): np.log(ec[(0, 100)] / ec[(0, 200)]) / np.log(2.0),
-           (1, 50): np.log(ec[(1, 50)] / ec[(1, 100)]) / np.log(2.0)}
+    pairs = {(0, 50): 100, (0, 100): 200, (1, 50): 100, (1, 40): 80, (2, 40): 69, (3, 40): 52}
+    eoc = {(k, N): np.log(ec[(k, N)] / ec[(k, M)]) / np.log(M / N) for (k, N), M in pairs.items()}
     print("e_c", ec, "EOC", eoc, flush=True)
     for (k, N), r in eoc.items():
         assert abs(r - (k + plus)) < 0.3, (k, N, r)

@@ -184,6 +184,7 @@ int gd_plan_bins(const gd_plan* plan, long long* n_bins);
  * all levels) and the group's slot count (cells plus bracket padding) */
 int gd_plan_schedule_stats(const gd_plan* plan, int group, long long* frags_mixed, long long* frags_fp64,
                            int* n_slots);
+/* Waits for the plan's work in flight (its stream and its lanes' streams), then frees it. */
 void gd_plan_destroy(gd_plan* plan);
 
 /*

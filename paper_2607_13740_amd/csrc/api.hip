@@ -612,6 +612,10 @@ struct gd_plan {
     }
     ~gd_plan()
     {
+        // the plan's graphs and buffers may still be in use by work in flight
+        (void)hipStreamSynchronize(stream);
+        for (const Lane& L : lanes)
+            if (L.stream) (void)hipStreamSynchronize(L.stream);
         drop_graph();
         if (cap) (void)hipStreamDestroy(cap);
         for (Lane& L : lanes) release_lane(L);

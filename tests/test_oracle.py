@@ -673,6 +673,27 @@ def test_constant_kernel_convergence(oracle):
     assert ec[(16, 2)] < 0.05
 
 
+def test_ssp_rk3_is_third_order_in_time(oracle):
+    """Eq. RK3 alone: on a fixed grid where the limiter never acts (constant kernel,
+    g0 = x e^{-x} on [1e-3, 1e3], N = 12, orders 0 and 1), the state at tau = 0.5 after
+    10, 20 and 40 steps differs from a 640-step run by errors that fall 8-fold per
+    halving (temporal order 3).  A wrong stage weight leaves order 2 or 1."""
+    O = oracle
+    for k in (0, 1):
+        cfg = _cfg(O, N=12, k=k, xmin=1e-3, xmax=1e3, kernel="const")
+        g0 = O.project(cfg, lambda x: x * np.exp(-x))
+        ref, viol = O.rk(cfg, g0, 0.5 / 640, 640)
+        assert viol == 0
+        h = np.repeat(np.diff(O.edges(cfg)), k + 1)
+        errs = []
+        for n in (10, 20, 40):
+            g, viol = O.rk(cfg, g0, 0.5 / n, n)
+            assert viol == 0
+            errs.append(np.max(np.abs((g - ref) * h)) / np.max(np.abs(ref * h)))
+        orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+        assert np.all(np.abs(orders - 3.0) < 0.2), (k, errs, orders)
+
+
 def test_order4_converges_and_beats_order3(oracle):
     """Sec. 4.2 setup as above with k = 3 and k = 4 (the paper's accuracy runs go up to
     k = 4): the k = 4 errors are below the k = 3 errors at equal N and fall at a high

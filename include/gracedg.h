@@ -399,6 +399,21 @@ int gd_plan_use_graph(gd_plan* plan, int enable);
  * gd_plan_lanes -- the lanes in use, and (first_tiles, if given, room for 8) the
  * first tile of each.
  */
+/*
+ * gd_plan_checks -- the device checks of the checked build (libgracedg_checks.so,
+ * compiled with -DGD_CHECKS): before using them, the kernels test the work items,
+ * iteration descriptors, fragment and iteration ranges and slot -> cell indices
+ * against the sizes of the plan's groups, skip the work on a failure (the results
+ * are then incomplete) and set a bit of the plan's check word; the stage kernel also
+ * flags non-finite new states.  *flags receives the word (GD_CHECK_* bits) of the
+ * calls since the last read, which clears it; synchronous.  The regular build
+ * returns GD_EUNSUPPORTED with *flags = 0.
+ */
+#define GD_CHECK_ITEM 1u        /* a work item outside its group's levels, row blocks or tiles */
+#define GD_CHECK_DESC 2u        /* an iteration list or descriptor outside the schedule */
+#define GD_CHECK_SLOT 4u        /* a slot mapped to a cell outside its group */
+#define GD_CHECK_NONFINITE 8u   /* a stage produced a non-finite coefficient */
+int gd_plan_checks(gd_plan* plan, unsigned* flags);
 int gd_plan_set_lanes(gd_plan* plan, int lanes);
 int gd_plan_lanes(const gd_plan* plan, int* lanes, int* first_tiles);
 

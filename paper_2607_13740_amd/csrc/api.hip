@@ -573,6 +573,7 @@ struct gd_plan {
     double* y1 = nullptr;
     double* y2 = nullptr;
     unsigned long long* viol = nullptr;
+    unsigned* checks = nullptr;             // device-check word (set only by a GD_CHECKS build)
     double* dtc = nullptr;                  // per-cell steps of an adaptive sub-step (first adaptive call)
     unsigned long long* below = nullptr;    // count of cells short of the end time
     double* courant = nullptr;              // per-bin Courant numbers of the transport step (groups concatenated)
@@ -973,10 +974,17 @@ extern "C" int gd_plan_create(const gd_tensor* const* tensors, const int* cells_
         d.tile_off = G.tile_off;
         d.conservative = t->spec.conservative;
         d.R = t->R;
+        d.n_frag = S.frags;
+        d.n_iters = S.iters_total;
+        d.n_cells = G.C;
         d.gam0 = pl->n_bins;
         pl->n_bins += (long long)G.C * t->N;
         gdev.push_back(d);
     }
+    // the word the device checks of a GD_CHECKS build set (cleared by gd_plan_checks)
+    if ((rc = dalloc(pl.get(), &pl->checks, 1))) return rc;
+    HIP_TRY(hipMemset(pl->checks, 0, sizeof(unsigned)));
+    for (GroupDev& d : gdev) d.checks = pl->checks;
     pl->gdev = gdev;
     if ((rc = dcopy(pl.get(), &pl->groups_dev, gdev))) return rc;
     if ((rc = dalloc(pl.get(), &pl->y1, pl->n_values))) return rc;
@@ -1056,6 +1064,17 @@ extern "C" int gd_plan_lanes(const gd_plan* pl, int* lanes, int* first_tiles)
     *lanes = pl->lanes.empty() ? 1 : int(pl->lanes.size());
     if (first_tiles)
         for (int l = 0; l < *lanes; ++l) first_tiles[l] = pl->lanes.empty() ? 0 : pl->lanes[size_t(l)].t0;
+    return GD_OK;
+}
+
+extern "C" int gd_plan_checks(gd_plan* pl, unsigned* flags)
+{
+    if (!pl || !flags) return fail(GD_EINVAL, "null argument");
+    *flags = 0;
+    if (!kChecks) return fail(GD_EUNSUPPORTED, "this library was built without device checks (GD_CHECKS)");
+    if (int rc = quiesce(pl)) return rc;
+    HIP_TRY(hipMemcpy(flags, pl->checks, sizeof(unsigned), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(pl->checks, 0, sizeof(unsigned)));
     return GD_OK;
 }
 

@@ -60,11 +60,32 @@ struct MixedItem {
     uint4* buf0;
     uint4* buf1;
 
+    // device checks (GD_CHECKS) of an iteration descriptor before its fragments are
+    // fetched; uniform over the workgroup, as the descriptors are
+    template <int KS>
+    __device__ __forceinline__ bool desc_ok(const IterDesc& d) const
+    {
+        bool ok = d.nseg >= 0 && d.nseg <= kSegMax && d.nfrag >= 0 && d.nfrag <= frag_budget(KS) && d.frag >= 0 &&
+                  (long long)d.frag + d.nfrag <= gp->n_frag;
+        for (int s = 0; s < kSegMax; ++s)
+            if (s < d.nseg) ok = ok && d.p[s] >= 0 && d.p[s] < gp->P && d.lo[s] >= 0 && d.lo[s] < KS;
+        if (!ok && threadIdx.x == 0) check_fail(gp->checks, kCheckDesc);
+        return ok;
+    }
+
     template <int KS>
     __device__ __forceinline__ void item()
     {
         constexpr int SEG = kSegMax;
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        if constexpr (kChecks) {
+            if (!(r >= 0 && r < gp->R && ob0 >= 0 && ob0 < ob1 && ob1 <= gp->NOB && tile0 >= 0 && ntile >= 0 &&
+                  ntile <= W * T && KS == gp->KS)) {
+                if (tid == 0) check_fail(gp->checks, kCheckItem);
+                return;
+            }
+        }
+        bool bad = false;   // a failed device check (GD_CHECKS): the item stops, nothing is stored
         const GD_GLOBAL uint4* frag = gptr(gp->frag);
         const GD_CONST IterDesc* iters = cptr(gp->iters);
         const GD_CONST float* scale = cptr(gp->scale);
@@ -108,6 +129,12 @@ struct MixedItem {
         // one iteration: compute d from rd while the fragments of dn stream into wr
         auto body = [&](const IterDesc& d, const IterDesc& dn, const float (&mp)[T][SEG], const float (&sc)[SEG],
                         float (&mpn)[T][SEG], float (&scn)[SEG], const uint4* rd, uint4* wr) {
+            if constexpr (kChecks) {
+                if (!desc_ok<KS>(dn)) {
+                    bad = true;
+                    return;
+                }
+            }
             dma_frags<W>(frag + (size_t)dn.frag * 128, wr, dn.nfrag, wave, lane);
             prefetch_w(dn, mpn, scn);
             int f = 0;
@@ -129,6 +156,14 @@ struct MixedItem {
             const int list = r * gp->NOB + ob;
             const GD_CONST IterDesc* its = iters + cptr(gp->list_off)[list];
             const int n_it = cptr(gp->list_cnt)[list];
+            if constexpr (kChecks) {
+                // the list and the two descriptors read past its end lie inside the schedule
+                const long long off = cptr(gp->list_off)[list];
+                if (!(n_it >= 1 && off >= 0 && off + n_it + 2 <= gp->n_iters && desc_ok<KS>(its[0]))) {
+                    if (tid == 0 && n_it >= 1) check_fail(gp->checks, kCheckDesc);
+                    return;
+                }
+            }
 #pragma unroll
             for (int t = 0; t < T; ++t)
 #pragma unroll
@@ -143,12 +178,14 @@ struct MixedItem {
             for (int i = 0; i < n_it; i += 2) {
                 const IterDesc dC = its[i + 2];
                 body(dA, dB, mp0, sc0, mp1, sc1, buf0, buf1);
-                if (i + 1 >= n_it) break;
+                if (i + 1 >= n_it || bad) break;
                 const IterDesc dD = its[i + 3];
                 body(dB, dC, mp1, sc1, mp0, sc0, buf1, buf0);
+                if (bad) break;
                 dA = dC;
                 dB = dD;
             }
+            if (bad) return;
 #pragma unroll
             for (int t = 0; t < T; ++t) {
                 if (!sv[t]) continue;

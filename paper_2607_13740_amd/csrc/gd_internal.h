@@ -93,6 +93,19 @@ struct Schedule {
     long long iters_total = 0;
 };
 
+// Device-side checks, compiled in with -DGD_CHECKS (the second build of the library,
+// libgracedg_checks.so): before using them, the kernels test the work items,
+// iteration descriptors, fragment and iteration ranges and slot -> cell indices
+// against the sizes in the group descriptor, skip the work on a failure and record
+// it as a bit of the plan's check word; the stage kernel also flags non-finite new
+// states.  Without the flag the tests compile away.
+enum : unsigned { kCheckItem = 1u, kCheckDesc = 2u, kCheckSlot = 4u, kCheckNonFinite = 8u };
+#ifdef GD_CHECKS
+constexpr bool kChecks = true;
+#else
+constexpr bool kChecks = false;
+#endif
+
 // One group of a plan as the kernels see it: the tensor of the group in the plan's
 // precision and the group's slot buffers.  Slots are the cells of the group sorted
 // by threshold bracket, each bracket padded to a multiple of 32 slots.
@@ -132,7 +145,18 @@ struct GroupDev {
     double* G1p;               // [parts][NQB][n_slots][P] first-sum partials
     double* Dth;               // [NPS][NQB][n_slots] blend-weight partials
     const double* dthdv;       // [n_slots] d theta / d v_frag of the slot's cell
+    // sizes the device checks test against (GD_CHECKS), and the word they set
+    unsigned* checks;
+    long long n_frag;          // 2 KB fragments of the schedule (all levels)
+    long long n_iters;         // iteration descriptors of the schedule (with the sentinels)
+    int n_cells;               // cells of the group
 };
+
+// record a failed device check (any thread; the word is the plan's)
+__device__ __forceinline__ void check_fail(unsigned* word, unsigned bit)
+{
+    if (word) atomicOr(word, bit);
+}
 
 // One contraction workgroup: {group, level, ob0 | ob1 << 10 | ntile << 20, first
 // tile}.  The workgroup's waves take consecutive tiles (32 slots split path, 16 slots

@@ -135,6 +135,9 @@ extern "C" int gd_collision_rhs_noalloc(const gd_tensor* t, int precision, int n
     d.tiles16 = tiles16;
     d.conservative = t->spec.conservative;
     d.R = t->R;
+    d.n_frag = S.frags;
+    d.n_iters = S.iters_total;
+    d.n_cells = n_cells;       // checks: nullptr, the path keeps no check word
 
     // row blocks of level 0, costliest first
     ObOrder order{};

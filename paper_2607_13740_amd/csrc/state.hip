@@ -136,7 +136,13 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
     __shared__ double sfac[32];
     if (tid < 32) {
         const int s = tile * 32 + tid;
-        const int c = (s < n_slots) ? (perm ? perm[s] : s) : -1;
+        int c = (s < n_slots) ? (perm ? perm[s] : s) : -1;
+        if constexpr (kChecks) {
+            if (c >= G->n_cells || (tile < 0 || tile >= G->tiles32)) {
+                check_fail(G->checks, kCheckSlot);
+                c = -1;
+            }
+        }
         scell[tid] = c;
         double fac = (c >= 0 && kscale) ? kscale[c] : 1.0;
         if (c >= 0 && a.mode >= 0 && Yf) fac = ldexp(fac, 2 * eslot[s]);
@@ -280,6 +286,11 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(StageArgs a)
                     default: v[i] = hold ? xn[i] : (1.0 / 3.0) * xn[i] + (2.0 / 3.0) * (xs[i] + dt * L); break;
                     }
                 }
+            }
+            if constexpr (kChecks) {
+                bool fin = true;
+                for (int i = 0; i < K1; ++i) fin = fin && isfinite(v[i]);
+                if (!fin) check_fail(G->checks, kCheckNonFinite);
             }
             if (a.limit && !(ADAPT && a.mode >= 1 && !(sdt[sl] > 0.0))) {
                 double gam;

@@ -13,7 +13,9 @@ import re
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgracedg.so")
+# GRACEDG_LIBRARY=checks selects the build with the device checks (gd_plan_checks)
+LIB_PATH = os.path.join(_HERE, "libgracedg_checks.so" if os.environ.get("GRACEDG_LIBRARY") == "checks"
+                        else "libgracedg.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "gracedg.h")
 
 GD_OK, GD_EINVAL, GD_EHIP, GD_ENOMEM, GD_EUNSUPPORTED, GD_EPOSITIVITY = 0, -1, -2, -3, -4, -5
@@ -87,6 +89,7 @@ def lib():
             "gd_split_step": ([_VP, _VP, _VP, _DP, ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_plan_set_lanes": ([_VP, ctypes.c_int], ctypes.c_int),
+            "gd_plan_checks": ([_VP, ctypes.POINTER(ctypes.c_uint)], ctypes.c_int),
             "gd_plan_lanes": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_collision_rhs_noalloc": ([_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
             "gd_rk_step": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
@@ -417,6 +420,13 @@ class Plan:
         _check(lib().gd_plan_autotune(self.h, _ptr(g), _ptr(kscale), cp, ctypes.byref(w), ctypes.byref(t),
                                       ctypes.byref(r), ctypes.byref(x)))
         return {"waves": w.value, "tiles_per_wave": t.value, "rows": r.value, "xcd": x.value}
+
+    def checks(self):
+        """The device-check word of the checked build since the last read (gd_plan_checks);
+        raises GDError (GD_EUNSUPPORTED) on the regular build."""
+        f = ctypes.c_uint(0)
+        _check(lib().gd_plan_checks(self.h, ctypes.byref(f)))
+        return f.value
 
     def set_lanes(self, lanes=0):
         """Lanes of gd_rk_step, gd_rk_advance and gd_collision_rhs (0 = by size): cell

@@ -52,3 +52,17 @@ def test_tensor_info_counts():
     assert inf["flops_per_eval"] == 2.0 * inf["nnz_folded"]
     t2 = G.Tensor(6, 2, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=(0.5,), conservative=False)
     assert t2.info()["n_out"] == 6 + 6 * 2
+
+
+def test_checked_build_exports_every_declared_symbol():
+    """The checked build (device checks on, -DGD_CHECKS) has the same C ABI; built here
+    when a checkout has none."""
+    import os
+    from paper_2607_13740_amd import build as B
+    if not os.path.exists(B.LIB_CHECKS):
+        B.build(checks=True)
+    L = ctypes.CDLL(B.LIB_CHECKS)
+    for n in G.declared_symbols():
+        assert hasattr(L, n), n
+    f = ctypes.c_uint(5)
+    assert L.gd_plan_checks(None, ctypes.byref(f)) == G.GD_EINVAL

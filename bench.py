@@ -468,10 +468,16 @@ def main():
             tune = {"waves": vv[0], "rows": vv[1], "xcd": vv[2], "tiles_per_wave": tp, "fixed": True}
         else:
             tune = plan.autotune(g, kscale=ks)
+        one_lane_ms = None
+        if args.lanes == 0 and plan.lanes()[0] > 1:
+            # the same step with every launch over all cells, for comparison (not the metric)
+            plan.set_lanes(1)
+            one_lane_ms = time_steps(plan, g, w, ks, max(4, args.steps // 2), 2)[0]
         plan.set_lanes(args.lanes)
         ms, kms, launches, sms, dist = time_steps(plan, g, w, ks, args.steps, args.warmup)
         res[prec] = {"ms_per_step": ms, "kernel_ms": kms, "launches": launches, "plan": plan, "stage_ms": sms,
-                     "variant": plan.variant(), "tune": tune, "step_ms_dist": dist, "lanes": plan.lanes()}
+                     "variant": plan.variant(), "tune": tune, "step_ms_dist": dist, "lanes": plan.lanes(),
+                     "one_lane_ms_per_step": one_lane_ms}
         print(f"# {prec}: {ms:.3f} ms/step, contraction {kms:.4f} ms/launch over {launches} launches, "
               f"stage kernel {sms:.4f} ms/launch, "
               f"variant {res[prec]['variant']}, lanes {res[prec]['lanes']}", file=sys.stderr, flush=True)
@@ -547,7 +553,8 @@ def main():
                    "precision": "split FP16 (hi+lo, 3 MFMA products) with FP32 MFMA accumulation, FP64 p-sum, "
                                 "FP64 state/limiter/RK",
                    "contraction_variant": mixed["variant"],
-                   "lanes": {"count": mixed["lanes"][0], "first_tiles": mixed["lanes"][1]},
+                   "lanes": {"count": mixed["lanes"][0], "first_tiles": mixed["lanes"][1],
+                             "one_lane_ms_per_step": mixed["one_lane_ms_per_step"]},
                    "step": "one captured HIP graph per RK step and lane; lanes (cell ranges of equal cost) "
                            "step side by side on streams of their own and join at the end of the call"},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
@@ -574,6 +581,7 @@ def main():
                            "step_ms_single_replays": f["step_ms_dist"],
                            "achieved_tflops": flops_launch / (f["kernel_ms"] * 1e-3) / 1e12,
                            "variant": f["variant"], "lanes": f["lanes"][0],
+                           "one_lane_ms_per_step": f["one_lane_ms_per_step"],
                            "peak_tflops": PEAK_F64_TFLOPS, "mass_drift": f["mass_drift"],
                            "per_cell_steps": f["adaptive"]}
         out["speedup_mixed_vs_fp64"] = cell_evals / f_evals

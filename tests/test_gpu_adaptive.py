@@ -595,3 +595,42 @@ def test_rk_advance_split_follows_fp64_over_substeps(oracle, name):
         assert int((dg > 2e-6).sum()) <= flat and dg.max() <= 1e-4, (i, np.sort(dg)[-4:], flat)
         assert np.array_equal(ta >= t_end, tb >= t_end)
     assert 0 < int((runs["fp64"][-1][1] >= t_end).sum()) < C
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_checkpoint_and_resume_in_a_new_plan(oracle, prec, tmp_path):
+    """Checkpoint / resume: the state of a run is the caller's coefficient array and
+    per-cell clocks.  One plan takes 3 + 3 per-cell sub-steps and 2 + 1 fixed steps (four
+    calls); the same calls with the arrays saved to .npy after the first and the third,
+    loaded into a new plan or onto new device buffers, and continued there: bit for bit
+    the same (no hidden plan state carries over between calls)."""
+    O = oracle
+    C = 40
+    t, cfg, g, ks, t_end = _case(O, "coupled_k2", C, seed=27)
+    ksd = torch.tensor(ks, device=DEV)
+    floor = 0.0 if prec == "fp64" else 1e-4
+    a = G.Plan(t, C, precision=prec)
+    ga = torch.tensor(g, device=DEV).view(-1)
+    ta = torch.zeros(C, dtype=torch.float64, device=DEV)
+    a.rk_advance(ga, ta, t_end, CFL, 1e30, 3, kscale=ksd, flux_floor=floor)
+    a.rk_advance(ga, ta, t_end, CFL, 1e30, 3, kscale=ksd, flux_floor=floor)
+    a.rk_step(ga, 1e-3, 2, kscale=ksd)
+    a.rk_step(ga, 1e-3, 1, kscale=ksd)
+    b = G.Plan(t, C, precision=prec)
+    gb = torch.tensor(g, device=DEV).view(-1)
+    tb = torch.zeros(C, dtype=torch.float64, device=DEV)
+    b.rk_advance(gb, tb, t_end, CFL, 1e30, 3, kscale=ksd, flux_floor=floor)
+    np.save(tmp_path / "g.npy", gb.cpu().numpy())
+    np.save(tmp_path / "t.npy", tb.cpu().numpy())
+    del b, gb, tb
+    c = G.Plan(t, C, precision=prec)
+    gc = torch.tensor(np.load(tmp_path / "g.npy"), device=DEV)
+    tc = torch.tensor(np.load(tmp_path / "t.npy"), device=DEV)
+    c.rk_advance(gc, tc, t_end, CFL, 1e30, 3, kscale=ksd, flux_floor=floor)
+    c.rk_step(gc, 1e-3, 2, kscale=ksd)
+    np.save(tmp_path / "g2.npy", gc.cpu().numpy())
+    gd = torch.tensor(np.load(tmp_path / "g2.npy"), device=DEV)
+    c.rk_step(gd, 1e-3, 1, kscale=ksd)
+    torch.cuda.synchronize()
+    assert torch.equal(ta, tc)
+    assert torch.equal(ga, gd)

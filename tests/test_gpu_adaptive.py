@@ -207,7 +207,7 @@ def test_rk_advance_uneven_batch_and_thresholds(oracle):
     assert tg[32] == t_end and np.array_equal(tg[:33] == t_end, to1 == t_end)
     assert np.max(np.abs(tg - to) / np.maximum(to, 1e-300)) <= 1e-6
 
-    # per-cell thresholds between tabulated levels (R13 blend), bracket-sorted slots
+    # per-cell thresholds between tabulated levels (the blend of two levels), bracket-sorted slots
     lv = W.VFRAG_LEVELS
     N, k, C = 12, 2, 70
     tt = G.Tensor(N, k, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=lv, conservative=True)

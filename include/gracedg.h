@@ -359,8 +359,11 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, const
  *   may be NULL.
  * gd_plan_autotune -- time every variant on state g (device, state layout, read
  *   only; kscale as in gd_rk_step) and keep the fastest (XCD-ordered items win ties
- *   within 2%: they move less HBM traffic).  cache_path (or NULL)
- *   names a text file of "key waves tiles_per_wave rows xcd" lines: a plan of the same shape (precision,
+ *   within 2%: they move less HBM traffic); on a plan of several groups, then the row
+ *   blocks per work item group by group (costliest first; a group keeps another
+ *   choice where the whole launch gets 1% faster).  cache_path (or NULL) names a text
+ *   file of "key waves tiles_per_wave rows xcd [g:rows_0,rows_1,...]" lines (-1: the
+ *   plan's rows): a plan of the same shape (precision,
  *   bins, order, levels, cells and brackets of every group) takes its stored
  *   choice without timing; a newly timed choice is appended.  Synchronous.
  * gd_plan_use_graph -- (default on) gd_rk_step captures one RK step (three
@@ -370,6 +373,9 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, const
  *   one.  Timing (gd_plan_timing) also issues them one by one.
  */
 int gd_plan_set_variant(gd_plan* plan, int waves, int tiles_per_wave, int rows, int xcd);
+/* gd_plan_group_rows -- the row blocks per work item of every group (rows[n_groups];
+ * the autotuner may set them group by group, gd_plan_set_variant resets them to rows). */
+int gd_plan_group_rows(const gd_plan* plan, int* rows);
 int gd_plan_variant(const gd_plan* plan, int* waves, int* tiles_per_wave, int* rows, int* xcd, int* n_items,
                     double* exec_flops);
 /*

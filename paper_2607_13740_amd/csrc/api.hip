@@ -3,6 +3,8 @@
 // the right-hand side and the SSP-RK3 step.
 #include <algorithm>
 #include <climits>
+#include <cstdlib>
+#include <string>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -564,6 +566,7 @@ struct gd_plan {
     int n_items = 0;
     size_t items_cap = 0;
     double exec_flops = 0.0;                // MFMA flops one contraction launch executes
+    std::vector<int> group_rows;            // per-group row blocks per item (autotuner; -1 or empty: rows)
     int lanes_req = 0;                      // requested lanes of the fixed step (0: by size)
     std::vector<Lane> lanes;                // more than one: gd_rk_step runs them side by side
     hipEvent_t fork = nullptr;
@@ -684,7 +687,9 @@ static int make_items(const gd_plan* pl, int which, int W, int rows, int xcd, st
         const Schedule& S = which == 1 ? G.t->adj : (mixed ? G.t->mixed : G.t->f64);
         const int NOB = S.NOB;
         if (NOB > 1023 || W > 2047) return fail(GD_EUNSUPPORTED, "too many row blocks for the work-item encoding");
-        const int nr = rows <= 0 ? NOB : std::min(NOB, rows);
+        // the forward contraction's rows per item may be tuned group by group
+        const int rg = (which == 0 && gi < pl->group_rows.size() && pl->group_rows[gi] >= 0) ? pl->group_rows[gi] : rows;
+        const int nr = rg <= 0 ? NOB : std::min(NOB, rg);
         // the lane's 32-slot tiles [lt0, lt1), in this group's tiles of ts slots
         const int la = std::max(0, lt0 - G.tile_off) * (32 / ts);
         const int lb = int(std::min<long long>((long long)lt1 - G.tile_off, G.tiles32)) * (32 / ts);
@@ -1034,7 +1039,16 @@ extern "C" int gd_plan_set_variant(gd_plan* pl, int waves, int tiles_per_wave, i
     pl->tpw = tiles_per_wave;
     pl->rows = rows;
     pl->xcd = xcd ? 1 : 0;
+    pl->group_rows.clear();
     return build_items(pl);
+}
+
+extern "C" int gd_plan_group_rows(const gd_plan* pl, int* rows)
+{
+    if (!pl || !rows) return fail(GD_EINVAL, "null argument");
+    for (size_t gi = 0; gi < pl->groups.size(); ++gi)
+        rows[gi] = (gi < pl->group_rows.size() && pl->group_rows[gi] >= 0) ? pl->group_rows[gi] : pl->rows;
+    return GD_OK;
 }
 
 extern "C" int gd_plan_variant(const gd_plan* pl, int* waves, int* tiles_per_wave, int* rows, int* xcd, int* n_items,
@@ -1752,19 +1766,34 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
         if (FILE* f = std::fopen(cache_path, "r")) {
             char line[4096];
             int bw = 0, bt = 1, br = -1, bx = 0;
+            std::vector<int> bg;
             while (std::fgets(line, sizeof line, f)) {
-                char k[4000];
+                char k[4000], gr[4000] = "";
                 int w, tt, r, x;
-                if (std::sscanf(line, "%3999s %d %d %d %d", k, &w, &tt, &r, &x) == 5 && key == k) {
+                const int n = std::sscanf(line, "%3999s %d %d %d %d %3999s", k, &w, &tt, &r, &x, gr);
+                if (n >= 5 && key == k) {
                     bw = w;
                     bt = tt;
                     br = r;
                     bx = x;
+                    bg.clear();
+                    // optional per-group rows "g:r0,r1,..."
+                    if (n == 6 && gr[0] == 'g' && gr[1] == ':')
+                        for (const char* c = gr + 2; *c;) {
+                            char* e = nullptr;
+                            bg.push_back(int(std::strtol(c, &e, 10)));
+                            if (e == c) break;
+                            c = (*e == ',') ? e + 1 : e;
+                        }
                 }
             }
             std::fclose(f);
             if ((bw == 4 || bw == 8) && br >= 0) {
                 if ((rc = gd_plan_set_variant(pl, bw, bt, br, bx))) return rc;
+                if (bg.size() == pl->groups.size()) {
+                    pl->group_rows = bg;
+                    if ((rc = build_items(pl))) return rc;
+                }
                 if (waves) *waves = bw;
                 if (tiles_per_wave) *tiles_per_wave = bt;
                 if (rows) *rows = br;
@@ -1795,19 +1824,23 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
     pl->timing = false;
     float best = 1e30f;
     int bw = 4, bt = 1, br = 1, bx = 1;
+    // one launch to warm up, then three timed (ms of the three, or a failure code)
+    auto time_launches = [&](float* ms) -> int {
+        int r;
+        if ((r = contract(pl, s, g))) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return fail(GD_EHIP, "event record");
+        for (int i = 0; i < 3; ++i)
+            if ((r = contract(pl, s, g))) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return fail(GD_EHIP, "event timing");
+        (void)hipEventElapsedTime(ms, e0, e1);
+        return GD_OK;
+    };
     rc = GD_OK;
     for (auto& c : cand) {
         if ((rc = gd_plan_set_variant(pl, c.w, c.t, c.r, c.x))) break;
-        if ((rc = contract(pl, s, g))) break;
-        if (hipEventRecord(e0, s) != hipSuccess) { rc = fail(GD_EHIP, "event record"); break; }
-        for (int i = 0; i < 3 && !rc; ++i) rc = contract(pl, s, g);
-        if (rc) break;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-            rc = fail(GD_EHIP, "event timing");
-            break;
-        }
         float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
+        if ((rc = time_launches(&ms))) break;
         // XCD ordering reads the fragments of fewer lists per L2 (about 40% less HBM
         // traffic at equal speed, which the other lane's stage kernels can use):
         // it wins ties within 2%
@@ -1820,14 +1853,52 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
             bx = c.x;
         }
     }
+    // then the row blocks per item group by group (costliest group first): a group
+    // keeps another choice only where the whole launch gets 1% faster
+    if (!rc && (rc = gd_plan_set_variant(pl, bw, bt, br, bx)) == GD_OK && pl->groups.size() > 1) {
+        float cur = 0.0f;
+        rc = time_launches(&cur);
+        std::vector<size_t> order;
+        for (size_t gi = 0; gi < pl->groups.size(); ++gi)
+            if (pl->groups[gi].C > 0) order.push_back(gi);
+        auto gcost = [&](size_t gi) {
+            const Group& G = pl->groups[gi];
+            const Schedule& S = pl->prec == GD_PREC_MIXED_F16X3 ? G.t->mixed : G.t->f64;
+            long long c = 0;
+            for (long long v : S.list_cost) c += v;
+            return double(c) * G.C;
+        };
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return gcost(a) > gcost(b); });
+        pl->group_rows.assign(pl->groups.size(), -1);
+        for (size_t gi : order) {
+            if (rc) break;
+            const int gnob = pl->prec == GD_PREC_MIXED_F16X3 ? pl->groups[gi].t->NOB : pl->groups[gi].t->NOB16;
+            int keep = -1;
+            for (int r : {1, 2, 0}) {
+                if (r == br || (r != 0 && r >= gnob)) continue;
+                pl->group_rows[gi] = r;
+                if ((rc = build_items(pl))) break;
+                float ms = 0.0f;
+                if ((rc = time_launches(&ms))) break;
+                if (ms < 0.99f * cur) {
+                    cur = ms;
+                    keep = r;
+                }
+            }
+            pl->group_rows[gi] = keep;
+        }
+        if (!rc) rc = build_items(pl);
+    }
     pl->timing = timing;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    if ((rc = gd_plan_set_variant(pl, bw, bt, br, bx))) return rc;
     if (cache_path)
         if (FILE* f = std::fopen(cache_path, "a")) {
-            std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), bw, bt, br, bx);
+            std::string gr;
+            for (size_t gi = 0; gi < pl->group_rows.size(); ++gi)
+                gr += (gi ? "," : "g:") + std::to_string(pl->group_rows[gi]);
+            std::fprintf(f, "%s %d %d %d %d%s%s\n", key.c_str(), bw, bt, br, bx, gr.empty() ? "" : " ", gr.c_str());
             std::fclose(f);
         }
     if (waves) *waves = bw;

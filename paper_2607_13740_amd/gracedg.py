@@ -90,6 +90,7 @@ def lib():
                                ctypes.POINTER(ctypes.c_longlong)], ctypes.c_int),
             "gd_plan_set_lanes": ([_VP, ctypes.c_int], ctypes.c_int),
             "gd_plan_checks": ([_VP, ctypes.POINTER(ctypes.c_uint)], ctypes.c_int),
+            "gd_plan_group_rows": ([_VP, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_plan_lanes": ([_VP, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
             "gd_collision_rhs_noalloc": ([_VP, ctypes.c_int, ctypes.c_int, _VP, _VP, _VP, _VP, _VP], ctypes.c_int),
             "gd_rk_step": ([_VP, _VP, _VP, ctypes.c_double, ctypes.c_int,
@@ -395,6 +396,12 @@ class Plan:
         """Contraction variant: waves per workgroup (4 or 8), tiles per wave (1 or 2), row
         blocks per item (0 = all), items grouped by XCD (1) or in one largest-first order (0)."""
         _check(lib().gd_plan_set_variant(self.h, int(waves), int(tiles_per_wave), int(rows), int(xcd)))
+
+    def group_rows(self):
+        """Row blocks per work item of every group (gd_plan_group_rows)."""
+        out = (ctypes.c_int * len(self.tensors))()
+        _check(lib().gd_plan_group_rows(self.h, out))
+        return list(out)
 
     def variant(self):
         w, t, r, x, n = (ctypes.c_int() for _ in range(5))

@@ -180,6 +180,38 @@ def test_autotune_keeps_results_and_uses_cache(oracle, tmp_path):
                                                                        choice["tiles_per_wave"])
 
 
+def test_autotune_per_group_rows_keep_results_and_cache(tmp_path):
+    """On an uneven batch the autotuner also picks the row blocks per item group by
+    group; every choice accumulates in the same order (results bit for bit those of
+    the default variant), the choice goes to the cache file, and a plan of the same
+    shape takes it back from there."""
+    w = W.WORKLOADS["c4_uneven"]
+    shapes = ((16, 1), (24, 3), (32, 2), (48, 3))
+    counts = [700, 500, 400, 300]
+    tensors = [G.Tensor(N, k, w.x_min, w.x_max, kernel=w.kernel, frag=w.frag, levels=w.levels,
+                        conservative=w.conservative) for N, k in shapes]
+    parts = []
+    for i, (t, n) in enumerate(zip(tensors, counts)):
+        smp = torch.tensor(W.samples(w, t.projection_points(), cells=n, params=W.lognormal_cells(n, 40 + i)),
+                           device=DEV)
+        parts.append(t.project(smp).reshape(-1))
+    g0 = torch.cat(parts)
+    for prec in ("mixed", "fp64"):
+        plan = G.Plan(tensors, counts, precision=prec)
+        ref = _raw(plan, g0)
+        cache = str(tmp_path / f"tune_{prec}.txt")
+        plan.autotune(g0, cache_path=cache)
+        rows = plan.group_rows()
+        assert len(rows) == 4 and all(r in (0, 1, 2) for r in rows), rows
+        assert torch.equal(_raw(plan, g0), ref)
+        line = open(cache).read().splitlines()[-1]
+        assert line.split()[-1].startswith("g:"), line
+        p2 = G.Plan(tensors, counts, precision=prec)
+        p2.autotune(g0, cache_path=cache)
+        assert p2.group_rows() == rows
+        assert torch.equal(_raw(p2, g0), ref)
+
+
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
 def test_full_size_uneven_workload_sampled(oracle, prec):
     """The uneven batch at full size (100000 cells over the twelve shapes) in the

@@ -231,6 +231,8 @@ int gd_collision_rhs_noalloc(const gd_tensor* t, int precision, int n_cells, con
  *                average by the limiter (such a bin is flattened, its mass kept),
  *                or with a non-finite coefficient; a nonzero count makes the call
  *                return GD_EPOSITIVITY (after completing every step).
+ * Asynchronous otherwise, on the plan's stream; a plan with lanes (gd_plan_set_lanes)
+ * steps them on their own streams and joins them to the plan's stream first.
  */
 int gd_rk_step(gd_plan* plan, double* g, const double* kscale, double dt, int n_steps, long long* violations);
 

@@ -361,7 +361,8 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, const
  *   may be NULL.
  * gd_plan_autotune -- time every variant on state g (device, state layout, read
  *   only; kscale as in gd_rk_step) and keep the fastest (XCD-ordered items win ties
- *   within 2%: they move less HBM traffic); on a plan of several groups, then the row
+ *   within 5%: they move less than half the HBM traffic, which lanes share with the
+ *   other lane's stage kernels).  On a plan of several groups, then the row
  *   blocks per work item group by group (costliest first; a group keeps another
  *   choice where the whole launch gets 1% faster).  cache_path (or NULL) names a text
  *   file of "key waves tiles_per_wave rows xcd [g:rows_0,rows_1,...]" lines (-1: the

@@ -1199,7 +1199,9 @@ static int contract(gd_plan* pl, hipStream_t s, const double* gs, const Lane* la
 
 extern "C" int gd_collision_rhs(gd_plan* pl, const double* g, const double* kscale, double* rhs, double* raw)
 {
-    if (!pl || !g || !rhs) return fail(GD_EINVAL, "null argument");
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    if (pl->n_values == 0) return GD_OK;   // no cell: nothing to evaluate (null arrays allowed)
+    if (!g || !rhs) return fail(GD_EINVAL, "null argument");
     const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
     hipStream_t s = pl->stream;
     int rc;
@@ -1318,8 +1320,13 @@ static int read_violations(gd_plan* pl, long long* violations)
 extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double dt, int n_steps,
                           long long* violations)
 {
-    if (!pl || !g || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!pl || n_steps < 0) return fail(GD_EINVAL, "bad argument");
     if (!std::isfinite(dt)) return fail(GD_EINVAL, "dt must be finite");
+    if (pl->n_values == 0) {   // no cell: nothing to step (null arrays allowed)
+        if (violations) *violations = 0;
+        return GD_OK;
+    }
+    if (!g) return fail(GD_EINVAL, "bad argument");
     int rc;
     hipStream_t s = pl->stream;
     if ((rc = launch_fill_u64(pl->viol, 1, s))) return rc;
@@ -1430,11 +1437,17 @@ extern "C" int gd_rk_advance(gd_plan* pl, double* g, const double* kscale, doubl
                              double dt_max, double flux_floor, int n_substeps, long long* violations,
                              long long* unfinished)
 {
-    if (!pl || !g || !t || n_substeps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!pl || n_substeps < 0) return fail(GD_EINVAL, "bad argument");
     if (!std::isfinite(t_end)) return fail(GD_EINVAL, "t_end must be finite");
     if (!(cfl > 0.0) || !std::isfinite(cfl)) return fail(GD_EINVAL, "cfl must be positive and finite");
     if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return fail(GD_EINVAL, "dt_max must be positive and finite");
     if (!(flux_floor >= 0.0) || !std::isfinite(flux_floor)) return fail(GD_EINVAL, "flux_floor must be >= 0 and finite");
+    if (pl->n_values == 0) {   // no cell: nothing to advance (null arrays allowed)
+        if (violations) *violations = 0;
+        if (unfinished) *unfinished = 0;
+        return GD_OK;
+    }
+    if (!g || !t) return fail(GD_EINVAL, "bad argument");
     int rc;
     hipStream_t s = pl->stream;
     if (!pl->dtc) {

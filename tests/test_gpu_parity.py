@@ -478,3 +478,41 @@ def test_split_step_matches_oracle(oracle, prec):
     m0 = (g * h)[:, ::cfg.k + 1].sum()
     m1 = (gg * h)[:, ::cfg.k + 1].sum()
     assert abs(m1 - m0) / m0 <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_smallest_shapes_and_empty_plans(oracle, prec):
+    """Degenerate sizes: two bins (one interior edge) at orders 0, 1 and 4, conservative
+    and not, one cell and a ragged 33 cells, against the oracle (raw vector and two RK
+    steps); a plan whose groups hold no cell evaluates and steps nothing without error."""
+    O = oracle
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    for k in (0, 1, 4):
+        for cons in (True, False):
+            t = G.Tensor(2, k, 1e-2, 1e2, kernel="const", frag="none", conservative=cons)
+            cfg = O.Config(N=2, k=k, xmin=1e-2, xmax=1e2, kernel="const", conservative=cons)
+            for C in (1, 33):
+                g = np.stack([O.project(cfg, lambda x, s=s: x * np.exp(-x * s)) for s in np.linspace(0.5, 2.0, C)])
+                Yo, _, _ = O.rhs(cfg, g)
+                plan = G.Plan(t, C, precision=prec)
+                gd = torch.tensor(g, device=DEV).view(-1)
+                raw = torch.zeros(plan.n_raw, dtype=torch.float64, device=DEV)
+                plan.collision_rhs(gd, raw=raw)
+                Yg = raw.cpu().numpy().reshape(C, -1)
+                scale = np.maximum(np.abs(Yo).max(axis=1), 1e-300)
+                assert np.all(np.abs(Yg - Yo).max(axis=1) <= tol * scale), (k, cons, C)
+                go, vo = O.rk(cfg, g, 1e-2, 2)
+                v = plan.rk_step(gd, 1e-2, 2, count_violations=True)
+                h = np.repeat(np.diff(O.edges(cfg)), k + 1)
+                gg = gd.cpu().numpy().reshape(C, -1)
+                err = np.abs((gg - go) * h).max(axis=1) / np.abs(go * h).max(axis=1)
+                assert err.max() <= tol * 10 and v == vo, (k, cons, C, err.max(), v, vo)
+    t = G.Tensor(8, 2, 1e-4, 1e8, kernel="ballistic", frag="powerlaw", levels=(0.5,), conservative=True)
+    empty = G.Plan([t, t], [0, 0], precision=prec)
+    assert empty.n_cells == 0 and empty.n_values == 0
+    g0 = torch.zeros(0, dtype=torch.float64, device=DEV)
+    assert empty.collision_rhs(g0).numel() == 0
+    assert empty.rk_step(g0, 1e-3, 2, count_violations=True) == 0
+    t0 = torch.zeros(0, dtype=torch.float64, device=DEV)
+    assert empty.rk_advance(g0, t0, 1.0, 0.1, 1e-3, 2, count=True) == (0, 0)
+    torch.cuda.synchronize()

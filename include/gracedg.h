@@ -362,7 +362,8 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, const
  *   (every stored fragment, all products, for every tile of an item); any pointer
  *   may be NULL.
  * gd_plan_autotune -- time every variant on state g (device, state layout, read
- *   only; kscale as in gd_rk_step) and keep the fastest (XCD-ordered items win ties
+ *   only; kscale as in gd_rk_step; the fastest of five samples of three contraction
+ *   launches per variant) and keep the fastest (XCD-ordered items win ties
  *   within 5%: they move less than half the HBM traffic, which lanes share with the
  *   other lane's stage kernels).  On a plan of several groups, then the row
  *   blocks per work item group by group (costliest first; a group keeps another

@@ -2,6 +2,7 @@
 // (groups of hydro cells, workspaces, threshold brackets) and the calls that run
 // the right-hand side and the SSP-RK3 step.
 #include <algorithm>
+#include <limits>
 #include <climits>
 #include <cstdlib>
 #include <string>
@@ -1859,15 +1860,22 @@ extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* ksca
     float best = 1e30f;
     int bw = 4, bt = 1, br = 1, bx = 1;
     // one launch to warm up, then three timed (ms of the three, or a failure code)
+    // fastest of five samples of three launches each (after one warm-up launch): a
+    // sample disturbed by clock changes or other work on the device does not decide
     auto time_launches = [&](float* ms) -> int {
         int r;
         if ((r = contract(pl, s, g))) return r;
-        if (hipEventRecord(e0, s) != hipSuccess) return fail(GD_EHIP, "event record");
-        for (int i = 0; i < 3; ++i)
-            if ((r = contract(pl, s, g))) return r;
-        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
-            return fail(GD_EHIP, "event timing");
-        (void)hipEventElapsedTime(ms, e0, e1);
+        *ms = std::numeric_limits<float>::max();
+        for (int rep = 0; rep < 5; ++rep) {
+            if (hipEventRecord(e0, s) != hipSuccess) return fail(GD_EHIP, "event record");
+            for (int i = 0; i < 3; ++i)
+                if ((r = contract(pl, s, g))) return r;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return fail(GD_EHIP, "event timing");
+            float t = 0.0f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            *ms = std::min(*ms, t);
+        }
         return GD_OK;
     };
     rc = GD_OK;

@@ -1198,6 +1198,36 @@ static int contract(gd_plan* pl, hipStream_t s, const double* gs, const Lane* la
     return GD_OK;
 }
 
+// Lanes are forked from the plan's stream s and joined back to it.  Once forked, a
+// call joins its lanes on every path, also after a failed launch, so that no lane
+// work is left running behind the caller's back; the first error is returned.
+static int fork_lanes(gd_plan* pl, hipStream_t s)
+{
+    HIP_TRY(hipEventRecord(pl->fork, s));
+    for (size_t l = 1; l < pl->lanes.size(); ++l) HIP_TRY(hipStreamWaitEvent(pl->lanes[l].stream, pl->fork, 0));
+    return GD_OK;
+}
+
+static int join_lanes(gd_plan* pl, hipStream_t s, int rc)
+{
+    for (size_t l = 1; l < pl->lanes.size(); ++l) {
+        hipError_t e = hipEventRecord(pl->lanes[l].done, pl->lanes[l].stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(s, pl->lanes[l].done, 0);
+        if (e != hipSuccess) {
+            // the plan's stream cannot be ordered after this lane: wait for it here
+            (void)hipStreamSynchronize(pl->lanes[l].stream);
+            if (!rc) rc = fail(GD_EHIP, std::string("joining a lane: ") + hipGetErrorString(e));
+        }
+    }
+    return rc;
+}
+
+static inline int launch_graph(const hipGraphExec_t exec, hipStream_t s)
+{
+    HIP_TRY(hipGraphLaunch(exec, s));
+    return GD_OK;
+}
+
 extern "C" int gd_collision_rhs(gd_plan* pl, const double* g, const double* kscale, double* rhs, double* raw)
 {
     if (!pl) return fail(GD_EINVAL, "null plan");
@@ -1216,15 +1246,9 @@ extern "C" int gd_collision_rhs(gd_plan* pl, const double* g, const double* ksca
         return stage(pl, ls, 0, 0, 0, kscale, nullptr, g, rhs, 0.0, raw, nullptr, nullptr, L);
     };
     if (pl->lanes.size() <= 1 || pl->timing) return launches(s, nullptr);
-    HIP_TRY(hipEventRecord(pl->fork, s));
-    for (size_t l = 1; l < pl->lanes.size(); ++l) HIP_TRY(hipStreamWaitEvent(pl->lanes[l].stream, pl->fork, 0));
-    for (size_t l = 0; l < pl->lanes.size(); ++l)
-        if ((rc = launches(l == 0 ? s : pl->lanes[l].stream, &pl->lanes[l]))) return rc;
-    for (size_t l = 1; l < pl->lanes.size(); ++l) {
-        HIP_TRY(hipEventRecord(pl->lanes[l].done, pl->lanes[l].stream));
-        HIP_TRY(hipStreamWaitEvent(s, pl->lanes[l].done, 0));
-    }
-    return GD_OK;
+    if ((rc = fork_lanes(pl, s))) return rc;
+    for (size_t l = 0; l < pl->lanes.size() && !rc; ++l) rc = launches(l == 0 ? s : pl->lanes[l].stream, &pl->lanes[l]);
+    return join_lanes(pl, s, rc);
 }
 
 // y1 = gn + dt L(gn); y2 = 3/4 gn + 1/4 (y1 + dt L(y1)); gn = 1/3 gn + 2/3 (y2 + dt L(y2)),
@@ -1285,20 +1309,14 @@ static int rk_steps(gd_plan* pl, double* g, const double* kscale, double dt, int
         if (graph)
             for (Lane& L : pl->lanes)
                 if (!current(L.graph) && (rc = capture_step(pl, g, kscale, dt, &L))) return rc;
-        HIP_TRY(hipEventRecord(pl->fork, s));
-        for (size_t l = 1; l < pl->lanes.size(); ++l) HIP_TRY(hipStreamWaitEvent(pl->lanes[l].stream, pl->fork, 0));
-        for (int n = 0; n < n_steps; ++n)
-            for (size_t l = 0; l < pl->lanes.size(); ++l) {
+        if ((rc = fork_lanes(pl, s))) return rc;
+        for (int n = 0; n < n_steps && !rc; ++n)
+            for (size_t l = 0; l < pl->lanes.size() && !rc; ++l) {
                 Lane& L = pl->lanes[l];
                 hipStream_t ls = l == 0 ? s : L.stream;
-                if (graph) HIP_TRY(hipGraphLaunch(L.graph.exec, ls));
-                else if ((rc = step_launches(pl, ls, g, kscale, dt, &L))) return rc;
+                rc = graph ? launch_graph(L.graph.exec, ls) : step_launches(pl, ls, g, kscale, dt, &L);
             }
-        for (size_t l = 1; l < pl->lanes.size(); ++l) {
-            HIP_TRY(hipEventRecord(pl->lanes[l].done, pl->lanes[l].stream));
-            HIP_TRY(hipStreamWaitEvent(s, pl->lanes[l].done, 0));
-        }
-        return GD_OK;
+        return join_lanes(pl, s, rc);
     }
     if (graph && !current(pl->graph) && (rc = capture_step(pl, g, kscale, dt))) return rc;
     for (int n = 0; n < n_steps; ++n) {
@@ -1469,19 +1487,14 @@ extern "C" int gd_rk_advance(gd_plan* pl, double* g, const double* kscale, doubl
         if (graph)
             for (Lane& L : pl->lanes)
                 if (!current(L.sgraph) && (rc = capture_substep(pl, g, kscale, dt_max, ad, &L))) return rc;
-        HIP_TRY(hipEventRecord(pl->fork, s));
-        for (size_t l = 1; l < pl->lanes.size(); ++l) HIP_TRY(hipStreamWaitEvent(pl->lanes[l].stream, pl->fork, 0));
-        for (int n = 0; n < n_substeps; ++n)
-            for (size_t l = 0; l < pl->lanes.size(); ++l) {
+        if ((rc = fork_lanes(pl, s))) return rc;
+        for (int n = 0; n < n_substeps && !rc; ++n)
+            for (size_t l = 0; l < pl->lanes.size() && !rc; ++l) {
                 Lane& L = pl->lanes[l];
                 hipStream_t ls = l == 0 ? s : L.stream;
-                if (graph) HIP_TRY(hipGraphLaunch(L.sgraph.exec, ls));
-                else if ((rc = substep_launches(pl, ls, g, kscale, dt_max, ad, &L))) return rc;
+                rc = graph ? launch_graph(L.sgraph.exec, ls) : substep_launches(pl, ls, g, kscale, dt_max, ad, &L);
             }
-        for (size_t l = 1; l < pl->lanes.size(); ++l) {
-            HIP_TRY(hipEventRecord(pl->lanes[l].done, pl->lanes[l].stream));
-            HIP_TRY(hipStreamWaitEvent(s, pl->lanes[l].done, 0));
-        }
+        if ((rc = join_lanes(pl, s, rc))) return rc;
     } else {
         if (graph && !current(pl->sgraph) && (rc = capture_substep(pl, g, kscale, dt_max, ad))) return rc;
         for (int n = 0; n < n_substeps; ++n) {

@@ -20,6 +20,11 @@
  *    doubles, coefficient index p = j*(order+1) + i for bin j and Legendre
  *    degree i (Eq. 2.3).  Cells of a plan are ordered group by group.
  *  - Calls on a plan are asynchronous on the plan's HIP stream unless stated.
+ *  - A plan holds workspaces, work lists and captured graphs: calls on one plan
+ *    must not overlap from several host threads.  Distinct plans share no device
+ *    memory and may run on different streams at once.  A tensor is read only once
+ *    its device layouts exist; gd_tensor_upload and gd_plan_create, which build
+ *    them on first use, must not run concurrently on the same tensor.
  *  - Invalid arguments return GD_EINVAL before any launch; HIP failures return
  *    GD_EHIP with the HIP error string in gd_last_error().
  */

@@ -21,7 +21,7 @@
  *    degree i (Eq. 2.3).  Cells of a plan are ordered group by group.
  *  - Calls on a plan are asynchronous on the plan's HIP stream unless stated.
  *  - A plan holds workspaces, work lists and captured graphs: calls on one plan
- *    must not overlap from several host threads.  Distinct plans share no device
+ *    must not overlap from several host threads.  Distinct plans share no writable device
  *    memory and may run on different streams at once.  A tensor is read only once
  *    its device layouts exist; gd_tensor_upload and gd_plan_create, which build
  *    them on first use, must not run concurrently on the same tensor.

@@ -23,8 +23,10 @@
  *  - A plan holds workspaces, work lists and captured graphs: calls on one plan
  *    must not overlap from several host threads.  Distinct plans share no writable device
  *    memory and may run on different streams at once.  A tensor is read only once
- *    its device layouts exist; gd_tensor_upload and gd_plan_create, which build
- *    them on first use, must not run concurrently on the same tensor.
+ *    its device layouts exist; the calls that build them on first use
+ *    (gd_tensor_upload and gd_plan_create: the forward layouts; a plan's first
+ *    gd_adjoint or gd_collision_vjp: the transposed layout) must not run
+ *    concurrently on the same tensor.
  *  - Invalid arguments return GD_EINVAL before any launch; HIP failures return
  *    GD_EHIP with the HIP error string in gd_last_error().
  */

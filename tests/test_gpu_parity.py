@@ -342,6 +342,24 @@ def test_full_size_batched_workload_sampled(oracle, prec):
     h = torch.tensor(np.diff(t.edges()), device=DEV)
     L0 = L.view(w.cells, w.bins, w.order + 1)[:, :, 0] * h
     assert float((L0.sum(1).abs() / L0.abs().sum(1)).max()) <= 1e-13
+    # the contraction variant the benchmark's autotuner picks on this workload (8 waves,
+    # one tile per wave, XCD-ordered items) gives the same raw vector bit for bit
+    plan.set_variant(waves=8, tiles_per_wave=1, rows=1, xcd=1)
+    raw8 = torch.zeros_like(raw)
+    plan.collision_rhs(g0, kscale=ks, raw=raw8)
+    torch.cuda.synchronize()
+    assert torch.equal(raw8, raw)
+    # one SSP-RK3 step of the workload's dt in that configuration (the plan's default
+    # lanes at this size), sampled cells against the oracle's step
+    assert plan.lanes()[0] >= 2
+    g = g0.clone()
+    plan.rk_step(g, w.dt, 1, kscale=ks)
+    torch.cuda.synchronize()
+    go, _ = O.rk(cfg, gs, w.dt, 1, kscale=p["kscale"][idx], vfrag=p["vfrag"][idx])
+    gg = g.view(w.cells, -1)[idx].cpu().numpy()
+    hP = np.repeat(np.diff(t.edges()), w.order + 1)
+    err = np.max(np.abs((gg - go) * hP), axis=1) / np.max(np.abs(go * hP), axis=1)
+    assert err.max() <= (1e-11 if prec == "fp64" else 1e-6), err.max()
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])

@@ -377,8 +377,9 @@ int gd_collision_vjp(gd_plan* plan, const double* g, const double* kscale, const
  *   choice where the whole launch gets 1% faster).  cache_path (or NULL) names a text
  *   file of "key waves tiles_per_wave rows xcd [g:rows_0,rows_1,...]" lines (-1: the
  *   plan's rows): a plan of the same shape (precision,
- *   bins, order, levels, cells and brackets of every group) takes its stored
- *   choice without timing; a newly timed choice is appended.  Synchronous.
+ *   bins, order, levels, cells, brackets and stored fragments of every group) on
+ *   the same device (architecture and compute units) takes its stored choice
+ *   without timing; a newly timed choice is appended.  Synchronous.
  * gd_plan_use_graph -- (default on) gd_rk_step captures one RK step (three
  *   contractions and three stage kernels) into a HIP graph on a private stream and
  *   replays it once per step on the plan's stream.  The graph is captured again

@@ -1779,13 +1779,26 @@ extern "C" int gd_collision_vjp(gd_plan* pl, const double* g, const double* ksca
 // Times every contraction variant (4 or 8 waves per workgroup; 1, 2 or all row
 // blocks per work item) on the given state and keeps the fastest.  With a cache
 // file, a plan of the same shape reuses the stored choice without timing.
+// precision; per group bins x order, levels, cells, brackets and stored fragments (the
+// tensor's sparsity: kernels and fragment laws of one shape differ there); the device
+// (architecture and compute units).  No spaces: the cache line is space-separated.
 static std::string tune_key(const gd_plan* pl)
 {
-    std::string k = pl->prec == GD_PREC_MIXED_F16X3 ? "mixed" : "fp64";
+    const bool mixed = pl->prec == GD_PREC_MIXED_F16X3;
+    std::string k = mixed ? "mixed" : "fp64";
     for (const Group& G : pl->groups) {
         const gd_tensor* t = G.t;
         k += ";" + std::to_string(t->N) + "x" + std::to_string(t->k) + "r" + std::to_string(t->R) + "c" +
-             std::to_string(G.C) + "b" + std::to_string(G.brackets.size());
+             std::to_string(G.C) + "b" + std::to_string(G.brackets.size()) + "f" +
+             std::to_string(mixed ? t->mixed.frags : t->f64.frags);
+    }
+    int dev = 0;
+    hipDeviceProp_t prop{};
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::string arch = prop.gcnArchName;
+        for (char& c : arch)
+            if (c == ' ') c = '_';
+        k += "@" + arch + "/" + std::to_string(prop.multiProcessorCount);
     }
     return k;
 }

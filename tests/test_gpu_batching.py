@@ -178,6 +178,17 @@ def test_autotune_keeps_results_and_uses_cache(oracle, tmp_path):
     v = p2.variant()
     assert (v["waves"], v["rows"], v["xcd"], v["tiles_per_wave"]) == (choice["waves"], choice["rows"], choice["xcd"],
                                                                        choice["tiles_per_wave"])
+    # a tensor of the same shape without fragmentation stores other fragments (the
+    # contraction's cost follows the stored blocks, not their values): its plan does
+    # not take the stored line, it is timed and appended; every key names the device
+    t_nf = G.Tensor(12, 3, 1e-4, 1e8, kernel="const", frag="none", levels=W.VFRAG_LEVELS, conservative=True)
+    p3 = G.Plan(t_nf, C, precision="mixed", vfrag=vf)
+    assert p3.schedule_stats()["frags_mixed"] != plan.schedule_stats()["frags_mixed"]
+    p3.autotune(gd, kscale=ksd, cache_path=cache)
+    lines3 = open(cache).read().splitlines()
+    assert len(lines3) == 2 and lines3[0] == lines[0], lines3
+    assert lines3[1].split()[0] != lines[0].split()[0]
+    assert all("@gfx" in ln.split()[0] for ln in lines3), lines3
 
 
 def test_autotune_per_group_rows_keep_results_and_cache(tmp_path):

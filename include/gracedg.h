@@ -202,8 +202,10 @@ void gd_plan_destroy(gd_plan* plan);
  *  raw     : device [n_cells][n_out of the cell's group] FP64 raw flux vector Y, or NULL.
  */
 int gd_collision_rhs(gd_plan* plan, const double* g, const double* kscale, double* rhs, double* raw);
-/* A plan whose groups hold no cell evaluates, steps and advances nothing: gd_collision_rhs,
- * gd_rk_step and gd_rk_advance return GD_OK (zero counts) and accept NULL arrays then. */
+/* A plan whose groups hold no cell computes nothing: gd_collision_rhs, gd_rk_step,
+ * gd_rk_advance, gd_rk_forward, gd_adjoint, gd_collision_vjp, gd_advect, gd_split_step
+ * and gd_plan_autotune (which reports the plan's variant) return GD_OK, with zero
+ * counts, after their scalar argument checks, and accept NULL arrays then. */
 
 /*
  * gd_collision_rhs_noalloc -- gd_collision_rhs for callers that cannot allocate

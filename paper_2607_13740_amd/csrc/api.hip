@@ -1354,9 +1354,14 @@ extern "C" int gd_rk_step(gd_plan* pl, double* g, const double* kscale, double d
 }
 
 // Courant numbers vel_j * dt / dx of every bin (host values checked, then copied)
+static bool transport_scalars_ok(double dt, double dx)
+{
+    return dx > 0.0 && std::isfinite(dx) && std::isfinite(dt) && dt >= 0.0;
+}
+
 static int set_courant(gd_plan* pl, const double* vel, double dt, double dx)
 {
-    if (!vel || !(dx > 0.0) || !std::isfinite(dx) || !std::isfinite(dt) || dt < 0.0)
+    if (!vel || !transport_scalars_ok(dt, dx))
         return fail(GD_EINVAL, "transport needs velocities, dx > 0 and a finite dt >= 0");
     const int nb = pl->bin_off.empty() ? 0 : pl->bin_off.back() + pl->groups.back().t->N;
     std::vector<double> c(nb);
@@ -1387,7 +1392,10 @@ static int advect_launches(gd_plan* pl, double* g, int periodic)
 
 extern "C" int gd_advect(gd_plan* pl, double* g, const double* vel, double dt, double dx, int periodic)
 {
-    if (!pl || !g) return fail(GD_EINVAL, "null argument");
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    if (!transport_scalars_ok(dt, dx)) return fail(GD_EINVAL, "transport needs dx > 0 and a finite dt >= 0");
+    if (pl->n_values == 0) return GD_OK;   // no cell: nothing to transport (null arrays allowed)
+    if (!g) return fail(GD_EINVAL, "null argument");
     int rc = set_courant(pl, vel, dt, dx);
     if (rc) return rc;
     return advect_launches(pl, g, periodic ? 1 : 0);
@@ -1396,8 +1404,14 @@ extern "C" int gd_advect(gd_plan* pl, double* g, const double* vel, double dt, d
 extern "C" int gd_split_step(gd_plan* pl, double* g, const double* kscale, const double* vel, double dx,
                              int periodic, double dt, int n_steps, long long* violations)
 {
-    if (!pl || !g || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!pl || n_steps < 0) return fail(GD_EINVAL, "bad argument");
     if (!std::isfinite(dt)) return fail(GD_EINVAL, "dt must be finite");
+    if (!transport_scalars_ok(0.5 * dt, dx)) return fail(GD_EINVAL, "transport needs dx > 0 and a finite dt >= 0");
+    if (pl->n_values == 0) {   // no cell: nothing to step (null arrays allowed)
+        if (violations) *violations = 0;
+        return GD_OK;
+    }
+    if (!g) return fail(GD_EINVAL, "null argument");
     int rc = set_courant(pl, vel, 0.5 * dt, dx);
     if (rc) return rc;
     if ((rc = launch_fill_u64(pl->viol, 1, pl->stream))) return rc;
@@ -1616,8 +1630,13 @@ extern "C" int gd_plan_set_vfrag(gd_plan* pl, const double* vfrag)
 extern "C" int gd_rk_forward(gd_plan* pl, double* g, const double* kscale, double dt, int n_steps, double* states,
                              double* gammas, long long* violations)
 {
-    if (!pl || !g || !states || !gammas || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!pl || n_steps < 0) return fail(GD_EINVAL, "bad argument");
     if (!std::isfinite(dt)) return fail(GD_EINVAL, "dt must be finite");
+    if (pl->n_values == 0) {   // no cell: nothing to step or record (null arrays allowed)
+        if (violations) *violations = 0;
+        return GD_OK;
+    }
+    if (!g || !states || !gammas) return fail(GD_EINVAL, "bad argument");
     int rc;
     hipStream_t s = pl->stream;
     const int split = pl->prec == GD_PREC_MIXED_F16X3 ? 1 : 0;
@@ -1708,7 +1727,9 @@ static int adj_contract(gd_plan* pl, hipStream_t s, const double* y)
 extern "C" int gd_adjoint(gd_plan* pl, const double* states, const double* gammas, const double* kscale, double dt,
                           int n_steps, double* lam, double* dkscale, double* dvfrag)
 {
-    if (!pl || !states || !gammas || !lam || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (!pl || n_steps < 0) return fail(GD_EINVAL, "bad argument");
+    if (pl->n_values == 0) return GD_OK;   // no cell: no cotangent (null arrays allowed)
+    if (!states || !gammas || !lam) return fail(GD_EINVAL, "bad argument");
     int rc;
     if ((rc = prepare_adjoint(pl))) return rc;
     hipStream_t s = pl->stream;
@@ -1758,7 +1779,9 @@ extern "C" int gd_adjoint(gd_plan* pl, const double* states, const double* gamma
 extern "C" int gd_collision_vjp(gd_plan* pl, const double* g, const double* kscale, const double* mu, double* grad,
                                 double* dkscale, double* dvfrag)
 {
-    if (!pl || !g || !mu || !grad) return fail(GD_EINVAL, "null argument");
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    if (pl->n_values == 0) return GD_OK;   // no cell: nothing to differentiate (null arrays allowed)
+    if (!g || !mu || !grad) return fail(GD_EINVAL, "null argument");
     int rc;
     if ((rc = prepare_adjoint(pl))) return rc;
     if (dkscale && (rc = launch_fill_f64(dkscale, pl->n_cells, 0.0, pl->stream))) return rc;
@@ -1820,7 +1843,11 @@ extern "C" int gd_plan_algorithmic_flops(const gd_plan* pl, double* flops)
 extern "C" int gd_plan_autotune(gd_plan* pl, const double* g, const double* kscale, const char* cache_path,
                                 int* waves, int* tiles_per_wave, int* rows, int* xcd)
 {
-    if (!pl || !g) return fail(GD_EINVAL, "null argument");
+    if (!pl) return fail(GD_EINVAL, "null plan");
+    if (pl->n_values == 0) {   // no cell: nothing to time; the plan keeps its variant
+        return gd_plan_variant(pl, waves, tiles_per_wave, rows, xcd, nullptr, nullptr);
+    }
+    if (!g) return fail(GD_EINVAL, "null argument");
     const std::string key = tune_key(pl);
     int rc;
     if (cache_path) {

@@ -533,4 +533,18 @@ def test_smallest_shapes_and_empty_plans(oracle, prec):
     assert empty.rk_step(g0, 1e-3, 2, count_violations=True) == 0
     t0 = torch.zeros(0, dtype=torch.float64, device=DEV)
     assert empty.rk_advance(g0, t0, 1.0, 0.1, 1e-3, 2, count=True) == (0, 0)
+    st, gm, v = empty.rk_forward(g0, 1e-3, 2, count_violations=True)
+    assert st.numel() == 0 and gm.numel() == 0 and v == 0
+    dks, dvf = empty.adjoint(st, gm, 1e-3, 2, g0)
+    assert dks.numel() == 0 and dvf.numel() == 0
+    grad, dks, dvf = empty.collision_vjp(g0, g0)
+    assert grad.numel() == 0
+    vel = [1.0] * (2 * t.bins)
+    empty.advect(g0, vel, 1e-3, 1.0)
+    assert empty.split_step(g0, vel, 1.0, 1e-3, 2, count_violations=True) == 0
+    choice = empty.autotune(g0)
+    var = empty.variant()
+    assert choice == {key: var[key] for key in choice}
+    with pytest.raises(G.GDError):
+        empty.advect(g0, vel, 1e-3, 0.0)         # dx > 0 is still required
     torch.cuda.synchronize()
